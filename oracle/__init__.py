@@ -1,0 +1,241 @@
+"""FP64 CPU oracle for the disk-blended light field renderer (numpy wrapper).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only users. The product path never imports it.
+It shares no code with the HIP library (see ``oracle.c`` for the readings of
+the paper it implements).
+
+Paper passages followed (all Sec. 3 of the paper):
+  * eye rays .............. Sec. 3.1, Eq. (1)
+  * disk-blended query .... Sec. 3.1, Eq. (2); linear kernel and disk placement
+  * point-splat reading ... Sec. 3.1, Eq. (3) (constant-colour special case)
+  * two-pass accumulate ... Sec. 3.2 (numerator / denominator, then divide)
+  * intra-image occlusion . Sec. 3.2.2 (nearest hit within one view's mesh)
+  * per-view mesh ......... Sec. 3.5 (depth map, two triangles per pixel)
+  * offline query L-bar ... Sec. 4.1 (denser / larger support reconstruction),
+    used here as the supersampled reference render.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "conv_oracle.c")]
+
+
+class _Views(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32), ("mesh_m", ctypes.c_int32),
+        ("src_fov_deg", ctypes.c_double),
+        ("centres", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("rgba8", ctypes.c_void_p),
+        ("zdepth", ctypes.c_void_p), ("zrange", ctypes.c_void_p),
+        ("disk_radius", ctypes.c_double),
+        ("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
+    ]
+
+
+class _Lists(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int32), ("cand", ctypes.c_void_p), ("cand_band", ctypes.c_void_p),
+                ("contrib", ctypes.c_void_p), ("contrib_band", ctypes.c_void_p), ("n_cand", ctypes.c_void_p)]
+
+
+REC_DTYPE = np.dtype([("a", "f8"), ("u", "f8"), ("v", "f8"), ("rho", "f8"), ("t_hit", "f8"),
+                      ("Xs", "f8"), ("Ys", "f8"), ("rgb", "f8", (3,)), ("cand", "i4"), ("hit", "i4")])
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain C, FP64, OpenMP)."""
+    srcs = [s for s in _SRCS if os.path.exists(s)]
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE", *srcs,
+           "-o", _SO + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(_SO)
+        vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_zrange.argtypes = [i32, i32, vp, vp]
+        L.orc_eye_rays.argtypes = [vp, vp, f64, i32, i32, i64, vp, vp, vp]
+        L.orc_disk.argtypes = [ctypes.POINTER(_Views), i32, vp, vp, vp, vp, vp, vp]
+        L.orc_mesh_hit.argtypes = [ctypes.POINTER(_Views), i32, vp, vp]
+        L.orc_mesh_hit.restype = f64
+        L.orc_sample.argtypes = [ctypes.POINTER(_Views), i32, f64, f64, vp]
+        L.orc_render_rays.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, vp, vp, vp, ctypes.POINTER(_Lists)]
+        L.orc_ray_records.argtypes = [ctypes.POINTER(_Views), vp, vp, vp]
+        L.orc_views_size.restype = i32
+        L.orc_rec_size.restype = i32
+        L.orc_max_threads.restype = i32
+        if L.orc_views_size() != ctypes.sizeof(_Views):
+            raise RuntimeError("orc_views layout mismatch")
+        if L.orc_rec_size() != REC_DTYPE.itemsize:
+            raise RuntimeError("orc_rec layout mismatch")
+        _conv_bind(L)
+        _lib = L
+    return _lib
+
+
+def _conv_bind(L):
+    if not hasattr(L, "orc_conv3x3_fwd"):
+        return
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    L.orc_conv3x3_fwd.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp, i32]
+    L.orc_conv3x3_bwd.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, i32]
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+class OracleViews:
+    """Light field as the oracle sees it: arrays kept alive for the C side."""
+
+    def __init__(self, centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, mode="traversal", threads=0):
+        self.centres = np.ascontiguousarray(centres, np.float64)
+        self.rot = np.ascontiguousarray(np.asarray(rot, np.float64).reshape(-1, 9))
+        self.rgba8 = np.ascontiguousarray(rgba8, np.uint8)
+        self.zdepth = np.ascontiguousarray(zdepth, np.float32)
+        n, h, w, _ = self.rgba8.shape
+        m = self.zdepth.shape[1]
+        assert self.centres.shape == (n, 3) and self.rot.shape == (n, 9) and self.zdepth.shape == (n, m, m)
+        self.zrange = np.zeros((n, 2), np.float64)
+        lib().orc_zrange(n, m, _p(self.zdepth), _p(self.zrange))
+        self.s = _Views(n, w, h, m, float(src_fov_deg), _p(self.centres), _p(self.rot), _p(self.rgba8),
+                        _p(self.zdepth), _p(self.zrange), float(disk_radius),
+                        1 if mode == "brute" else 0, int(threads))
+
+    @classmethod
+    def from_views(cls, v, mode="traversal", threads=0, disk_radius=None):
+        return cls(v.centres, v.rot, v.rgba8, v.zdepth, v.src_fov_deg,
+                   v.disk_radius if disk_radius is None else disk_radius, mode, threads)
+
+    @property
+    def n(self):
+        return self.s.n
+
+    def with_disk_radius(self, r):
+        o = OracleViews.__new__(OracleViews)
+        o.__dict__.update(self.__dict__)
+        o.s = _Views.from_buffer_copy(self.s)
+        o.s.disk_radius = float(r)
+        return o
+
+    def with_mode(self, mode):
+        o = self.with_disk_radius(self.s.disk_radius)
+        o.s.mode = 1 if mode == "brute" else 0
+        return o
+
+
+# --------------------------------------------------------------------------- rays
+
+def eye_rays(pos, rot, hfov_deg, W, H, pxy):
+    """Eq. (1): rays through continuous pixel positions pxy (n,2); centre of pixel (x,y) is (x+.5, y+.5)."""
+    pxy = np.ascontiguousarray(pxy, np.float64).reshape(-1, 2)
+    n = pxy.shape[0]
+    o = np.zeros((n, 3)); e = np.zeros((n, 3))
+    pos = np.ascontiguousarray(pos, np.float64); rot = np.ascontiguousarray(np.asarray(rot, np.float64).reshape(9))
+    lib().orc_eye_rays(_p(pos), _p(rot), float(hfov_deg), int(W), int(H), n, _p(pxy), _p(o), _p(e))
+    return o, e
+
+
+def pixel_centres(W, H, idx=None):
+    if idx is None:
+        idx = np.arange(W * H)
+    idx = np.asarray(idx, np.int64)
+    return np.stack([(idx % W) + 0.5, (idx // W) + 0.5], 1).astype(np.float64)
+
+
+def stereo_eyes(head_pos, head_rot, ipd):
+    """Two eyes offset by -/+ ipd/2 along the head's image +x axis, same orientation."""
+    head_pos = np.asarray(head_pos, np.float64)
+    R = np.asarray(head_rot, np.float64).reshape(3, 3)
+    r = R[:, 0]
+    return [(head_pos - 0.5 * ipd * r, R.copy()), (head_pos + 0.5 * ipd * r, R.copy())]
+
+
+def render_rays(ov: OracleViews, o, e, cap: int = 0):
+    o = np.ascontiguousarray(o, np.float64).reshape(-1, 3)
+    e = np.ascontiguousarray(e, np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    rgb = np.zeros((n, 3)); ws = np.zeros(n); cnt = np.zeros(n, np.int32)
+    out = {"rgb": rgb, "wsum": ws, "count": cnt}
+    Lp = None
+    if cap > 0:
+        for k in ("cand", "cand_band", "contrib", "contrib_band"):
+            out[k] = np.full((n, cap), -1, np.int32)
+        out["n_cand"] = np.zeros(n, np.int32)
+        L = _Lists(cap, _p(out["cand"]), _p(out["cand_band"]), _p(out["contrib"]), _p(out["contrib_band"]),
+                   _p(out["n_cand"]))
+        Lp = ctypes.byref(L)
+    lib().orc_render_rays(ctypes.byref(ov.s), n, _p(o), _p(e), _p(rgb), _p(ws), _p(cnt), Lp)
+    return out
+
+
+def render(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, cap: int = 0, jitter=None):
+    """Eq. (2) at the pixel centres listed in idx (all pixels if None)."""
+    pxy = pixel_centres(W, H, idx)
+    if jitter is not None:
+        pxy = pxy + np.asarray(jitter, np.float64)
+    o, e = eye_rays(pos, rot, hfov_deg, W, H, pxy)
+    return render_rays(ov, o, e, cap)
+
+
+def render_reference(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, ss: int = 4, disk_scale: float = 2.0):
+    """Offline reference: ss x ss regular sub-pixel rays per pixel, disks scaled by
+    disk_scale, every view considered; the pixel is the box average of the sub-ray
+    values (an uncovered sub-ray counts as 0)."""
+    if idx is None:
+        idx = np.arange(W * H)
+    idx = np.asarray(idx, np.int64)
+    base = np.stack([(idx % W).astype(np.float64), (idx // W).astype(np.float64)], 1)
+    offs = (np.arange(ss) + 0.5) / ss
+    sub = np.stack(np.meshgrid(offs, offs, indexing="xy"), -1).reshape(-1, 2)  # (ss*ss, 2) as (x, y)
+    pxy = (base[:, None, :] + sub[None, :, :]).reshape(-1, 2)
+    o, e = eye_rays(pos, rot, hfov_deg, W, H, pxy)
+    r = render_rays(ov.with_disk_radius(ov.s.disk_radius * disk_scale), o, e)
+    return r["rgb"].reshape(len(idx), ss * ss, 3).mean(1)
+
+
+def disk(ov: OracleViews, i, o, e):
+    o = np.ascontiguousarray(o, np.float64); e = np.ascontiguousarray(e, np.float64)
+    out = np.zeros(4)
+    ptrs = [out.ctypes.data + 8 * k for k in range(4)]
+    lib().orc_disk(ctypes.byref(ov.s), int(i), _p(o), _p(e), *ptrs)
+    return tuple(out)
+
+
+def mesh_hit(ov: OracleViews, i, o, e) -> float:
+    o = np.ascontiguousarray(o, np.float64); e = np.ascontiguousarray(e, np.float64)
+    return float(lib().orc_mesh_hit(ctypes.byref(ov.s), int(i), _p(o), _p(e)))
+
+
+def sample(ov: OracleViews, i, Xs, Ys):
+    out = np.zeros(3)
+    lib().orc_sample(ctypes.byref(ov.s), int(i), float(Xs), float(Ys), _p(out))
+    return out
+
+
+def records(ov: OracleViews, o, e):
+    o = np.ascontiguousarray(o, np.float64); e = np.ascontiguousarray(e, np.float64)
+    recs = np.zeros(ov.n, REC_DTYPE)
+    lib().orc_ray_records(ctypes.byref(ov.s), _p(o), _p(e), _p(recs))
+    return recs

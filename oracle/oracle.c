@@ -1,0 +1,405 @@
+/*
+ * FP64 CPU oracle for disk-blended light field reconstruction.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain reference that the
+ * GPU path is checked against. Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it. It shares no code, header,
+ * table or helper with the HIP library; the only thing both consume is the
+ * synthetic input data written by the seeded generator.
+ *
+ * What it computes (paper, Sec. 3.1, Eqs. (1)-(2)): for an eye ray (o, e)
+ *
+ *     L(o, e) = sum_i I_i(s_i, t_i) rho_i(u_i, v_i) / sum_i rho_i(u_i, v_i)
+ *
+ * where (u_i, v_i) is where the ray crosses view i's disk (centred on the
+ * view's centre of projection, tangent to the capture sphere, normal along the
+ * optical axis, u and v along the image axes: Sec. 3.1 and Sec. 3.4), rho_i is
+ * the linear-falloff kernel (1 at the centre, 0 at the rim: Sec. 3.1), and
+ * (s_i, t_i) is the image-i position of the nearest intersection of the ray
+ * with view i's own triangle mesh (Sec. 3.1; intra-image occlusion only,
+ * Sec. 3.2.2; the mesh is the depth map tessellated with two triangles per
+ * depth pixel, Sec. 3.5). Pass 1 / pass 2 of Sec. 3.2 (accumulate numerator and
+ * denominator, then divide) become two running sums and one division.
+ *
+ * The geometry is deliberately evaluated in WORLD space with the published
+ * watertight ray/triangle test (Woop, Benthin & Wald 2013), over either all
+ * triangles ("brute") or the cells visited by an Amanatides-Woo 2-D grid walk
+ * (Amanatides & Woo 1987) dilated by one cell ("traversal"); the nearest hit
+ * is the minimum t over every triangle tested, with no early exit.
+ *
+ * Readings of points the paper leaves open (each also listed in the design
+ * notes of the repository):
+ *   - disk: a planar circle of radius R in the tangent plane at c_i, normal f_i;
+ *     rho = 1 - r/R, a candidate iff rho > 0; a ray with e.f_i <= 0 never uses
+ *     view i (back-facing disk);
+ *   - mesh: vertices at depth-pixel centres, V_jk = c_i + z_jk R_i (X_j, Y_k, 1),
+ *     cell (j,k) split along (j,k)-(j+1,k+1); both faces count; barycentric
+ *     tests inclusive;
+ *   - (s,t): exact projection of the 3-D hit into view i;
+ *   - a view whose mesh the ray misses adds nothing to either sum; if both sums
+ *     are empty the pixel is (0,0,0);
+ *   - sampling: bilinear, texel centres at half-integers, clamp-to-edge, RGB of
+ *     the RGBA8 texel divided by 255, alpha ignored.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t n, img_w, img_h, mesh_m;
+    double src_fov_deg;
+    const double *centres;   /* [n][3] world metres */
+    const double *rot;       /* [n][9] row-major, columns (r,u,f) */
+    const uint8_t *rgba8;    /* [n][img_h][img_w][4] */
+    const float *zdepth;     /* [n][mesh_m][mesh_m] z along f, metres */
+    const double *zrange;    /* [n][2] min,max of each depth map (orc_zrange) */
+    double disk_radius;
+    int32_t mode;            /* 0 = traversal, 1 = brute force over all triangles */
+    int32_t threads;
+} orc_views;
+
+/* Per-ray outputs. Lists are ascending view ids padded with -1. */
+typedef struct {
+    int32_t cap;             /* capacity of each list (0 = no lists) */
+    int32_t *cand;           /* [n_rays][cap] views with rho > 0 */
+    int32_t *cand_band;      /* [n_rays][cap] views whose disk decision is ill-conditioned */
+    int32_t *contrib;        /* [n_rays][cap] candidates whose mesh is hit */
+    int32_t *contrib_band;   /* [n_rays][cap] contributing or not, hit/miss ill-conditioned */
+    int32_t *n_cand;         /* [n_rays] number of candidates (even beyond cap) */
+} orc_lists;
+
+static inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static inline void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static inline void sub3(const double a[3], const double b[3], double o[3]) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+/* column a of a row-major frame */
+static inline void col3(const double *R, int a, double o[3]) { o[0] = R[a]; o[1] = R[3 + a]; o[2] = R[6 + a]; }
+/* R^T x  (world vector -> view-local components along r, u, f) */
+static inline void to_local(const double *R, const double x[3], double o[3]) {
+    o[0] = R[0] * x[0] + R[3] * x[1] + R[6] * x[2];
+    o[1] = R[1] * x[0] + R[4] * x[1] + R[7] * x[2];
+    o[2] = R[2] * x[0] + R[5] * x[1] + R[8] * x[2];
+}
+
+/* Exact min / max of each depth map (the mesh cannot leave this z range). */
+void orc_zrange(int32_t n, int32_t m, const float *z, double *out) {
+    for (int32_t i = 0; i < n; ++i) {
+        const float *zi = z + (int64_t)i * m * m;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t k = 0; k < (int64_t)m * m; ++k) {
+            if (zi[k] < lo) lo = zi[k];
+            if (zi[k] > hi) hi = zi[k];
+        }
+        out[2 * i] = lo;
+        out[2 * i + 1] = hi;
+    }
+}
+
+/*
+ * Eye rays (Sec. 3.1, Eq. (1)): origin o = eye centre, direction through the
+ * continuous pixel position (x, y), where pixel (px, py) has its centre at
+ * (px + 1/2, py + 1/2). The FOV is horizontal; the vertical half-angle follows
+ * from the aspect ratio (square pixels).
+ */
+void orc_eye_rays(const double pos[3], const double *rot, double hfov_deg, int32_t W, int32_t H,
+                  int64_t n, const double *pxy, double *o, double *e) {
+    double tx = tan(0.5 * hfov_deg * M_PI / 180.0), ty = tx * (double)H / (double)W;
+    for (int64_t k = 0; k < n; ++k) {
+        double X = (2.0 * pxy[2 * k] / W - 1.0) * tx;
+        double Y = (1.0 - 2.0 * pxy[2 * k + 1] / H) * ty;
+        for (int a = 0; a < 3; ++a) {
+            o[3 * k + a] = pos[a];
+            e[3 * k + a] = rot[3 * a + 0] * X + rot[3 * a + 1] * Y + rot[3 * a + 2];
+        }
+    }
+}
+
+/*
+ * Disk of view i (Sec. 3.1 and Sec. 3.4): plane through c_i with normal f_i,
+ * local axes r_i, u_i. Returns a = e.f_i, the local intersection (u, v) and
+ * rho = 1 - |(u,v)| / R (not clamped). For a <= 0 the disk faces away and
+ * u, v, rho are set to NaN.
+ */
+void orc_disk(const orc_views *V, int32_t i, const double o[3], const double e[3],
+              double *a_out, double *u_out, double *v_out, double *rho_out) {
+    const double *c = V->centres + 3 * i, *R = V->rot + 9 * i;
+    double f[3], r[3], u[3];
+    col3(R, 0, r); col3(R, 1, u); col3(R, 2, f);
+    double a = dot3(e, f);
+    *a_out = a;
+    if (!(a > 0.0)) { *u_out = *v_out = *rho_out = NAN; return; }
+    double co[3]; sub3(c, o, co);
+    double ts = dot3(co, f) / a;
+    double q[3] = {o[0] + ts * e[0] - c[0], o[1] + ts * e[1] - c[1], o[2] + ts * e[2] - c[2]};
+    double uu = dot3(q, r), vv = dot3(q, u);
+    *u_out = uu; *v_out = vv;
+    *rho_out = 1.0 - sqrt(uu * uu + vv * vv) / V->disk_radius;
+}
+
+/* World-space vertex (j, k) of view i's mesh: c_i + z_jk R_i (X_j, Y_k, 1). */
+static inline void mesh_vertex(const orc_views *V, int32_t i, int32_t j, int32_t k, double out[3]) {
+    const int32_t M = V->mesh_m;
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    double X = (2.0 * (j + 0.5) / M - 1.0) * ts;
+    double Y = (1.0 - 2.0 * (k + 0.5) / M) * ts;
+    double z = (double)V->zdepth[((int64_t)i * M + k) * M + j];
+    const double *c = V->centres + 3 * i, *R = V->rot + 9 * i;
+    for (int a = 0; a < 3; ++a) out[a] = c[a] + z * (R[3 * a + 0] * X + R[3 * a + 1] * Y + R[3 * a + 2]);
+}
+
+/*
+ * Watertight ray/triangle test (Woop, Benthin & Wald, JCGT 2013): the ray is
+ * sheared so that it runs along the +z axis of a permuted frame, and the
+ * triangle is tested by the signs of three 2-D edge functions. A shared edge or
+ * vertex is evaluated from the same operands in every triangle that owns it,
+ * so a ray through it hits at least one of them (no cracks). Both faces count;
+ * a zero edge function is inside (inclusive).
+ */
+static int tri_hit(const double o[3], const double d[3], const double v0[3], const double v1[3],
+                   const double v2[3], double *t_out) {
+    int kz = 0;
+    if (fabs(d[1]) > fabs(d[kz])) kz = 1;
+    if (fabs(d[2]) > fabs(d[kz])) kz = 2;
+    int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+    if (d[kz] < 0.0) { int tmp = kx; kx = ky; ky = tmp; }
+    const double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
+    double A[3], B[3], C[3];
+    sub3(v0, o, A);
+    sub3(v1, o, B);
+    sub3(v2, o, C);
+    const double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
+    const double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
+    const double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
+    const double U = Cx * By - Cy * Bx;
+    const double Vv = Ax * Cy - Ay * Cx;
+    const double Ww = Bx * Ay - By * Ax;
+    if ((U < 0.0 || Vv < 0.0 || Ww < 0.0) && (U > 0.0 || Vv > 0.0 || Ww > 0.0)) return 0;
+    const double det = U + Vv + Ww;
+    if (det == 0.0) return 0;
+    const double T = U * (Sz * A[kz]) + Vv * (Sz * B[kz]) + Ww * (Sz * C[kz]);
+    *t_out = T / det;
+    return 1;
+}
+
+/* Both triangles of cell (j, k); updates *best with the smallest positive t. */
+static void test_cell(const orc_views *V, int32_t i, int32_t j, int32_t k, const double o[3],
+                      const double e[3], double *best) {
+    const int32_t M = V->mesh_m;
+    if (j < 0 || k < 0 || j > M - 2 || k > M - 2) return;
+    double v00[3], v10[3], v01[3], v11[3], t;
+    mesh_vertex(V, i, j, k, v00);
+    mesh_vertex(V, i, j + 1, k, v10);
+    mesh_vertex(V, i, j, k + 1, v01);
+    mesh_vertex(V, i, j + 1, k + 1, v11);
+    if (tri_hit(o, e, v00, v10, v11, &t) && t > 0.0 && t < *best) *best = t;
+    if (tri_hit(o, e, v00, v11, v01, &t) && t > 0.0 && t < *best) *best = t;
+}
+
+/*
+ * Nearest intersection of the ray with view i's mesh (Sec. 3.1, Sec. 3.2.2,
+ * Sec. 3.5). Returns t (INFINITY when the mesh is missed).
+ */
+double orc_mesh_hit(const orc_views *V, int32_t i, const double o[3], const double e[3]) {
+    const int32_t M = V->mesh_m;
+    double best = INFINITY;
+    if (V->mode == 1) {
+        for (int32_t k = 0; k < M - 1; ++k)
+            for (int32_t j = 0; j < M - 1; ++j) test_cell(V, i, j, k, o, e, &best);
+        return best;
+    }
+    /* Traversal: the mesh lies within z in [zmin, zmax] in view i's frame, so the
+     * hit projects onto the image-plane segment between the ray's points at
+     * those two depths. Walk the grid cells that segment crosses. */
+    const double *c = V->centres + 3 * i, *R = V->rot + 9 * i;
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    double oc[3], ol[3], el[3];
+    sub3(o, c, oc);
+    to_local(R, oc, ol);
+    to_local(R, e, el);
+    if (!(el[2] > 0.0)) {
+        /* rays that never move forward along f can still meet the mesh only if
+         * they start in front of the view; never the case for eyes inside the
+         * capture sphere, so fall back to the brute force walk */
+        for (int32_t k = 0; k < M - 1; ++k)
+            for (int32_t j = 0; j < M - 1; ++j) test_cell(V, i, j, k, o, e, &best);
+        return best;
+    }
+    double zlo = V->zrange[2 * i], zhi = V->zrange[2 * i + 1];
+    double g[2][2];
+    for (int s = 0; s < 2; ++s) {
+        double z = s ? zhi : zlo;
+        double t = (z - ol[2]) / el[2];
+        double px = ol[0] + t * el[0], py = ol[1] + t * el[1];
+        double X = px / z, Y = py / z;
+        g[s][0] = (X / ts + 1.0) * 0.5 * M - 0.5;  /* grid coordinate: vertex j sits at j */
+        g[s][1] = (1.0 - Y / ts) * 0.5 * M - 0.5;
+    }
+    double bx0 = fmin(g[0][0], g[1][0]), bx1 = fmax(g[0][0], g[1][0]);
+    double by0 = fmin(g[0][1], g[1][1]), by1 = fmax(g[0][1], g[1][1]);
+    if (bx1 < -2.0 || by1 < -2.0 || bx0 > M + 1.0 || by0 > M + 1.0) return best;
+    /* clip the walk to the grid box grown by two cells (the dilation covers the rest) */
+    double x0 = g[0][0], y0 = g[0][1], x1 = g[1][0], y1 = g[1][1];
+    {
+        double dx = x1 - x0, dy = y1 - y0, tl = 0.0, th = 1.0;
+        const double lo = -2.0, hi = M + 1.0;
+        double p[4] = {-dx, dx, -dy, dy}, q[4] = {x0 - lo, hi - x0, y0 - lo, hi - y0};
+        for (int s = 0; s < 4; ++s) {
+            if (p[s] == 0.0) { if (q[s] < 0.0) return best; continue; }
+            double r = q[s] / p[s];
+            if (p[s] < 0.0) { if (r > tl) tl = r; } else { if (r < th) th = r; }
+        }
+        if (tl > th) return best;
+        double nx0 = x0 + tl * dx, ny0 = y0 + tl * dy, nx1 = x0 + th * dx, ny1 = y0 + th * dy;
+        x0 = nx0; y0 = ny0; x1 = nx1; y1 = ny1;
+    }
+    /* Amanatides-Woo over unit cells; cell (j,k) spans [j, j+1) x [k, k+1) */
+    int64_t cj = (int64_t)floor(x0), ck = (int64_t)floor(y0);
+    int64_t ej = (int64_t)floor(x1), ek = (int64_t)floor(y1);
+    double dx = x1 - x0, dy = y1 - y0;
+    int sx = dx > 0 ? 1 : (dx < 0 ? -1 : 0), sy = dy > 0 ? 1 : (dy < 0 ? -1 : 0);
+    double tmx = INFINITY, tmy = INFINITY, tdx = INFINITY, tdy = INFINITY;
+    if (sx != 0) { double nb = sx > 0 ? (double)(cj + 1) : (double)cj; tmx = (nb - x0) / dx; tdx = fabs(1.0 / dx); }
+    if (sy != 0) { double nb = sy > 0 ? (double)(ck + 1) : (double)ck; tmy = (nb - y0) / dy; tdy = fabs(1.0 / dy); }
+    int64_t guard = 4 * (int64_t)M + 16;
+    for (;;) {
+        for (int64_t kk = ck - 1; kk <= ck + 1; ++kk)
+            for (int64_t jj = cj - 1; jj <= cj + 1; ++jj) test_cell(V, i, (int32_t)jj, (int32_t)kk, o, e, &best);
+        if ((cj == ej && ck == ek) || --guard < 0) break;
+        if (tmx < tmy) { if (tmx > 1.0) break; cj += sx; tmx += tdx; }
+        else { if (tmy > 1.0) break; ck += sy; tmy += tdy; }
+    }
+    return best;
+}
+
+/* Continuous sample of view i's image at normalised image-plane point (Xs, Ys):
+ * bilinear over texel centres, clamp-to-edge, RGB/255. */
+void orc_sample(const orc_views *V, int32_t i, double Xs, double Ys, double rgb[3]) {
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    const int32_t W = V->img_w, H = V->img_h;
+    double px = (Xs / ts + 1.0) * 0.5 * W - 0.5;
+    double py = (1.0 - Ys / ts) * 0.5 * H - 0.5;
+    double fx0 = floor(px), fy0 = floor(py);
+    double fx = px - fx0, fy = py - fy0;
+    int64_t x0 = (int64_t)fx0, y0 = (int64_t)fy0, x1 = x0 + 1, y1 = y0 + 1;
+    if (x0 < 0) x0 = 0; if (x0 > W - 1) x0 = W - 1;
+    if (x1 < 0) x1 = 0; if (x1 > W - 1) x1 = W - 1;
+    if (y0 < 0) y0 = 0; if (y0 > H - 1) y0 = H - 1;
+    if (y1 < 0) y1 = 0; if (y1 > H - 1) y1 = H - 1;
+    const uint8_t *img = V->rgba8 + (int64_t)i * W * H * 4;
+    const uint8_t *p00 = img + (y0 * W + x0) * 4, *p10 = img + (y0 * W + x1) * 4;
+    const uint8_t *p01 = img + (y1 * W + x0) * 4, *p11 = img + (y1 * W + x1) * 4;
+    for (int a = 0; a < 3; ++a) {
+        double top = p00[a] + fx * ((double)p10[a] - p00[a]);
+        double bot = p01[a] + fx * ((double)p11[a] - p01[a]);
+        rgb[a] = (top + fy * (bot - top)) / 255.0;
+    }
+}
+
+/* One view's full record for one ray (used by the per-ray loop and by tests). */
+typedef struct {
+    double a, u, v, rho, t_hit, Xs, Ys, rgb[3];
+    int32_t cand, hit;
+} orc_rec;
+
+void orc_view_ray(const orc_views *V, int32_t i, const double o[3], const double e[3], orc_rec *r) {
+    memset(r, 0, sizeof(*r));
+    orc_disk(V, i, o, e, &r->a, &r->u, &r->v, &r->rho);
+    r->t_hit = INFINITY;
+    r->Xs = r->Ys = NAN;
+    r->cand = (r->a > 0.0 && r->rho > 0.0);
+    if (!r->cand) return;
+    double t = orc_mesh_hit(V, i, o, e);
+    if (!isfinite(t)) return;
+    r->hit = 1;
+    r->t_hit = t;
+    /* reproject the 3-D hit into view i */
+    const double *c = V->centres + 3 * i, *R = V->rot + 9 * i;
+    double P[3] = {o[0] + t * e[0] - c[0], o[1] + t * e[1] - c[1], o[2] + t * e[2] - c[2]};
+    double Pl[3];
+    to_local(R, P, Pl);
+    r->Xs = Pl[0] / Pl[2];
+    r->Ys = Pl[1] / Pl[2];
+    orc_sample(V, i, r->Xs, r->Ys, r->rgb);
+}
+
+static void list_put(int32_t *list, int32_t cap, int32_t *cnt, int32_t id) {
+    if (list && *cnt < cap) list[*cnt] = id;
+    (*cnt)++;
+}
+
+/*
+ * Eq. (2) for a batch of rays over ALL views (no culling). Outputs colour
+ * (n,3), weight sum W (n), contributing-view count (n); lists optional.
+ */
+void orc_render_rays(const orc_views *V, int64_t n_rays, const double *o, const double *e,
+                     double *rgb, double *wsum, int32_t *count, const orc_lists *L) {
+#ifdef _OPENMP
+    if (V->threads > 0) omp_set_num_threads(V->threads);
+#endif
+    const double md_band = 1e-5, a_band = 1e-9, edge_band = 1e-6;
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    const double dom = 1.0 - 1.0 / V->mesh_m; /* mesh domain in normalised image units */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_rays; ++k) {
+        const double *ok = o + 3 * k, *ek = e + 3 * k;
+        double acc[3] = {0, 0, 0}, ws = 0.0;
+        int32_t cnt = 0, nc = 0, nb = 0, nh = 0, nhb = 0;
+        int32_t cap = L ? L->cap : 0;
+        int32_t *lc = L && L->cand ? L->cand + k * cap : NULL;
+        int32_t *lb = L && L->cand_band ? L->cand_band + k * cap : NULL;
+        int32_t *lh = L && L->contrib ? L->contrib + k * cap : NULL;
+        int32_t *lhb = L && L->contrib_band ? L->contrib_band + k * cap : NULL;
+        double en = sqrt(dot3(ek, ek));
+        for (int32_t i = 0; i < V->n; ++i) {
+            orc_rec r;
+            orc_view_ray(V, i, ok, ek, &r);
+            if (L) {
+                double md = isnan(r.rho) ? INFINITY : fabs(r.rho);
+                if (md <= md_band || fabs(r.a) <= a_band * en) list_put(lb, cap, &nb, i);
+            }
+            if (!r.cand) continue;
+            list_put(lc, cap, &nc, i);
+            if (!r.hit) continue;
+            if (L) {
+                double m = fmin(dom - fabs(r.Xs / ts), dom - fabs(r.Ys / ts));
+                if (m < edge_band) list_put(lhb, cap, &nhb, i);
+            }
+            list_put(lh, cap, &nh, i);
+            for (int a = 0; a < 3; ++a) acc[a] += r.rho * r.rgb[a];
+            ws += r.rho;
+            cnt++;
+        }
+        if (L) {
+            if (L->n_cand) L->n_cand[k] = nc;
+            for (int32_t s = nc; s < cap; ++s) if (lc) lc[s] = -1;
+            for (int32_t s = nb; s < cap; ++s) if (lb) lb[s] = -1;
+            for (int32_t s = nh; s < cap; ++s) if (lh) lh[s] = -1;
+            for (int32_t s = nhb; s < cap; ++s) if (lhb) lhb[s] = -1;
+        }
+        for (int a = 0; a < 3; ++a) rgb[3 * k + a] = ws > 0.0 ? acc[a] / ws : 0.0;
+        if (wsum) wsum[k] = ws;
+        if (count) count[k] = cnt;
+    }
+}
+
+/* Per-view records for a single ray (tests and diagnostics). */
+void orc_ray_records(const orc_views *V, const double o[3], const double e[3], orc_rec *recs) {
+    for (int32_t i = 0; i < V->n; ++i) orc_view_ray(V, i, o, e, &recs[i]);
+}
+
+int32_t orc_views_size(void) { return (int32_t)sizeof(orc_views); }
+int32_t orc_rec_size(void) { return (int32_t)sizeof(orc_rec); }
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
