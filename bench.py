@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the light field renderer on one MI355X.
+
+Workload (synthetic, seeded): 1024 source views of 1024x1024 RGBA8 on a
+0.35 m Fibonacci capture sphere with 256x256 z-depth meshes, a scene of 12
+textured spheres in a 6 m box; stereo eye pairs of 2 x 1440x1600 at 100 deg
+horizontal FOV, IPD 64 mm, for 3000 seeded head poses in a 0.25 m ball. One
+step is one stereo frame through the whole path (per-eye set-up, tile
+culling, fused reproject + gather + blend), with the light field already
+resident in HBM.
+
+Prints ONE JSON line. `value` is eye-view Mpix/s of the compact-storage path
+(FP16 images, FP16 geometry, FP32 arithmetic); the plain FP32 path (FP32
+images and geometry) is timed beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "eye-view Mpix/s + ms/stereo frame, FP16/batched vs plain FP32 at ≤2/255 err"
+EYE_W, EYE_H, HFOV, IPD = 1440, 1600, 100.0, 0.064
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+# algorithmic FP32 operations per counted unit of k_render
+FLOPS_PER = {"disk_tests": 25, "candidates": 30, "cells": 28, "samples": 50}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1810_08860_amd", "csrc", "lf_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path, variant):
+    """HBM bytes per k_render launch measured by rocprofv3 --pmc (FETCH_SIZE,
+    WRITE_SIZE), scaled by a copy-kernel calibration; None when absent or
+    taken on a different kernel source."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_source_hash():
+        return None
+    v = t.get("variants", {}).get(variant)
+    if not v:
+        return None
+    return v.get("fetch_bytes", 0) + v.get("write_bytes", 0)
+
+
+def time_variant(lf, torch, ctx, eyes_all, steps, warmup, profile=False):
+    npx = 2 * EYE_W * EYE_H
+    out = torch.empty(npx * 3, dtype=torch.float32, device="cuda")
+    res = np.array([[EYE_W, EYE_H], [EYE_W, EYE_H]], np.int32)
+    P = len(eyes_all)
+    for k in range(warmup):
+        lf.lf_render(ctx, eyes_all[k % P], HFOV, res, out)
+    torch.cuda.synchronize()
+    if profile:
+        lf.lf_profile(ctx, True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        lf.lf_render(ctx, eyes_all[k % P], HFOV, res, out)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        prof = lf.lf_profile_read(ctx)
+        lf.lf_profile(ctx, False)
+    frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    total_s = t1 - t0
+    return {
+        "mpix_s": npx * steps / total_s / 1e6,
+        "ms_per_stereo_frame": 1e3 * total_s / steps,
+        "p50_ms": float(np.percentile(frame_ms, 50)),
+        "p99_ms": float(np.percentile(frame_ms, 99)),
+        "prof": prof,
+        "out": out,
+    }
+
+
+def cpu_baseline(lf, torch, views, head_pos, head_rot, ctx_plain, seconds):
+    """FP64 oracle on a bounded sample of the same workload (pixels of the
+    first stereo frame, strided), on all host cores; also the largest
+    difference of the plain FP32 GPU render from it on that sample."""
+    import oracle
+    ov = oracle.OracleViews.from_views(views)
+    eyes = oracle.stereo_eyes(head_pos[0], head_rot[0], IPD)
+    npx = EYE_W * EYE_H
+    gpu = torch.empty(2 * npx * 3, dtype=torch.float32, device="cuda")
+    lf.lf_render(ctx_plain, lf.lf_stereo_eyes(head_pos[0], head_rot[0], IPD), HFOV,
+                 np.array([[EYE_W, EYE_H]] * 2, np.int32), gpu)
+    torch.cuda.synchronize()
+    gpu_h = gpu.view(2, npx, 3).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    done, t_used, errs = 0, 0.0, []
+    chunk = 4096
+    while t_used < seconds:
+        e = done % 2
+        idx = rng.integers(0, npx, chunk)
+        t0 = time.perf_counter()
+        r = oracle.render(ov, eyes[e][0], eyes[e][1], HFOV, EYE_W, EYE_H, idx)
+        t_used += time.perf_counter() - t0
+        errs.append(np.abs(gpu_h[e][idx] - r["rgb"]).max(1))
+        done += chunk
+    err = np.concatenate(errs)
+    return {
+        "value": done / t_used / 1e6,
+        "unit": "Mpix/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"{done} random pixels of the first stereo frame (2x{EYE_W}x{EYE_H}), FP64, all views, "
+                  f"{t_used:.1f} s",
+        "s_per_stereo_frame": 2 * npx / (done / t_used),
+        "gpu_fp32_vs_oracle": {"max_abs": float(err.max()), "p999_abs": float(np.quantile(err, 0.999)),
+                               "frac_gt_1e-4": float((err > 1e-4).mean())},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000, help="stereo frames timed per variant")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="plain,fp16,rgba8")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lfsynth
+    from paper_1810_08860_amd import lf
+
+    t0 = time.perf_counter()
+    w = lfsynth.make_workload("full", seed=0)
+    V = w.views
+    log(f"[bench] generated {V.n} views {V.img_res}^2 + {V.mesh_m}^2 depth, {len(w.head_pos)} poses "
+        f"in {time.perf_counter() - t0:.1f} s")
+    eyes_all = [lf.lf_stereo_eyes(w.head_pos[k], w.head_rot[k], IPD) for k in range(len(w.head_pos))]
+
+    variants = {"plain": ("rgba32f", "f32"), "fp16": ("rgba16f", "f16"), "rgba8": ("rgba8", "f16")}
+    chosen = [v for v in args.variants.split(",") if v]
+    results, ctx_plain = {}, None
+    for name in chosen:
+        img, geo = variants[name]
+        t0 = time.perf_counter()
+        ctx = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
+                               img_fmt=img, geo_fmt=geo)
+        log(f"[bench] {name}: loaded ({img}, {geo}) in {time.perf_counter() - t0:.1f} s")
+        r = time_variant(lf, torch, ctx, eyes_all, args.steps, args.warmup, profile=(name == "fp16"))
+        if name == "fp16":
+            # work counters of the same frames (outside the timed region)
+            acc = {k: 0 for k in lf.STAT_NAMES}
+            n_stat = min(64, len(eyes_all))
+            for k in range(n_stat):
+                s = lf.lf_render_stats(ctx, eyes_all[k], HFOV, np.array([[EYE_W, EYE_H]] * 2, np.int32))
+                for kk in acc:
+                    acc[kk] += s[kk]
+            r["stats_per_frame"] = {k: v / n_stat for k, v in acc.items()}
+        del r["out"]
+        results[name] = r
+        log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.3f} ms/stereo frame "
+            f"(p50 {r['p50_ms']:.3f}, p99 {r['p99_ms']:.3f})")
+        if name == "plain" and not args.no_cpu_baseline:
+            ctx_plain = ctx
+        else:
+            ctx.close()
+        torch.cuda.empty_cache()
+
+    main_name = "fp16" if "fp16" in results else chosen[0]
+    m = results[main_name]
+    roofline = None
+    if m.get("prof") and m.get("stats_per_frame"):
+        p, st = m["prof"], m["stats_per_frame"]
+        render_ms = p["render_ms"] / max(p["render_n"], 1)   # one k_render launch per stereo frame
+        flops = sum(FLOPS_PER[k] * st[k] for k in FLOPS_PER)
+        achieved = flops / (render_ms * 1e-3) / 1e12
+        traffic = load_traffic(args.traffic, main_name)
+        roofline = {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "k_render",
+            "kernel_ms": render_ms,
+            "algorithmic_flop_per_launch": flops,
+            "work_per_launch": st,
+            "cull_ms": p["cull_ms"] / max(p["cull_n"], 1),
+            "prep_ms": p["prep_ms"] / max(p["prep_n"], 1),
+            "output_write_gbs": (2 * EYE_W * EYE_H * 12) / (render_ms * 1e-3) / 1e9,
+        }
+
+    cpu = None
+    if ctx_plain is not None:
+        log("[bench] cpu baseline (FP64 oracle) ...")
+        cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctx_plain, args.cpu_seconds)
+        ctx_plain.close()
+
+    line = {
+        "metric": METRIC,
+        "value": m["mpix_s"],
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_stereo_frame"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "stereo 2x1440x1600 eye views at 100 deg from 1024 views of 1024^2 RGBA8 with 256^2 "
+                        "depth meshes, 12 spheres + box, 3000 seeded head poses",
+            "path": main_name,
+            "storage": dict(zip(("images", "geometry"), variants[main_name])),
+            "tile": "16x16",
+            "cap": 32,
+        },
+        "ms_per_stereo_frame": m["ms_per_stereo_frame"],
+        "p50_ms": m["p50_ms"],
+        "p99_ms": m["p99_ms"],
+        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms")}
+                     for k, v in results.items()},
+        "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

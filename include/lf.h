@@ -1,0 +1,181 @@
+/*
+ * lf.h -- C ABI of the MI355X light field renderer (liblf.so).
+ *
+ * The library answers the disk-blended light field query of Overbeck et al.
+ * 2018 (Sec. 3.1, Eq. (2)) for every pixel of one or more eye views:
+ *
+ *   L(o, e) = sum_i I_i(s_i, t_i) rho_i(u_i, v_i) / sum_i rho_i(u_i, v_i)
+ *
+ * over a set of source views captured on a sphere. Each view i has a centre of
+ * projection c_i, an orthonormal frame R_i (columns r_i, u_i, f_i: image +x,
+ * image up, optical axis), an RGBA8 image and a z-depth map that defines the
+ * view's own triangle mesh (Sec. 3.5: two triangles per depth pixel, vertices
+ * at depth-pixel centres, cell (j,k) split along its (j,k)-(j+1,k+1) diagonal).
+ * The disk of view i lies in the plane through c_i with normal f_i, with local
+ * axes r_i, u_i, and weights rays by rho = 1 - r/R (Sec. 3.1 linear falloff).
+ * (s_i, t_i) is the image-i position of the nearest intersection of the ray
+ * with view i's mesh (intra-image occlusion only, Sec. 3.2.2); a view whose
+ * disk or mesh the ray misses contributes to neither sum. A pixel no view
+ * contributes to is (0,0,0).
+ *
+ * Conventions
+ *  - Every function returns LF_OK (0) or a negative LF_E* code; the message of
+ *    the last failure on the calling thread is returned by lf_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Frames are 3x3 row-major doubles whose COLUMNS are (r, u, f). The
+ *    camera-local point (X z, Y z, z) is the world point c + R (X z, Y z, z).
+ *  - Pixel (x, y) of a W x H image with horizontal half-FOV tangent tx has its
+ *    centre ray through X = (2(x+1/2)/W - 1) tx, Y = (1 - 2(y+1/2)/H) ty,
+ *    ty = tx H / W (row 0 at the top, square pixels). Source views are square
+ *    with the same FOV on both axes.
+ *  - Render calls are asynchronous on the given HIP stream (NULL = the null
+ *    stream). Argument errors are returned at once; a device fault surfaces as
+ *    LF_EHIP from a later call or synchronisation.
+ *  - A context owns all device memory it allocates and is not thread-safe; use
+ *    one context per host thread / stream. Separate contexts are independent.
+ */
+#ifndef LF_H
+#define LF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lf_ctx lf_ctx;
+
+enum {
+    LF_OK = 0,
+    LF_EINVAL = -1, /* invalid argument (null pointer, bad size, non-orthonormal frame, ...) */
+    LF_ENOMEM = -2, /* device allocation failed */
+    LF_EHIP = -3,   /* HIP runtime error (launch failure, asynchronous fault) */
+    LF_ESTATE = -4  /* call not valid in the context's current state */
+};
+
+/* Storage format of the source images on the device. RGBA32F is the plain
+ * FP32 form; RGBA16F and RGBA8 (UNORM) are the compact forms. All sampling
+ * and blending arithmetic is FP32 in every format. */
+enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2 };
+
+/* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex, in
+ * FP32 or FP16, packed per mesh cell. Intersection arithmetic is FP32. */
+enum { LF_GEO_F32 = 0, LF_GEO_F16 = 1 };
+
+/* lf_views_desc.flags: the rgba8 / zdepth pointers are device pointers. */
+enum { LF_SRC_DEVICE = 1 };
+
+typedef struct {
+    int32_t n_views;          /* N >= 1 (at most 65535) */
+    int32_t img_w, img_h;     /* source image size, pixels (square FOV: img_w == img_h) */
+    int32_t mesh_m;           /* depth map is mesh_m x mesh_m, mesh_m >= 2 */
+    double src_fov_deg;       /* full FOV of the source views, in (0, 180) */
+    const double *centres;    /* [N][3] view centres c_i, world metres (host memory) */
+    const double *rot;        /* [N][9] frames R_i, row-major, columns (r,u,f) (host memory) */
+    const uint8_t *rgba8;     /* [N][img_h][img_w][4] images, UNORM8; alpha is ignored */
+    const float *zdepth;      /* [N][mesh_m][mesh_m] z along f_i at depth-pixel centres, metres, > 0 */
+    double disk_radius;       /* R, metres, > 0 */
+    int32_t img_fmt;          /* LF_IMG_* */
+    int32_t geo_fmt;          /* LF_GEO_* */
+    int32_t flags;            /* LF_SRC_DEVICE or 0 */
+} lf_views_desc;
+
+/* One eye: centre of projection and frame (columns r, u, f). */
+typedef struct {
+    double pos[3];
+    double rot[9];
+} lf_eye;
+
+/* Launch shape: screen tile (tile_w x tile_h pixels, both multiples of 8,
+ * tile_w * tile_h <= 256) and the number of candidate views staged in LDS per
+ * pass (cap in [1, 64]). */
+typedef struct {
+    int32_t tile_w, tile_h, cap;
+} lf_tune;
+
+/*
+ * Copy a light field to the device and prepare it for rendering: convert the
+ * images to img_fmt, turn each depth map into per-cell inverse-depth corners
+ * (the vertex set of the view's mesh, Sec. 3.5) and record each view's
+ * inverse-depth range. The caller may free every input on return.
+ * Errors: LF_EINVAL for a null pointer, non-positive size, mesh_m < 2,
+ * img_w != img_h, FOV outside (0,180), a frame not orthonormal to 1e-6, a
+ * depth that is not finite and positive, or R <= 0; LF_ENOMEM; LF_EHIP.
+ * On success *out owns the device data until lf_free.
+ */
+int lf_load_views(const lf_views_desc *d, lf_ctx **out);
+
+/* Stereo pair from a head pose: eyes at pos -/+ (ipd/2) r_head with the head's
+ * frame (parallel optical axes). out[0] is the left eye. */
+int lf_stereo_eyes(const double head_pos[3], const double head_rot[9], double ipd_m, lf_eye out[2]);
+
+/* Set the launch shape used by lf_render (NULL restores the default 16x16, 32). */
+int lf_set_tune(lf_ctx *c, const lf_tune *t);
+
+/*
+ * Render n_eyes eye views (Sec. 3.1, Eqs. (1)-(2)). res[2k], res[2k+1] are the
+ * width and height of eye k; hfov_deg is the horizontal FOV of every eye.
+ * out_rgb is a DEVICE buffer of sum_k W_k H_k RGB float triples, eyes
+ * concatenated in order, each eye row-major from the top row. out_wsum
+ * (device, one float per pixel: sum of rho over contributing views) and
+ * out_count (device, one byte per pixel: number of contributing views,
+ * saturating at 255) may be NULL. Every eye must lie behind every view's disk
+ * plane (inside the capture surface), else LF_EINVAL.
+ */
+int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+              float *out_rgb, float *out_wsum, uint8_t *out_count, void *hip_stream);
+
+/*
+ * Offline reference render (the analogue of the high-quality offline query of
+ * Sec. 4.1): ss x ss regular sub-pixel rays per pixel, disks of radius
+ * disk_scale * R, box-averaged; a sub-ray no view covers counts as 0.
+ * Same buffers and layout as lf_render (out_rgb only).
+ */
+int lf_render_reference(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                        int32_t ss, double disk_scale, float *out_rgb, void *hip_stream);
+
+/*
+ * Per-pixel view sets of one eye, for parity checks: out_cand[p][cap] lists
+ * the views whose disk covers pixel p's centre ray (rho > 0), out_contrib[p][cap]
+ * those of them whose mesh the ray hits, both ascending and padded with -1
+ * (device int32 buffers of W*H*cap entries). out_ncand (device int32, may be
+ * NULL) receives the full candidate count even when it exceeds cap.
+ * The decisions are exactly the ones lf_render takes.
+ */
+int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W, int32_t H, int32_t cap,
+                        int32_t *out_cand, int32_t *out_contrib, int32_t *out_ncand, void *hip_stream);
+
+/*
+ * Count the work one lf_render call with the same arguments performs (it runs
+ * the same decisions without writing an image): counters[0] pixels,
+ * [1] per-ray disk tests, [2] candidate (ray, view) pairs with rho > 0,
+ * [3] mesh cells visited by the intersection walk, [4] contributing
+ * (ray, view) pairs (bilinear samples). Synchronous on hip_stream.
+ */
+int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    uint64_t counters[5], void *hip_stream);
+
+/*
+ * Per-kernel timing. lf_profile(c, 1) clears the totals and starts bracketing
+ * every kernel the context launches with HIP events on the launch stream;
+ * lf_profile(c, 0) stops. lf_profile_read waits for the recorded events and
+ * returns the accumulated milliseconds of the set-up, cull and render kernels
+ * in out[0..2] and their launch counts in out[3..5].
+ */
+int lf_profile(lf_ctx *c, int32_t enable);
+int lf_profile_read(lf_ctx *c, double out[6]);
+
+/* Number of views, image and mesh sizes and formats of a context. */
+int lf_query(const lf_ctx *c, int32_t *n_views, int32_t *img_w, int32_t *mesh_m, int32_t *img_fmt,
+             int32_t *geo_fmt);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char *lf_last_error(void);
+
+/* Release a context and all its device memory (NULL is a no-op). */
+void lf_free(lf_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LF_H */

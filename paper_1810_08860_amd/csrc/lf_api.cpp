@@ -1,0 +1,524 @@
+// Host runtime of liblf.so: argument validation, device memory, eye set-up and
+// kernel launches behind the C ABI declared in include/lf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lf.h"
+#include "lf_internal.h"
+
+using namespace lf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? LF_ENOMEM : LF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LF_HIP(call, what)                          \
+    do {                                            \
+        hipError_t _e = (call);                     \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+bool frame_ok(const double *R) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int r = 0; r < 3; ++r) s += R[3 * r + a] * R[3 * r + b];
+            if (!std::isfinite(s) || std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    return true;
+}
+
+size_t img_bytes_per_texel(int fmt) { return fmt == LF_IMG_RGBA8 ? 4 : (fmt == LF_IMG_RGBA16F ? 8 : 16); }
+size_t geo_bytes_per_cell(int fmt) { return fmt == LF_GEO_F32 ? 16 : 8; }
+
+}  // namespace
+
+struct lf_ctx {
+    int device = 0;
+    int32_t n = 0, img_w = 0, img_h = 0, M = 0;
+    double src_fov_deg = 0.0, tan_s = 0.0, R = 0.0;
+    int32_t img_fmt = 0, geo_fmt = 0;
+    void *img = nullptr;     // device images in img_fmt
+    void *geo = nullptr;     // device mesh cells in geo_fmt
+    double *vt = nullptr;    // device [n][12]: centre, frame
+    float2 *wr = nullptr;    // device [n]: inverse-depth range
+    std::vector<double> h_vt;  // host copy of the view table (eye validation)
+    // per-render scratch: eye-view table and tile lists, grown on demand
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    lf_tune tune{16, 16, 32};
+    // optional per-kernel timing (lf_profile): event pairs around each launch
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool profiling = false;
+    std::vector<Timed> timed;
+    double prof_ms[3] = {0, 0, 0};
+    double prof_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+// Run `launch` on stream s, bracketed by events when profiling is on.
+// kind: 0 = prep, 1 = cull, 2 = render.
+template <class F>
+hipError_t timed_launch(lf_ctx *c, int kind, hipStream_t s, F launch) {
+    if (!c->profiling) return launch();
+    lf_ctx::Timed t{kind, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&t.a);
+    if (e == hipSuccess) e = hipEventCreate(&t.b);
+    if (e == hipSuccess) e = hipEventRecord(t.a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(t.b, s);
+    c->timed.push_back(t);
+    return e;
+}
+
+int ensure_scratch(lf_ctx *c, size_t bytes) {
+    if (bytes <= c->scratch_bytes) return LF_OK;
+    if (c->scratch) {
+        LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        LF_HIP(hipFree(c->scratch), "hipFree");
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    LF_HIP(hipMalloc(&c->scratch, want), "hipMalloc(scratch)");
+    c->scratch_bytes = want;
+    return LF_OK;
+}
+
+int check_eyes(const lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res) {
+    if (!eyes || !res) return fail(LF_EINVAL, "eyes and res must not be NULL");
+    if (n_eyes <= 0) return fail(LF_EINVAL, "n_eyes must be positive (got %d)", n_eyes);
+    if (!(hfov_deg > 0.0 && hfov_deg < 180.0)) return fail(LF_EINVAL, "hfov_deg must be in (0,180) (got %g)", hfov_deg);
+    for (int32_t k = 0; k < n_eyes; ++k) {
+        if (res[2 * k] <= 0 || res[2 * k + 1] <= 0 || res[2 * k] > 32768 || res[2 * k + 1] > 32768)
+            return fail(LF_EINVAL, "eye %d: resolution %dx%d out of range", k, res[2 * k], res[2 * k + 1]);
+        const lf_eye &E = eyes[k];
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(E.pos[a])) return fail(LF_EINVAL, "eye %d: position is not finite", k);
+        if (!frame_ok(E.rot)) return fail(LF_EINVAL, "eye %d: frame is not orthonormal to 1e-6", k);
+        // the eye must lie behind every disk plane (inside the capture surface)
+        for (int32_t v = 0; v < c->n; ++v) {
+            const double *vc = &c->h_vt[12 * (size_t)v];
+            const double *R = vc + 3;
+            double s = 0.0;
+            for (int r = 0; r < 3; ++r) s += R[3 * r + 2] * (E.pos[r] - vc[r]);
+            if (!(s < 0.0))
+                return fail(LF_EINVAL, "eye %d lies on or in front of the disk plane of view %d", k, v);
+        }
+    }
+    return LF_OK;
+}
+
+void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, double hfov_deg, const int32_t *res,
+                int64_t pix_off, int tw, int th) {
+    std::memset(&ch, 0, sizeof ch);
+    ch.n_eyes = n;
+    ch.tile_w = tw;
+    ch.tile_h = th;
+    const double tx = std::tan(0.5 * hfov_deg * M_PI / 180.0);
+    int32_t tiles = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        EyeParam &E = ch.e[k];
+        std::memcpy(E.pos, eyes[k].pos, sizeof E.pos);
+        std::memcpy(E.rot, eyes[k].rot, sizeof E.rot);
+        E.W = res[2 * k];
+        E.H = res[2 * k + 1];
+        E.tx = (float)tx;
+        E.ty = (float)(tx * E.H / E.W);
+        E.tiles_x = (E.W + tw - 1) / tw;
+        E.tiles_y = (E.H + th - 1) / th;
+        E.tile_off = tiles;
+        E.pix_off = pix_off;
+        tiles += E.tiles_x * E.tiles_y;
+        pix_off += (int64_t)E.W * E.H;
+    }
+    ch.total_tiles = tiles;
+}
+
+RenderArgs base_args(const lf_ctx *c, double R) {
+    RenderArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n_views = c->n;
+    a.img = c->img;
+    a.geo = c->geo;
+    a.M = c->M;
+    a.img_w = c->img_w;
+    a.img_h = c->img_h;
+    a.sM = (float)(c->M / (2.0 * c->tan_s));
+    a.cM = (float)(0.5 * (c->M - 1));
+    a.sW = (float)(c->img_w / (2.0 * c->tan_s));
+    a.cW = (float)(0.5 * (c->img_w - 1));
+    a.sH = (float)(c->img_h / (2.0 * c->tan_s));
+    a.cH = (float)(0.5 * (c->img_h - 1));
+    a.R = (float)R;
+    a.invR = (float)(1.0 / R);
+    a.texels_per_view = (int64_t)c->img_w * c->img_h;
+    a.cells_per_view = (int64_t)(c->M - 1) * (c->M - 1);
+    a.cap = c->tune.cap;
+    a.scale = 1.0f;
+    return a;
+}
+
+// Prep + cull for one chunk of eyes; fills the table/list pointers of `a`.
+int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t s) {
+    const size_t ev_bytes = sizeof(EyeView) * (size_t)ch.n_eyes * c->n;
+    const size_t list_bytes = sizeof(uint16_t) * (size_t)kListCap * ch.total_tiles;
+    const size_t cnt_bytes = sizeof(int32_t) * (size_t)ch.total_tiles;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    int rc = ensure_scratch(c, al(ev_bytes) + al(list_bytes) + al(cnt_bytes));
+    if (rc) return rc;
+    char *p = (char *)c->scratch;
+    EyeView *ev = (EyeView *)p;
+    uint16_t *tl = (uint16_t *)(p + al(ev_bytes));
+    int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
+    LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, ev, s); }), "k_prep launch");
+    // conservative radius: the exact per-ray test decides in k_render
+    const float R_keep = (float)(R * (1.0 + 1e-4) + 1e-7);
+    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, R_keep, tl, tc, s); }), "k_cull launch");
+    a.ev = ev;
+    a.tile_list = tl;
+    a.tile_count = tc;
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lf_last_error(void) { return g_err.c_str(); }
+
+int lf_stereo_eyes(const double head_pos[3], const double head_rot[9], double ipd_m, lf_eye out[2]) {
+    if (!head_pos || !head_rot || !out) return fail(LF_EINVAL, "NULL argument");
+    if (!std::isfinite(ipd_m) || ipd_m < 0.0) return fail(LF_EINVAL, "ipd must be finite and >= 0");
+    if (!frame_ok(head_rot)) return fail(LF_EINVAL, "head frame is not orthonormal to 1e-6");
+    for (int k = 0; k < 2; ++k) {
+        const double sgn = k == 0 ? -0.5 : 0.5;
+        for (int a = 0; a < 3; ++a) out[k].pos[a] = head_pos[a] + sgn * ipd_m * head_rot[3 * a + 0];
+        std::memcpy(out[k].rot, head_rot, sizeof(double) * 9);
+    }
+    return LF_OK;
+}
+
+int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
+    if (!d || !out) return fail(LF_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->n_views <= 0 || d->n_views > 65535) return fail(LF_EINVAL, "n_views must be in [1, 65535] (got %d)", d->n_views);
+    if (d->img_w <= 0 || d->img_h <= 0) return fail(LF_EINVAL, "image size must be positive");
+    if (d->img_w != d->img_h) return fail(LF_EINVAL, "source views must be square (got %dx%d)", d->img_w, d->img_h);
+    if (d->mesh_m < 2 || d->mesh_m > 8192) return fail(LF_EINVAL, "mesh_m must be in [2, 8192] (got %d)", d->mesh_m);
+    if (!(d->src_fov_deg > 0.0 && d->src_fov_deg < 180.0)) return fail(LF_EINVAL, "src_fov_deg must be in (0,180)");
+    if (!(d->disk_radius > 0.0) || !std::isfinite(d->disk_radius)) return fail(LF_EINVAL, "disk_radius must be > 0");
+    if (!d->centres || !d->rot || !d->rgba8 || !d->zdepth) return fail(LF_EINVAL, "NULL data pointer");
+    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_RGBA32F) return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
+    if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
+    if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
+    const int32_t n = d->n_views, M = d->mesh_m;
+    for (int32_t v = 0; v < n; ++v) {
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(d->centres[3 * v + a])) return fail(LF_EINVAL, "view %d: centre not finite", v);
+        if (!frame_ok(d->rot + 9 * (size_t)v)) return fail(LF_EINVAL, "view %d: frame is not orthonormal to 1e-6", v);
+    }
+    const bool dev_src = d->flags & LF_SRC_DEVICE;
+    const size_t n_z = (size_t)n * M * M;
+    if (!dev_src) {
+        for (size_t k = 0; k < n_z; ++k)
+            if (!(d->zdepth[k] > 0.0f) || !std::isfinite(d->zdepth[k]))
+                return fail(LF_EINVAL, "depth %zu (view %zu) is not finite and positive", k, k / ((size_t)M * M));
+    }
+
+    lf_ctx *c = new lf_ctx();
+    auto bail = [&](int rc) {
+        lf_free(c);
+        return rc;
+    };
+    (void)hipGetDevice(&c->device);
+    c->n = n;
+    c->img_w = d->img_w;
+    c->img_h = d->img_h;
+    c->M = M;
+    c->src_fov_deg = d->src_fov_deg;
+    c->tan_s = std::tan(0.5 * d->src_fov_deg * M_PI / 180.0);
+    c->R = d->disk_radius;
+    c->img_fmt = d->img_fmt;
+    c->geo_fmt = d->geo_fmt;
+    c->h_vt.resize(12 * (size_t)n);
+    for (int32_t v = 0; v < n; ++v) {
+        std::memcpy(&c->h_vt[12 * (size_t)v], d->centres + 3 * (size_t)v, 3 * sizeof(double));
+        std::memcpy(&c->h_vt[12 * (size_t)v + 3], d->rot + 9 * (size_t)v, 9 * sizeof(double));
+    }
+    hipError_t e;
+    const size_t n_tex = (size_t)n * d->img_w * d->img_h;
+    if ((e = hipMalloc(&c->vt, c->h_vt.size() * sizeof(double))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(view table)"));
+    if ((e = hipMalloc(&c->wr, sizeof(float2) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(w range)"));
+    if ((e = hipMemcpy(c->vt, c->h_vt.data(), c->h_vt.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "copy view table"));
+
+    // images: RGBA8 upload, converted on the device when another format is asked for
+    void *rgba_dev = nullptr;
+    bool rgba_owned = false;
+    if (dev_src) {
+        rgba_dev = (void *)d->rgba8;
+    } else {
+        if ((e = hipMalloc(&rgba_dev, n_tex * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(images)"));
+        rgba_owned = true;
+        if ((e = hipMemcpy(rgba_dev, d->rgba8, n_tex * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(rgba_dev);
+            return bail(hip_fail(e, "copy images"));
+        }
+    }
+    if (d->img_fmt == LF_IMG_RGBA8) {
+        if (rgba_owned) {
+            c->img = rgba_dev;
+        } else {
+            if ((e = hipMalloc(&c->img, n_tex * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(images)"));
+            if ((e = hipMemcpy(c->img, rgba_dev, n_tex * 4, hipMemcpyDeviceToDevice)) != hipSuccess)
+                return bail(hip_fail(e, "copy images"));
+        }
+    } else {
+        if ((e = hipMalloc(&c->img, n_tex * img_bytes_per_texel(d->img_fmt))) != hipSuccess) {
+            if (rgba_owned) (void)hipFree(rgba_dev);
+            return bail(hip_fail(e, "hipMalloc(converted images)"));
+        }
+        e = launch_convert_images((const uint8_t *)rgba_dev, c->img, d->img_fmt, (int64_t)n_tex, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (rgba_owned) (void)hipFree(rgba_dev);
+        if (e != hipSuccess) return bail(hip_fail(e, "image conversion"));
+    }
+
+    // geometry: z -> per-cell inverse-depth corners, then per-view range
+    float *z_dev = nullptr;
+    bool z_owned = false;
+    if (dev_src) {
+        z_dev = (float *)d->zdepth;
+    } else {
+        if ((e = hipMalloc(&z_dev, n_z * sizeof(float))) != hipSuccess) return bail(hip_fail(e, "hipMalloc(depth)"));
+        z_owned = true;
+        if ((e = hipMemcpy(z_dev, d->zdepth, n_z * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(z_dev);
+            return bail(hip_fail(e, "copy depth"));
+        }
+    }
+    const size_t n_cells = (size_t)n * (M - 1) * (M - 1);
+    if ((e = hipMalloc(&c->geo, n_cells * geo_bytes_per_cell(d->geo_fmt))) != hipSuccess) {
+        if (z_owned) (void)hipFree(z_dev);
+        return bail(hip_fail(e, "hipMalloc(mesh cells)"));
+    }
+    e = launch_geo_cells(z_dev, c->geo, d->geo_fmt, n, M, 0);
+    if (e == hipSuccess) e = launch_geo_range(c->geo, d->geo_fmt, n, M, c->wr, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (z_owned) (void)hipFree(z_dev);
+    if (e != hipSuccess) return bail(hip_fail(e, "geometry conversion"));
+    *out = c;
+    return LF_OK;
+}
+
+int lf_set_tune(lf_ctx *c, const lf_tune *t) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!t) {
+        c->tune = lf_tune{16, 16, 32};
+        return LF_OK;
+    }
+    if (t->tile_w <= 0 || t->tile_h <= 0 || t->tile_w % 8 || t->tile_h % 8 || t->tile_w * t->tile_h > 256)
+        return fail(LF_EINVAL, "tile must be multiples of 8 with at most 256 pixels (got %dx%d)", t->tile_w, t->tile_h);
+    if (t->cap < 1 || t->cap > kStage) return fail(LF_EINVAL, "cap must be in [1, %d] (got %d)", kStage, t->cap);
+    c->tune = *t;
+    return LF_OK;
+}
+
+int lf_query(const lf_ctx *c, int32_t *n_views, int32_t *img_w, int32_t *mesh_m, int32_t *img_fmt, int32_t *geo_fmt) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (n_views) *n_views = c->n;
+    if (img_w) *img_w = c->img_w;
+    if (mesh_m) *mesh_m = c->M;
+    if (img_fmt) *img_fmt = c->img_fmt;
+    if (geo_fmt) *geo_fmt = c->geo_fmt;
+    return LF_OK;
+}
+
+static int render_impl(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                       float *out_rgb, float *out_wsum, uint8_t *out_count, int mode, double R, float sub_x,
+                       float sub_y, float scale, int accumulate, hipStream_t s,
+                       unsigned long long *stats = nullptr) {
+    int64_t pix_off = 0;
+    for (int32_t k0 = 0; k0 < n_eyes; k0 += kMaxEyesPerLaunch) {
+        const int32_t nk = std::min(kMaxEyesPerLaunch, n_eyes - k0);
+        EyeChunk ch;
+        fill_chunk(c, ch, eyes + k0, nk, hfov_deg, res + 2 * k0, pix_off, c->tune.tile_w, c->tune.tile_h);
+        RenderArgs a = base_args(c, R);
+        int rc = prep_and_cull(c, ch, a, R, s);
+        if (rc) return rc;
+        a.out_rgb = out_rgb;
+        a.out_wsum = out_wsum;
+        a.out_count = out_count;
+        a.sub_x = sub_x;
+        a.sub_y = sub_y;
+        a.scale = scale;
+        a.accumulate = accumulate;
+        a.stats = stats;
+        LF_HIP(timed_launch(c, 2, s, [&] { return launch_render(ch, a, c->img_fmt, c->geo_fmt, mode, s); }),
+               "k_render launch");
+        for (int32_t k = 0; k < nk; ++k) pix_off += (int64_t)res[2 * (k0 + k)] * res[2 * (k0 + k) + 1];
+    }
+    return LF_OK;
+}
+
+int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res, float *out_rgb,
+              float *out_wsum, uint8_t *out_count, void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_rgb) return fail(LF_EINVAL, "out_rgb must not be NULL");
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    return render_impl(c, eyes, n_eyes, hfov_deg, res, out_rgb, out_wsum, out_count, MODE_RENDER, c->R, 0.5f, 0.5f,
+                       1.0f, 0, (hipStream_t)hip_stream);
+}
+
+int lf_render_reference(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                        int32_t ss, double disk_scale, float *out_rgb, void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_rgb) return fail(LF_EINVAL, "out_rgb must not be NULL");
+    if (ss < 1 || ss > 16) return fail(LF_EINVAL, "ss must be in [1,16] (got %d)", ss);
+    if (!(disk_scale > 0.0) || !std::isfinite(disk_scale)) return fail(LF_EINVAL, "disk_scale must be > 0");
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    const float scale = 1.0f / (float)(ss * ss);
+    for (int32_t sy = 0; sy < ss; ++sy)
+        for (int32_t sx = 0; sx < ss; ++sx) {
+            rc = render_impl(c, eyes, n_eyes, hfov_deg, res, out_rgb, nullptr, nullptr, MODE_SUBPIXEL,
+                             c->R * disk_scale, (sx + 0.5f) / ss, (sy + 0.5f) / ss, scale, (sx | sy) != 0,
+                             (hipStream_t)hip_stream);
+            if (rc) return rc;
+        }
+    return LF_OK;
+}
+
+int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W, int32_t H, int32_t cap,
+                        int32_t *out_cand, int32_t *out_contrib, int32_t *out_ncand, void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_cand || !out_contrib) return fail(LF_EINVAL, "out_cand and out_contrib must not be NULL");
+    if (cap < 1 || cap > 1024) return fail(LF_EINVAL, "cap must be in [1,1024] (got %d)", cap);
+    const int32_t res[2] = {W, H};
+    int rc = check_eyes(c, eye, 1, hfov_deg, res);
+    if (rc) return rc;
+    EyeChunk ch;
+    fill_chunk(c, ch, eye, 1, hfov_deg, res, 0, c->tune.tile_w, c->tune.tile_h);
+    RenderArgs a = base_args(c, c->R);
+    rc = prep_and_cull(c, ch, a, c->R, (hipStream_t)hip_stream);
+    if (rc) return rc;
+    a.dbg_cand = out_cand;
+    a.dbg_contrib = out_contrib;
+    a.dbg_ncand = out_ncand;
+    a.dbg_cap = cap;
+    LF_HIP(launch_render(ch, a, c->img_fmt, c->geo_fmt, MODE_DEBUG, (hipStream_t)hip_stream), "k_render launch");
+    return LF_OK;
+}
+
+int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    uint64_t counters[5], void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!counters) return fail(LF_EINVAL, "counters must not be NULL");
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long *d = nullptr;
+    LF_HIP(hipMalloc(&d, 5 * sizeof(unsigned long long)), "hipMalloc(stats)");
+    hipError_t e = hipMemsetAsync(d, 0, 5 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "hipMemsetAsync(stats)");
+    }
+    const bool prof = c->profiling;
+    c->profiling = false;
+    rc = render_impl(c, eyes, n_eyes, hfov_deg, res, nullptr, nullptr, nullptr, MODE_STATS, c->R, 0.5f, 0.5f, 1.0f,
+                     0, s, d);
+    c->profiling = prof;
+    if (rc == LF_OK) {
+        unsigned long long h[5];
+        e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "read stats");
+        else for (int k = 0; k < 5; ++k) counters[k] = h[k];
+    }
+    (void)hipFree(d);
+    return rc;
+}
+
+int lf_profile(lf_ctx *c, int32_t enable) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    for (auto &t : c->timed) {
+        (void)hipEventSynchronize(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    c->timed.clear();
+    for (int k = 0; k < 3; ++k) c->prof_ms[k] = c->prof_n[k] = 0.0;
+    c->profiling = enable != 0;
+    return LF_OK;
+}
+
+int lf_profile_read(lf_ctx *c, double out[6]) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out) return fail(LF_EINVAL, "out must not be NULL");
+    for (auto &t : c->timed) {
+        hipError_t e = hipEventSynchronize(t.b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+        if (e != hipSuccess) {
+            c->timed.clear();
+            return hip_fail(e, "profile events");
+        }
+        c->prof_ms[t.kind] += ms;
+        c->prof_n[t.kind] += 1.0;
+    }
+    c->timed.clear();
+    for (int k = 0; k < 3; ++k) {
+        out[k] = c->prof_ms[k];
+        out[3 + k] = c->prof_n[k];
+    }
+    return LF_OK;
+}
+
+void lf_free(lf_ctx *c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    if (c->img) (void)hipFree(c->img);
+    if (c->geo) (void)hipFree(c->geo);
+    if (c->vt) (void)hipFree(c->vt);
+    if (c->wr) (void)hipFree(c->wr);
+    if (c->scratch) (void)hipFree(c->scratch);
+    for (auto &t : c->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the C-ABI runtime (lf_api.cpp) and the HIP
+// kernels (lf_kernels.hip). Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf {
+
+constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
+constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
+constexpr int kStage = 64;             // candidate views staged in LDS per pass (upper bound of tune.cap)
+
+// One eye of a launch. pos/rot feed the per-(eye, view) setup in FP64.
+struct EyeParam {
+    double pos[3];
+    double rot[9];   // row-major, columns (r, u, f)
+    float tx, ty;    // half-FOV tangents
+    int32_t W, H;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_off;  // first tile of this eye within the launch
+    int32_t pad;
+    int64_t pix_off;   // first output pixel of this eye
+};
+
+struct EyeChunk {
+    int32_t n_eyes;
+    int32_t total_tiles;
+    int32_t tile_w, tile_h;
+    EyeParam e[kMaxEyesPerLaunch];
+};
+
+// Per (eye, view) transform, 64 bytes: e' = M (X, Y, 1) is the eye ray in the
+// view's frame, o' the eye centre in the view's frame.
+struct alignas(16) EyeView {
+    float m[9];
+    float o[3];
+    float wmin, wmax;  // inverse-depth range of the view's mesh
+    int32_t view;
+    int32_t pad;
+};
+
+enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3 };
+
+struct RenderArgs {
+    const EyeView *ev;          // [n_eyes][n_views]
+    int32_t n_views;
+    const uint16_t *tile_list;  // [tiles][kListCap]
+    const int32_t *tile_count;  // [tiles]
+    const void *img;
+    const void *geo;
+    int32_t M, img_w, img_h;
+    float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
+    float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
+    float R, invR;
+    int64_t texels_per_view, cells_per_view;
+    float *out_rgb;
+    float *out_wsum;
+    uint8_t *out_count;
+    int32_t cap;                // views staged per LDS pass
+    // sub-pixel (reference) passes: ray through (x + sub_x, y + sub_y); out += scale * L
+    float sub_x, sub_y, scale;
+    int32_t accumulate;
+    // debug lists
+    int32_t *dbg_cand, *dbg_contrib, *dbg_ncand;
+    int32_t dbg_cap;
+    // work counters: pixels, disk tests, candidates, mesh cells visited, samples
+    unsigned long long *stats;
+};
+
+// Launchers (lf_kernels.hip). All are asynchronous on `s` and return the
+// launch status.
+hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int64_t n_texels, hipStream_t s);
+hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
+hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
+hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, EyeView *ev,
+                       hipStream_t s);
+hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R_keep, uint16_t *tile_list,
+                       int32_t *tile_count, hipStream_t s);
+hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
+                         hipStream_t s);
+
+}  // namespace lf

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of liblf.so (include/lf.h). Argument marshalling only:
+every step of the render runs in the library's HIP kernels. Device buffers are
+passed as torch tensors (their data_ptr) or raw integer addresses."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblf.so")
+
+LF_OK, LF_EINVAL, LF_ENOMEM, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
+LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F = 0, 1, 2
+LF_GEO_F32, LF_GEO_F16 = 0, 1
+LF_SRC_DEVICE = 1
+
+IMG_FORMATS = {"rgba8": LF_IMG_RGBA8, "rgba16f": LF_IMG_RGBA16F, "rgba32f": LF_IMG_RGBA32F}
+GEO_FORMATS = {"f32": LF_GEO_F32, "f16": LF_GEO_F16}
+
+
+class lf_views_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_views", ctypes.c_int32), ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32),
+        ("mesh_m", ctypes.c_int32), ("src_fov_deg", ctypes.c_double),
+        ("centres", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("rgba8", ctypes.c_void_p),
+        ("zdepth", ctypes.c_void_p), ("disk_radius", ctypes.c_double),
+        ("img_fmt", ctypes.c_int32), ("geo_fmt", ctypes.c_int32), ("flags", ctypes.c_int32),
+    ]
+
+
+class lf_eye(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_double * 3), ("rot", ctypes.c_double * 9)]
+
+
+class lf_tune(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("cap", ctypes.c_int32)]
+
+
+class LFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load liblf.so; fail loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch owns device memory and streams: load its HIP runtime first so
+        # that liblf.so binds to the same runtime (same soname) instead of
+        # bringing a second one into the process
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.lf_load_views.argtypes = [ctypes.POINTER(lf_views_desc), ctypes.POINTER(vp)]
+        L.lf_stereo_eyes.argtypes = [vp, vp, f64, ctypes.POINTER(lf_eye)]
+        L.lf_set_tune.argtypes = [vp, ctypes.POINTER(lf_tune)]
+        L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
+        L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
+        L.lf_debug_candidates.argtypes = [vp, ctypes.POINTER(lf_eye), f64, i32, i32, i32, vp, vp, vp, vp]
+        L.lf_query.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
+        L.lf_profile.argtypes = [vp, i32]
+        L.lf_profile_read.argtypes = [vp, vp]
+        L.lf_last_error.restype = ctypes.c_char_p
+        L.lf_free.argtypes = [vp]
+        L.lf_free.restype = None
+        for name in ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
+                     "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LF_OK:
+        raise LFError(rc, lib().lf_last_error().decode())
+    return rc
+
+
+def _ptr(x):
+    """Device (or host) address of a torch tensor / numpy array / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_eyes(eyes) -> ctypes.Array:
+    """Eyes from a sequence of (pos[3], rot[3,3]) pairs or an lf_eye array."""
+    if isinstance(eyes, ctypes.Array):
+        return eyes
+    eyes = list(eyes)
+    arr = (lf_eye * len(eyes))()
+    for k, (p, r) in enumerate(eyes):
+        arr[k].pos[:] = [float(v) for v in np.asarray(p, np.float64).reshape(3)]
+        arr[k].rot[:] = [float(v) for v in np.asarray(r, np.float64).reshape(9)]
+    return arr
+
+
+class Context:
+    """Owns an lf_ctx handle (lf_free on close / garbage collection)."""
+
+    def __init__(self, handle, n_views, img_fmt, geo_fmt):
+        self.handle = handle
+        self.n_views = n_views
+        self.img_fmt = img_fmt
+        self.geo_fmt = geo_fmt
+
+    def close(self):
+        if self.handle:
+            lib().lf_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lf_load_views(centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, img_fmt="rgba8", geo_fmt="f32",
+                  device_src=False) -> Context:
+    img_fmt = IMG_FORMATS.get(img_fmt, img_fmt)
+    geo_fmt = GEO_FORMATS.get(geo_fmt, geo_fmt)
+    centres = np.ascontiguousarray(centres, np.float64)
+    rot = np.ascontiguousarray(np.asarray(rot, np.float64).reshape(-1, 9))
+    if device_src:
+        n, h, w, _ = tuple(rgba8.shape)
+        m = int(zdepth.shape[1])
+    else:
+        rgba8 = np.ascontiguousarray(rgba8, np.uint8)
+        zdepth = np.ascontiguousarray(zdepth, np.float32)
+        n, h, w, _ = rgba8.shape
+        m = zdepth.shape[1]
+    d = lf_views_desc(n, w, h, m, float(src_fov_deg), centres.ctypes.data, rot.ctypes.data, _ptr(rgba8),
+                      _ptr(zdepth), float(disk_radius), int(img_fmt), int(geo_fmt),
+                      LF_SRC_DEVICE if device_src else 0)
+    h_ = ctypes.c_void_p()
+    _check(lib().lf_load_views(ctypes.byref(d), ctypes.byref(h_)))
+    return Context(h_.value, n, img_fmt, geo_fmt)
+
+
+def lf_stereo_eyes(head_pos, head_rot, ipd_m):
+    hp = np.ascontiguousarray(head_pos, np.float64)
+    hr = np.ascontiguousarray(np.asarray(head_rot, np.float64).reshape(9))
+    out = (lf_eye * 2)()
+    _check(lib().lf_stereo_eyes(hp.ctypes.data, hr.ctypes.data, float(ipd_m), out))
+    return out
+
+
+def lf_set_tune(ctx: Context, tile_w=None, tile_h=None, cap=None):
+    if tile_w is None:
+        return _check(lib().lf_set_tune(ctx.handle, None))
+    t = lf_tune(int(tile_w), int(tile_h), int(cap))
+    return _check(lib().lf_set_tune(ctx.handle, ctypes.byref(t)))
+
+
+def _res(res, n):
+    r = np.ascontiguousarray(np.asarray(res, np.int32).reshape(-1))
+    if r.size == 2 and n > 1:
+        r = np.tile(r, n)
+    if r.size != 2 * n:
+        raise ValueError("res must hold a (W, H) pair per eye")
+    return r
+
+
+def lf_render(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, out_count=None, stream=None):
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    _check(lib().lf_render(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb), _ptr(out_wsum),
+                           _ptr(out_count), _stream(stream)))
+
+
+def lf_render_reference(ctx: Context, eyes, hfov_deg, res, ss, disk_scale, out_rgb, stream=None):
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    _check(lib().lf_render_reference(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, int(ss),
+                                     float(disk_scale), _ptr(out_rgb), _stream(stream)))
+
+
+def lf_debug_candidates(ctx: Context, eye, hfov_deg, W, H, cap, out_cand, out_contrib, out_ncand=None,
+                        stream=None):
+    e = make_eyes([eye]) if not isinstance(eye, ctypes.Array) else eye
+    _check(lib().lf_debug_candidates(ctx.handle, e, float(hfov_deg), int(W), int(H), int(cap), _ptr(out_cand),
+                                     _ptr(out_contrib), _ptr(out_ncand), _stream(stream)))
+
+
+STAT_NAMES = ("pixels", "disk_tests", "candidates", "cells", "samples")
+
+
+def lf_render_stats(ctx: Context, eyes, hfov_deg, res, stream=None) -> dict:
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    out = np.zeros(5, np.uint64)
+    _check(lib().lf_render_stats(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, out.ctypes.data,
+                                 _stream(stream)))
+    return {k: int(v) for k, v in zip(STAT_NAMES, out)}
+
+
+def lf_profile(ctx: Context, enable: bool):
+    _check(lib().lf_profile(ctx.handle, 1 if enable else 0))
+
+
+def lf_profile_read(ctx: Context) -> dict:
+    out = np.zeros(6, np.float64)
+    _check(lib().lf_profile_read(ctx.handle, out.ctypes.data))
+    return {"prep_ms": out[0], "cull_ms": out[1], "render_ms": out[2],
+            "prep_n": int(out[3]), "cull_n": int(out[4]), "render_n": int(out[5])}
+
+
+def lf_query(ctx: Context):
+    vals = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().lf_query(ctx.handle, *[ctypes.byref(v) for v in vals]))
+    return tuple(v.value for v in vals)
+
+
+def lf_last_error() -> str:
+    return lib().lf_last_error().decode()
+
+
+# names of every symbol include/lf.h declares (checked by the ABI test)
+EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
+           "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
+           "lf_last_error", "lf_free")

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/lf.h declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_08860_amd import lf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lf_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(lf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lf.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _desc(**kw):
+    c = np.zeros((2, 3))
+    r = np.tile(np.eye(3).reshape(1, 9), (2, 1))
+    img = np.zeros((2, 4, 4, 4), np.uint8)
+    z = np.ones((2, 3, 3), np.float32)
+    base = dict(n_views=2, img_w=4, img_h=4, mesh_m=3, src_fov_deg=120.0, centres=c.ctypes.data,
+                rot=r.ctypes.data, rgba8=img.ctypes.data, zdepth=z.ctypes.data, disk_radius=0.1,
+                img_fmt=0, geo_fmt=0, flags=0)
+    base.update(kw)
+    d = lf.lf_views_desc(**{k: v for k, v in base.items()})
+    return d, (c, r, img, z)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_views", 0, "n_views"),
+    ("img_w", 0, "image size"),
+    ("img_w", 5, "square"),
+    ("mesh_m", 1, "mesh_m"),
+    ("src_fov_deg", 180.0, "src_fov"),
+    ("disk_radius", 0.0, "disk_radius"),
+    ("img_fmt", 7, "img_fmt"),
+    ("geo_fmt", 5, "geo_fmt"),
+    ("flags", 8, "flags"),
+    ("rgba8", None, "NULL"),
+])
+def test_load_views_rejects_invalid(field, value, msg):
+    d, keep = _desc(**{field: value})
+    h = ctypes.c_void_p()
+    rc = lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h))
+    assert rc == lf.LF_EINVAL and h.value is None
+    assert msg in lf.lf_last_error()
+
+
+def test_load_views_rejects_bad_frame_and_depth():
+    d, (c, r, img, z) = _desc()
+    r[1, 0] = 1.1
+    h = ctypes.c_void_p()
+    assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL
+    assert "orthonormal" in lf.lf_last_error()
+    d, (c, r, img, z) = _desc()
+    z[1, 2, 2] = -1.0
+    assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL
+    assert "depth" in lf.lf_last_error()
+    d, (c, r, img, z) = _desc()
+    z[0, 0, 1] = np.nan
+    assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL
+
+
+def test_null_context_and_arguments():
+    L = lf.lib()
+    assert L.lf_set_tune(None, None) == lf.LF_EINVAL
+    assert L.lf_query(None, None, None, None, None, None) == lf.LF_EINVAL
+    e = lf.make_eyes([(np.zeros(3), np.eye(3))])
+    res = np.array([8, 8], np.int32)
+    assert L.lf_render(None, e, 1, 90.0, res.ctypes.data, 1, None, None, None) == lf.LF_EINVAL
+    assert "context" in lf.lf_last_error()
+    L.lf_free(None)  # no-op
+
+
+def test_stereo_eyes_matches_oracle_definition():
+    R = np.linalg.qr(np.random.default_rng(2).normal(size=(3, 3)))[0]
+    p = np.array([0.01, -0.1, 0.07])
+    out = lf.lf_stereo_eyes(p, R, 0.064)
+    ref = oracle.stereo_eyes(p, R, 0.064)
+    for k in range(2):
+        assert np.allclose(np.array(out[k].pos), ref[k][0], atol=1e-15)
+        assert np.allclose(np.array(out[k].rot).reshape(3, 3), ref[k][1])
+    assert np.linalg.norm(np.array(out[1].pos) - np.array(out[0].pos)) == pytest.approx(0.064)
+    bad = R.copy()
+    bad[0, 0] += 0.01
+    with pytest.raises(lf.LFError):
+        lf.lf_stereo_eyes(p, bad, 0.064)
+    with pytest.raises(lf.LFError):
+        lf.lf_stereo_eyes(p, R, -1.0)
