@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblf.so")
+HOSTCHECK_SO = os.path.join(HERE, "liblf_hostcheck.so")
 
 SOURCES = ["lf_kernels.hip", "lf_corrector.hip", "lf_api.cpp"]
 
@@ -46,6 +47,13 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(SO + ".tmp", SO)
+    # host build of the per-ray arithmetic, for CPU tests against the oracle
+    hc = [hipcc, *HIPCC_FLAGS, "-shared", "-I", os.path.join(ROOT, "include"),
+          os.path.join(CSRC, "lf_hostcheck.cpp"), "-o", HOSTCHECK_SO + ".tmp"]
+    if verbose:
+        print(" ".join(hc), flush=True)
+    subprocess.run(hc, check=True)
+    os.replace(HOSTCHECK_SO + ".tmp", HOSTCHECK_SO)
     return SO
 
 

@@ -63,6 +63,7 @@ struct lf_ctx {
     void *geo = nullptr;     // device mesh cells in geo_fmt
     double *vt = nullptr;    // device [n][12]: centre, frame
     float2 *wr = nullptr;    // device [n]: inverse-depth range
+    float2 *blk = nullptr;   // device [n][NB][NB]: inverse-depth range per block of cells
     std::vector<double> h_vt;  // host copy of the view table (eye validation)
     // per-render scratch: eye-view table and tile lists, grown on demand
     void *scratch = nullptr;
@@ -168,6 +169,8 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.n_views = c->n;
     a.img = c->img;
     a.geo = c->geo;
+    a.blk = c->blk;
+    a.NB = num_blocks(c->M);
     a.M = c->M;
     a.img_w = c->img_w;
     a.img_h = c->img_h;
@@ -330,8 +333,14 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         if (z_owned) (void)hipFree(z_dev);
         return bail(hip_fail(e, "hipMalloc(mesh cells)"));
     }
+    const int NB = num_blocks(M);
+    if ((e = hipMalloc(&c->blk, sizeof(float2) * (size_t)n * NB * NB)) != hipSuccess) {
+        if (z_owned) (void)hipFree(z_dev);
+        return bail(hip_fail(e, "hipMalloc(block bounds)"));
+    }
     e = launch_geo_cells(z_dev, c->geo, d->geo_fmt, n, M, 0);
     if (e == hipSuccess) e = launch_geo_range(c->geo, d->geo_fmt, n, M, c->wr, 0);
+    if (e == hipSuccess) e = launch_geo_blocks(c->geo, d->geo_fmt, n, M, c->blk, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (z_owned) (void)hipFree(z_dev);
     if (e != hipSuccess) return bail(hip_fail(e, "geometry conversion"));
@@ -513,6 +522,7 @@ void lf_free(lf_ctx *c) {
     if (c->geo) (void)hipFree(c->geo);
     if (c->vt) (void)hipFree(c->vt);
     if (c->wr) (void)hipFree(c->wr);
+    if (c->blk) (void)hipFree(c->blk);
     if (c->scratch) (void)hipFree(c->scratch);
     for (auto &t : c->timed) {
         (void)hipEventDestroy(t.a);

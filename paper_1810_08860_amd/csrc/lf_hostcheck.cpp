@@ -1,0 +1,109 @@
+// Host build of the renderer's per-ray arithmetic (lf_ray.h) for CPU tests:
+// the same disk test and two-level inverse-depth mesh walk the kernels run,
+// evaluated ray by ray on the host. Test support only; not part of liblf.so.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "lf_ray.h"
+
+using namespace lf;
+
+extern "C" {
+
+// For each ray k and view i: cand[k*n+i] (disk test passed), hit[k*n+i] (mesh
+// hit), and the normalised image-plane position (Xs, Ys) of the hit.
+// geo_fmt 0 = FP32 cells, 1 = FP16 cells. Returns 0.
+int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
+              double R, int32_t geo_fmt, int64_t n_rays, const double *o, const double *e, int32_t *cand,
+              int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
+    const int Mc = M - 1, NB = num_blocks(M);
+    const size_t per = (size_t)Mc * Mc;
+    std::vector<float4> c32(geo_fmt == 0 ? per * n : 0);
+    std::vector<uint2> c16(geo_fmt == 1 ? per * n : 0);
+    std::vector<float2> wr(n), blk((size_t)n * NB * NB);
+    for (int v = 0; v < n; ++v) {
+        const float *zv = z + (size_t)v * M * M;
+        for (int k = 0; k < Mc; ++k)
+            for (int j = 0; j < Mc; ++j) {
+                const float w00 = 1.0f / zv[k * M + j], w10 = 1.0f / zv[k * M + j + 1];
+                const float w01 = 1.0f / zv[(k + 1) * M + j], w11 = 1.0f / zv[(k + 1) * M + j + 1];
+                const size_t idx = (size_t)v * per + (size_t)k * Mc + j;
+                if (geo_fmt == 0) {
+                    c32[idx] = make_float4(w00, w10, w01, w11);
+                } else {
+                    __half2 a = __floats2half2_rn(w00, w10), b = __floats2half2_rn(w01, w11);
+                    uint2 q;
+                    std::memcpy(&q.x, &a, 4);
+                    std::memcpy(&q.y, &b, 4);
+                    c16[idx] = q;
+                }
+            }
+    }
+    const void *cells = geo_fmt == 0 ? (const void *)c32.data() : (const void *)c16.data();
+    for (int v = 0; v < n; ++v) {
+        float lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < NB * NB; ++b) {
+            const int bk = b / NB, bi = b % NB;
+            float blo = INFINITY, bhi = -INFINITY;
+            for (int k = bk * kBlk; k < std::min(bk * kBlk + kBlk, Mc); ++k)
+                for (int j = bi * kBlk; j < std::min(bi * kBlk + kBlk, Mc); ++j) {
+                    const float4 q = geo_fmt == 0 ? load_cell<0>(cells, (int64_t)v * per + (int64_t)k * Mc + j)
+                                                  : load_cell<1>(cells, (int64_t)v * per + (int64_t)k * Mc + j);
+                    blo = fminf(blo, fminf(fminf(q.x, q.y), fminf(q.z, q.w)));
+                    bhi = fmaxf(bhi, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
+                }
+            blk[(size_t)v * NB * NB + b] = make_float2(blo, bhi);
+            lo = fminf(lo, blo);
+            hi = fmaxf(hi, bhi);
+        }
+        wr[v] = make_float2(lo, hi);
+    }
+    const double ts = std::tan(0.5 * src_fov_deg * M_PI / 180.0);
+    const float sM = (float)(M / (2.0 * ts)), cM = (float)(0.5 * (M - 1));
+    const float Rf = (float)R, invR = (float)(1.0 / R);
+    for (int64_t k = 0; k < n_rays; ++k) {
+        for (int v = 0; v < n; ++v) {
+            const double *c = centres + 3 * v, *Rv = rot + 9 * v;
+            EyeView ev;
+            std::memset(&ev, 0, sizeof ev);
+            // e' = R^T e placed in the third column: the ray is (X, Y) = (0, 0)
+            for (int a = 0; a < 3; ++a) {
+                double s = 0.0, t = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    s += Rv[3 * r + a] * e[3 * k + r];
+                    t += Rv[3 * r + a] * (o[3 * k + r] - c[r]);
+                }
+                ev.m[3 * a + 2] = (float)s;
+                ev.o[a] = (float)t;
+            }
+            ev.wmin = wr[v].x;
+            ev.wmax = wr[v].y;
+            ev.view = v;
+            const size_t out = (size_t)k * n + v;
+            RayView rv;
+            cand[out] = disk_test(ev, 0.0f, 0.0f, Rf, invR, rv) ? 1 : 0;
+            hit[out] = 0;
+            Xs[out] = Ys[out] = NAN;
+            cells_visited[out] = 0;
+            if (!cand[out]) continue;
+            float wh;
+            int nc = 0;
+            const float2 *b = blk.data() + (size_t)v * NB * NB;
+            const void *cv = geo_fmt == 0 ? (const void *)(c32.data() + (size_t)v * per)
+                                          : (const void *)(c16.data() + (size_t)v * per);
+            const bool h = geo_fmt == 0
+                               ? march<0>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc)
+                               : march<1>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc);
+            cells_visited[out] = nc;
+            if (!h) continue;
+            hit[out] = 1;
+            Xs[out] = fmaf(wh, rv.Dx, rv.Vx);
+            Ys[out] = fmaf(wh, rv.Dy, rv.Vy);
+        }
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -10,6 +10,9 @@ namespace lf {
 constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
 constexpr int kStage = 64;             // candidate views staged in LDS per pass (upper bound of tune.cap)
+constexpr int kBlk = 8;                // mesh cells per side of an inverse-depth bounds block
+
+inline int num_blocks(int M) { return (M - 1 + kBlk - 1) / kBlk; }
 
 // One eye of a launch. pos/rot feed the per-(eye, view) setup in FP64.
 struct EyeParam {
@@ -49,6 +52,8 @@ struct RenderArgs {
     const int32_t *tile_count;  // [tiles]
     const void *img;
     const void *geo;
+    const float2 *blk;          // [n_views][NB][NB] inverse-depth bounds per cell block
+    int32_t NB;
     int32_t M, img_w, img_h;
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
     float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
@@ -73,6 +78,7 @@ struct RenderArgs {
 hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int64_t n_texels, hipStream_t s);
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
+hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, EyeView *ev,
                        hipStream_t s);
 hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R_keep, uint16_t *tile_list,

@@ -32,198 +32,9 @@
 #include <math.h>
 
 #include "lf_internal.h"
+#include "lf_ray.h"
 
 namespace lf {
-
-// ---------------------------------------------------------------------------------------------
-// storage formats
-
-struct Rgb {
-    float r, g, b;
-};
-
-template <int IMG>
-__device__ __forceinline__ Rgb texel(const void *__restrict__ img, int64_t idx);
-
-template <>
-__device__ __forceinline__ Rgb texel<0>(const void *__restrict__ img, int64_t idx) {  // RGBA8, 0..255
-    const uint32_t p = reinterpret_cast<const uint32_t *>(img)[idx];
-    return {(float)(p & 255u), (float)((p >> 8) & 255u), (float)((p >> 16) & 255u)};
-}
-template <>
-__device__ __forceinline__ Rgb texel<1>(const void *__restrict__ img, int64_t idx) {  // RGBA16F
-    uint2 p = reinterpret_cast<const uint2 *>(img)[idx];
-    __half2 rg = *reinterpret_cast<__half2 *>(&p.x);
-    __half2 ba = *reinterpret_cast<__half2 *>(&p.y);
-    return {__low2float(rg), __high2float(rg), __low2float(ba)};
-}
-template <>
-__device__ __forceinline__ Rgb texel<2>(const void *__restrict__ img, int64_t idx) {  // RGBA32F
-    float4 p = reinterpret_cast<const float4 *>(img)[idx];
-    return {p.x, p.y, p.z};
-}
-
-// scale from stored texel units to [0,1]
-template <int IMG>
-__device__ __forceinline__ float texel_scale() { return IMG == 0 ? (1.0f / 255.0f) : 1.0f; }
-
-// Corner inverse depths of one mesh cell: (w00, w10, w01, w11) with j to the
-// right and k downwards.
-template <int GEO>
-__device__ __forceinline__ float4 load_cell(const void *__restrict__ cells, int64_t idx);
-
-template <>
-__device__ __forceinline__ float4 load_cell<0>(const void *__restrict__ cells, int64_t idx) {
-    return reinterpret_cast<const float4 *>(cells)[idx];
-}
-template <>
-__device__ __forceinline__ float4 load_cell<1>(const void *__restrict__ cells, int64_t idx) {
-    uint2 p = reinterpret_cast<const uint2 *>(cells)[idx];
-    __half2 a = *reinterpret_cast<__half2 *>(&p.x);
-    __half2 b = *reinterpret_cast<__half2 *>(&p.y);
-    return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
-}
-
-// ---------------------------------------------------------------------------------------------
-// per-ray pieces
-
-struct RayView {
-    float Vx, Vy, Dx, Dy, rho;
-};
-
-// Exact disk test of one ray against one view (Sec. 3.1: linear falloff, disk
-// in the view's tangent plane). False for a back-facing disk or rho <= 0.
-__device__ __forceinline__ bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
-                                          RayView &rv) {
-    const float ez = fmaf(v.m[6], X, fmaf(v.m[7], Y, v.m[8]));
-    if (!(ez > 0.0f)) return false;
-    const float iz = 1.0f / ez;
-    const float Vx = fmaf(v.m[0], X, fmaf(v.m[1], Y, v.m[2])) * iz;
-    const float Vy = fmaf(v.m[3], X, fmaf(v.m[4], Y, v.m[5])) * iz;
-    const float Dx = fmaf(-v.o[2], Vx, v.o[0]);
-    const float Dy = fmaf(-v.o[2], Vy, v.o[1]);
-    const float r2 = fmaf(Dx, Dx, Dy * Dy);
-    if (!(r2 < R * R)) return false;
-    const float rho = fmaf(-sqrtf(r2), invR, 1.0f);
-    if (!(rho > 0.0f)) return false;
-    rv.Vx = Vx; rv.Vy = Vy; rv.Dx = Dx; rv.Dy = Dy; rv.rho = rho;
-    return true;
-}
-
-__device__ __forceinline__ float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
-
-// Inverse depth of the cell's mesh at local (fx, fy): triangle (00,10,11) where
-// fx >= fy, triangle (00,11,01) otherwise.
-__device__ __forceinline__ float field(const float4 &c, float fx, float fy) {
-    return fx >= fy ? fmaf(fy, c.w - c.y, fmaf(fx, c.y - c.x, c.x))
-                    : fmaf(fx, c.w - c.z, fmaf(fy, c.z - c.x, c.x));
-}
-
-__device__ __forceinline__ bool crosses(float g0, float g1) {
-    return (g0 < 0.0f && g1 >= 0.0f) || (g0 > 0.0f && g1 <= 0.0f);
-}
-
-// Largest w in [wlo, whi] at which the line (V + w D, w) meets the view's
-// mesh; false if it never does.
-template <int GEO>
-__device__ bool march(const void *__restrict__ cells, int M, float sM, float cM, float wlo, float whi, float Vx,
-                      float Vy, float Dx, float Dy, float &w_hit, int &n_cells) {
-    const float lim = (float)(M - 1);
-    const float ax = fmaf(Vx, sM, cM), bx = Dx * sM;
-    const float ay = fmaf(-Vy, sM, cM), by = -Dy * sM;
-    const bool mx = fabsf(bx) > 1e-20f, my = fabsf(by) > 1e-20f;
-    const float ibx = mx ? 1.0f / bx : 0.0f, iby = my ? 1.0f / by : 0.0f;
-    // clip to the mesh domain 0 <= g <= M-1 on both axes
-    if (mx) {
-        const float w1 = -ax * ibx, w2 = (lim - ax) * ibx;
-        wlo = fmaxf(wlo, fminf(w1, w2));
-        whi = fminf(whi, fmaxf(w1, w2));
-    } else if (!(ax >= 0.0f && ax <= lim)) {
-        return false;
-    }
-    if (my) {
-        const float w1 = -ay * iby, w2 = (lim - ay) * iby;
-        wlo = fmaxf(wlo, fminf(w1, w2));
-        whi = fminf(whi, fmaxf(w1, w2));
-    } else if (!(ay >= 0.0f && ay <= lim)) {
-        return false;
-    }
-    if (!(wlo <= whi)) return false;
-
-    const int Mc = M - 1;
-    float w0 = whi;
-    float gx = fmaf(w0, bx, ax), gy = fmaf(w0, by, ay);
-    int j = min(max((int)floorf(gx), 0), M - 2);
-    int k = min(max((int)floorf(gy), 0), M - 2);
-    const int sx = bx > 0.0f ? -1 : 1, sy = by > 0.0f ? -1 : 1;  // cell steps as w decreases
-    const float ox = bx > 0.0f ? 0.0f : 1.0f, oy = by > 0.0f ? 0.0f : 1.0f;
-    float4 cw = load_cell<GEO>(cells, (int64_t)k * Mc + j);
-    ++n_cells;
-    float fx0 = sat01(gx - (float)j), fy0 = sat01(gy - (float)k);
-    float g0 = field(cw, fx0, fy0) - w0;
-    if (g0 == 0.0f) {
-        w_hit = w0;
-        return true;
-    }
-    for (int it = 0; it < 2 * M + 4; ++it) {
-        // inverse depth at which the line leaves cell (j, k)
-        const float wxe = mx ? ((float)j + ox - ax) * ibx : -INFINITY;
-        const float wye = my ? ((float)k + oy - ay) * iby : -INFINITY;
-        const float wn = fmaxf(wxe, wye);
-        const bool last = !(wn > wlo);
-        const float w1 = last ? wlo : fminf(wn, w0);
-        const float fx1 = sat01(fmaf(w1, bx, ax) - (float)j), fy1 = sat01(fmaf(w1, by, ay) - (float)k);
-        const float d0 = fx0 - fy0, d1 = fx1 - fy1;
-        if ((d0 > 0.0f && d1 < 0.0f) || (d0 < 0.0f && d1 > 0.0f)) {
-            // the segment crosses the cell diagonal: two linear pieces
-            const float s = d0 / (d0 - d1);
-            const float wd = fmaf(s, w1 - w0, w0);
-            const float fd = fmaf(s, fx1 - fx0, fx0);
-            const float gd = field(cw, fd, fd) - wd;
-            if (crosses(g0, gd)) {
-                w_hit = fmaf(wd - w0, g0 / (g0 - gd), w0);
-                return true;
-            }
-            w0 = wd;
-            g0 = gd;
-            fx0 = fd;
-            fy0 = fd;
-        }
-        const float g1 = field(cw, fx1, fy1) - w1;
-        if (crosses(g0, g1)) {
-            w_hit = fmaf(w1 - w0, g0 / (g0 - g1), w0);
-            return true;
-        }
-        if (last) return false;
-        if (wxe == wn) j += sx;
-        if (wye == wn) k += sy;
-        if (j < 0 || j > M - 2 || k < 0 || k > M - 2) return false;
-        cw = load_cell<GEO>(cells, (int64_t)k * Mc + j);
-        ++n_cells;
-        fx0 = sat01(fmaf(w1, bx, ax) - (float)j);
-        fy0 = sat01(fmaf(w1, by, ay) - (float)k);
-        w0 = w1;
-        g0 = g1;
-    }
-    return false;
-}
-
-// Bilinear sample at normalised image-plane point (Xs, Ys): texel centres at
-// half-integers, clamp-to-edge (result in texel units; see texel_scale).
-template <int IMG>
-__device__ __forceinline__ Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float py) {
-    const float x0f = floorf(px), y0f = floorf(py);
-    const float fx = px - x0f, fy = py - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-    x0 = min(max(x0, 0), W - 1);
-    y0 = min(max(y0, 0), H - 1);
-    const Rgb a = texel<IMG>(img, (int64_t)y0 * W + x0), b = texel<IMG>(img, (int64_t)y0 * W + x1);
-    const Rgb c = texel<IMG>(img, (int64_t)y1 * W + x0), d = texel<IMG>(img, (int64_t)y1 * W + x1);
-    const float tr = fmaf(fx, b.r - a.r, a.r), tg = fmaf(fx, b.g - a.g, a.g), tb = fmaf(fx, b.b - a.b, a.b);
-    const float br = fmaf(fx, d.r - c.r, c.r), bg = fmaf(fx, d.g - c.g, c.g), bb = fmaf(fx, d.b - c.b, c.b);
-    return {fmaf(fy, br - tr, tr), fmaf(fy, bg - tg, tg), fmaf(fy, bb - tb, tb)};
-}
 
 __device__ __forceinline__ int find_eye(const EyeChunk &ch, int tile) {
     int e = 0;
@@ -303,6 +114,29 @@ __global__ __launch_bounds__(256) void k_geo_range(const void *__restrict__ cell
     if (threadIdx.x == 0) wr[blockIdx.x] = make_float2(slo[0], shi[0]);
 }
 
+// Min / max inverse depth over the vertices of each kBlk x kBlk block of cells
+// of each view (from the stored values). One thread per block.
+template <int GEO>
+__global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cells, int32_t n, int32_t M, int32_t NB,
+                                                    float2 *__restrict__ blk) {
+    const int64_t total = (int64_t)n * NB * NB;
+    const int Mc = M - 1;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < total; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = b / ((int64_t)NB * NB);
+        const int r = (int)(b % ((int64_t)NB * NB));
+        const int bk = r / NB, bi = r % NB;
+        const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc), k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc);
+        float lo = INFINITY, hi = -INFINITY;
+        for (int k = k0; k < k1; ++k)
+            for (int j = j0; j < j1; ++j) {
+                const float4 q = load_cell<GEO>(cells, v * (int64_t)Mc * Mc + (int64_t)k * Mc + j);
+                lo = fminf(lo, fminf(fminf(q.x, q.y), fminf(q.z, q.w)));
+                hi = fmaxf(hi, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
+            }
+        blk[b] = make_float2(lo, hi);
+    }
+}
+
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
 __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
                                               const float2 *__restrict__ wr, int32_t n, EyeView *__restrict__ ev) {
@@ -353,7 +187,33 @@ __device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, f
         dy[q] = fmaf(-v.o[2], fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5])) * iz, v.o[1]);
     }
     if (npos == 0) return false;
-    if (npos < 4) return true;
+    if (npos < 4) {
+        // the tile straddles the disk plane's horizon: test the disk's bounding
+        // sphere (centre c, radius R) against the tile's cone of rays instead;
+        // in the view's frame the disk centre sits at -o' from the eye
+        float ex[4], ey[4], ez[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ex[q] = fmaf(v.m[0], cx[q], fmaf(v.m[1], cy[q], v.m[2]));
+            ey[q] = fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5]));
+            ez[q] = fmaf(v.m[6], cx[q], fmaf(v.m[7], cy[q], v.m[8]));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int q1 = (q + 1) & 3, q2 = (q + 2) & 3;
+            float nx = ey[q] * ez[q1] - ez[q] * ey[q1];
+            float ny = ez[q] * ex[q1] - ex[q] * ez[q1];
+            float nz = ex[q] * ey[q1] - ey[q] * ex[q1];
+            if (nx * ex[q2] + ny * ey[q2] + nz * ez[q2] < 0.0f) {
+                nx = -nx;
+                ny = -ny;
+                nz = -nz;
+            }
+            const float dist = -(nx * v.o[0] + ny * v.o[1] + nz * v.o[2]);
+            if (dist < -R * sqrtf(nx * nx + ny * ny + nz * nz)) return false;
+        }
+        return true;
+    }
     bool allp = true, alln = true;
     float best = INFINITY;
 #pragma unroll
@@ -463,7 +323,8 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
                 float wh;
                 const void *cells = reinterpret_cast<const char *>(a.geo) +
                                     (int64_t)v.view * a.cells_per_view * (GEO == 0 ? 16 : 8);
-                if (!march<GEO>(cells, a.M, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, n_cells))
+                if (!march<GEO>(cells, a.blk + (int64_t)v.view * a.NB * a.NB, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax,
+                                rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, n_cells))
                     continue;
                 if (MODE == MODE_DEBUG) {
                     if (nh < a.dbg_cap) a.dbg_contrib[pix * a.dbg_cap + nh] = v.view;
@@ -561,6 +422,16 @@ hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M
         hipLaunchKernelGGL(k_geo_range<0>, dim3(n), dim3(256), 0, s, cells, M, wr);
     else
         hipLaunchKernelGGL(k_geo_range<1>, dim3(n), dim3(256), 0, s, cells, M, wr);
+    return hipGetLastError();
+}
+
+hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s) {
+    const int NB = num_blocks(M);
+    const int g = grid_for((int64_t)n * NB * NB, 256);
+    if (geo_fmt == 0)
+        hipLaunchKernelGGL(k_geo_blocks<0>, dim3(g), dim3(256), 0, s, cells, n, M, NB, blk);
+    else
+        hipLaunchKernelGGL(k_geo_blocks<1>, dim3(g), dim3(256), 0, s, cells, n, M, NB, blk);
     return hipGetLastError();
 }
 
