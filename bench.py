@@ -9,9 +9,12 @@ step is one stereo frame through the whole path (per-eye set-up, tile
 culling, fused reproject + gather + blend), with the light field already
 resident in HBM.
 
-Prints ONE JSON line. `value` is eye-view Mpix/s of the compact-storage path
-(FP16 images, FP16 geometry, FP32 arithmetic); the plain FP32 path (FP32
-images and geometry) is timed beside it.
+Prints ONE JSON line. `value` is eye-view Mpix/s of the FP16/batched path
+(FP16 images and geometry, FP32 arithmetic, 16 stereo frames per persistent
+graph-captured launch); the plain FP32 path (FP32 images and geometry, one
+launch sequence per stereo frame) is timed beside it, as are a mixed-size
+batch (64 stereo poses at 1080x1200 / 1440x1600 / 2160x2160 per eye, autotuned
+tile shape and staging cap) and the FP64 oracle on the host cores.
 """
 from __future__ import annotations
 
@@ -136,14 +139,110 @@ def cpu_baseline(lf, torch, views, head_pos, head_rot, ctx_plain, seconds):
     }
 
 
+def time_batched(lf, torch, ctx, w, steps, warmup, per_batch, profile=False):
+    """Stereo frames rendered per_batch at a time with lf_render_batch."""
+    P = len(w.head_pos)
+    nb = max(1, steps // per_batch)
+    res = np.array([[EYE_W, EYE_H]] * (2 * per_batch), np.int32)
+    batches = []
+    for b in range(max(nb, 1)):
+        eyes = []
+        for k in range(per_batch):
+            q = (b * per_batch + k) % P
+            eyes.extend(lf.lf_stereo_eyes(w.head_pos[q], w.head_rot[q], IPD))
+        batches.append(lf.make_eyes([(np.array(e.pos), np.array(e.rot)) for e in eyes]))
+    npx = 2 * per_batch * EYE_W * EYE_H
+    out = torch.empty(npx * 3, dtype=torch.float32, device="cuda")
+    if profile:
+        lf.lf_profile(ctx, True)  # graph captured with timing nodes from the start
+        lf.lf_profile(ctx, False)
+        lf.lf_profile(ctx, True)
+    for k in range(max(1, warmup // per_batch)):
+        lf.lf_render_batch(ctx, batches[k % nb], HFOV, res, out)
+    torch.cuda.synchronize()
+    if profile:
+        lf.lf_profile_read(ctx)  # drop warm-up timings
+        lf.lf_profile(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(nb):
+        lf.lf_render_batch(ctx, batches[b], HFOV, res, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = lf.lf_profile_read(ctx) if profile else None
+    if profile:
+        lf.lf_profile(ctx, False)
+    frames = nb * per_batch
+    return {
+        "mpix_s": npx * nb / (t1 - t0) / 1e6,
+        "ms_per_stereo_frame": 1e3 * (t1 - t0) / frames,
+        "frames": frames,
+        "frames_per_launch": per_batch,
+        "prof": prof,
+    }
+
+
+MIXED_SIZES = [(1080, 1200), (1440, 1600), (2160, 2160)]
+
+
+def mixed_batch(lf, torch, ctx, seed, n_poses=64, reps=10):
+    """64 stereo poses of uneven per-eye sizes in one persistent launch."""
+    import lfsynth
+    rng = np.random.default_rng(seed)
+    eyes_b, res = [], []
+    p, R = lfsynth.poses(seed, n_poses * reps, 0.25)
+    sizes = [MIXED_SIZES[rng.integers(0, 3)] for _ in range(n_poses)]
+    for r in range(reps):
+        eyes = []
+        for k in range(n_poses):
+            eyes.extend(lf.lf_stereo_eyes(p[r * n_poses + k], R[r * n_poses + k], IPD))
+        eyes_b.append(lf.make_eyes([(np.array(e.pos), np.array(e.rot)) for e in eyes]))
+    for k in range(n_poses):
+        res += [sizes[k], sizes[k]]
+    res = np.array(res, np.int32)
+    npx = int((res[:, 0].astype(np.int64) * res[:, 1]).sum())
+    out = torch.empty(npx * 3, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    best, table = lf.lf_autotune_batch(ctx, eyes_b[0], HFOV, res, out, reps=5)
+    tune_s = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    spans = []
+    lf.lf_render_batch(ctx, eyes_b[0], HFOV, res, out)
+    torch.cuda.synchronize()
+    for r in range(reps):
+        ev[r][0].record()
+        lf.lf_render_batch(ctx, eyes_b[r], HFOV, res, out)
+        ev[r][1].record()
+        t = lf.lf_batch_frame_times(ctx, 2 * n_poses)
+        for k in range(n_poses):
+            spans.append(max(t[2 * k + 1, 1], t[2 * k, 1]) - min(t[2 * k, 0], t[2 * k + 1, 0]))
+    batch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    spans = np.array(spans) / 1e3
+    return {
+        "poses": n_poses,
+        "pixels_per_batch": npx,
+        "eye_sizes": {f"{w}x{h}": int(sum(1 for s in sizes if s == (w, h))) for w, h in MIXED_SIZES},
+        "tune": {"tile": f"{best[0]}x{best[1]}", "cap": best[2], "seconds": tune_s,
+                 "median_ms": {f"{a}x{b}/{c}": v for (a, b, c), v in table.items()}},
+        "batch_ms_median": float(np.median(batch_ms)),
+        "mpix_s": npx / (np.median(batch_ms) * 1e-3) / 1e6,
+        "frame_span_ms_p50": float(np.percentile(spans, 50)),
+        "frame_span_ms_p99": float(np.percentile(spans, 99)),
+        "note": "frame span = device wall-clock from the first tile start to the last tile end of the pose's two "
+                "eyes inside the persistent launch",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000, help="stereo frames timed per variant")
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--per-batch", type=int, default=16, help="stereo frames per batched launch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="plain,fp16,rgba8")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
+    ap.add_argument("--variants", default="plain,fp16,rgba8,fp16_batched")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
@@ -176,17 +275,27 @@ def main():
         f"in {time.perf_counter() - t0:.1f} s")
     eyes_all = [lf.lf_stereo_eyes(w.head_pos[k], w.head_rot[k], IPD) for k in range(len(w.head_pos))]
 
-    variants = {"plain": ("rgba32f", "f32"), "fp16": ("rgba16f", "f16"), "rgba8": ("rgba8", "f16")}
+    storage = {"plain": ("rgba32f", "f32"), "fp16": ("rgba16f", "f16"), "rgba8": ("rgba8", "f16"),
+               "fp16_batched": ("rgba16f", "f16")}
     chosen = [v for v in args.variants.split(",") if v]
-    results, ctx_plain = {}, None
+    main_name = "fp16_batched" if "fp16_batched" in chosen else chosen[0]
+    results, ctxs = {}, {}
+    mixed = None
     for name in chosen:
-        img, geo = variants[name]
-        t0 = time.perf_counter()
-        ctx = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
-                               img_fmt=img, geo_fmt=geo)
-        log(f"[bench] {name}: loaded ({img}, {geo}) in {time.perf_counter() - t0:.1f} s")
-        r = time_variant(lf, torch, ctx, eyes_all, args.steps, args.warmup, profile=(name == "fp16"))
-        if name == "fp16":
+        img, geo = storage[name]
+        if (img, geo) not in ctxs:
+            t0 = time.perf_counter()
+            ctxs[(img, geo)] = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
+                                                img_fmt=img, geo_fmt=geo)
+            log(f"[bench] loaded ({img}, {geo}) in {time.perf_counter() - t0:.1f} s")
+        ctx = ctxs[(img, geo)]
+        prof = name == main_name
+        if name.endswith("_batched"):
+            r = time_batched(lf, torch, ctx, w, args.steps, args.warmup, args.per_batch, profile=prof)
+        else:
+            r = time_variant(lf, torch, ctx, eyes_all, args.steps, args.warmup, profile=prof)
+            del r["out"]
+        if prof:
             # work counters of the same frames (outside the timed region)
             acc = {k: 0 for k in lf.STAT_NAMES}
             n_stat = min(64, len(eyes_all))
@@ -195,23 +304,22 @@ def main():
                 for kk in acc:
                     acc[kk] += s[kk]
             r["stats_per_frame"] = {k: v / n_stat for k, v in acc.items()}
-        del r["out"]
         results[name] = r
-        log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.3f} ms/stereo frame "
-            f"(p50 {r['p50_ms']:.3f}, p99 {r['p99_ms']:.3f})")
-        if name == "plain" and not args.no_cpu_baseline:
-            ctx_plain = ctx
-        else:
-            ctx.close()
-        torch.cuda.empty_cache()
+        log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.4f} ms/stereo frame")
+    if not args.no_mixed and ("rgba16f", "f16") in ctxs:
+        log("[bench] mixed-size batch ...")
+        mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f16")], seed=4242)
+        log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']}/{mixed['tune']['cap']}, "
+            f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
-    main_name = "fp16" if "fp16" in results else chosen[0]
     m = results[main_name]
     roofline = None
     if m.get("prof") and m.get("stats_per_frame"):
         p, st = m["prof"], m["stats_per_frame"]
-        render_ms = p["render_ms"] / max(p["render_n"], 1)   # one k_render launch per stereo frame
-        flops = sum(FLOPS_PER[k] * st[k] for k in FLOPS_PER)
+        per_launch = m.get("frames_per_launch", 1)
+        render_ms = p["render_ms"] / max(p["render_n"], 1)
+        work = {k: v * per_launch for k, v in st.items()}
+        flops = sum(FLOPS_PER[k] * work[k] for k in FLOPS_PER)
         achieved = flops / (render_ms * 1e-3) / 1e12
         traffic = load_traffic(args.traffic, main_name)
         roofline = {
@@ -221,20 +329,20 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_render",
+            "kernel": "k_render_persistent" if main_name.endswith("_batched") else "k_render",
             "kernel_ms": render_ms,
+            "stereo_frames_per_launch": per_launch,
             "algorithmic_flop_per_launch": flops,
-            "work_per_launch": st,
-            "cull_ms": p["cull_ms"] / max(p["cull_n"], 1),
-            "prep_ms": p["prep_ms"] / max(p["prep_n"], 1),
-            "output_write_gbs": (2 * EYE_W * EYE_H * 12) / (render_ms * 1e-3) / 1e9,
+            "work_per_launch": work,
+            "output_write_gbs": (per_launch * 2 * EYE_W * EYE_H * 12) / (render_ms * 1e-3) / 1e9,
         }
 
     cpu = None
-    if ctx_plain is not None:
+    if not args.no_cpu_baseline and ("rgba32f", "f32") in ctxs:
         log("[bench] cpu baseline (FP64 oracle) ...")
-        cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctx_plain, args.cpu_seconds)
-        ctx_plain.close()
+        cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctxs[("rgba32f", "f32")], args.cpu_seconds)
+    for c in ctxs.values():
+        c.close()
 
     line = {
         "metric": METRIC,
@@ -253,16 +361,14 @@ def main():
             "workload": "stereo 2x1440x1600 eye views at 100 deg from 1024 views of 1024^2 RGBA8 with 256^2 "
                         "depth meshes, 12 spheres + box, 3000 seeded head poses",
             "path": main_name,
-            "storage": dict(zip(("images", "geometry"), variants[main_name])),
-            "tile": "16x16",
-            "cap": 32,
+            "storage": dict(zip(("images", "geometry"), storage[main_name])),
+            "stereo_frames_per_launch": m.get("frames_per_launch", 1),
         },
         "ms_per_stereo_frame": m["ms_per_stereo_frame"],
-        "p50_ms": m["p50_ms"],
-        "p99_ms": m["p99_ms"],
-        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms")}
+        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms") if kk in v}
                      for k, v in results.items()},
         "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
+        "mixed_batch": mixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

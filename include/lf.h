@@ -146,6 +146,38 @@ int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W
                         int32_t *out_cand, int32_t *out_contrib, int32_t *out_ncand, void *hip_stream);
 
 /*
+ * Batched render: the same images as lf_render for n_eyes eyes of any sizes,
+ * produced by ONE persistent launch in which every workgroup takes screen
+ * tiles of all eyes from a global queue. The launch sequence (queue reset,
+ * per-eye set-up, culling, persistent render) is captured once in a HIP graph
+ * per batch shape (eye count, sizes, FOV, output buffers, tune) and replayed;
+ * each call uploads only the eye poses. tune NULL = the context's tune (the
+ * autotuned one after lf_autotune_batch, else 16x16 tiles, cap 32).
+ * Output layout as lf_render. Per-eye start / end stamps of the last batch are
+ * read with lf_batch_frame_times.
+ */
+int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    float *out_rgb, float *out_wsum, uint8_t *out_count, const lf_tune *tune, void *hip_stream);
+
+/*
+ * Autotuner of the batched path: times lf_render_batch on the given batch for
+ * tiles {8x8, 16x16, 32x8} x cap {8, 16, 32} (median of reps runs each, after
+ * a capture and warm-up run), stores the fastest in the context and returns it
+ * in *best (may be NULL); ms[9] (may be NULL) receives the medians in the order
+ * shape-major, cap-minor. Synchronous.
+ */
+int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                      float *out_rgb, int32_t reps, lf_tune *best, float *ms, void *hip_stream);
+
+/*
+ * Device wall-clock stamps of the last batch: out_us[2k] / out_us[2k+1] are the
+ * start of eye k's first tile and the end of its last tile, in microseconds
+ * from the batch's first stamp. Synchronises the device. LF_ESTATE if the last
+ * batch did not have n_eyes eyes.
+ */
+int lf_batch_frame_times(lf_ctx *c, double *out_us, int32_t n_eyes);
+
+/*
  * Count the work one lf_render call with the same arguments performs (it runs
  * the same decisions without writing an image): counters[0] pixels,
  * [1] per-ray disk tests, [2] candidate (ray, view) pairs with rho > 0,
@@ -160,7 +192,9 @@ int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
  * every kernel the context launches with HIP events on the launch stream;
  * lf_profile(c, 0) stops. lf_profile_read waits for the recorded events and
  * returns the accumulated milliseconds of the set-up, cull and render kernels
- * in out[0..2] and their launch counts in out[3..5].
+ * in out[0..2] and their launch counts in out[3..5]. For lf_render_batch the
+ * render entry is the persistent render kernel inside the batch graph (event
+ * nodes around it, retargeted at every replay).
  */
 int lf_profile(lf_ctx *c, int32_t enable);
 int lf_profile_read(lf_ctx *c, double out[6]);

@@ -78,6 +78,27 @@ struct lf_ctx {
     std::vector<Timed> timed;
     double prof_ms[3] = {0, 0, 0};
     double prof_n[3] = {0, 0, 0};
+    // batched path: one persistent launch per batch, captured in a HIP graph
+    struct Batch {
+        hipStream_t cap_stream = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::string key;
+        EyeParam *eyes_dev = nullptr;
+        EyeParam *eyes_host = nullptr;  // pinned staging of the eye table
+        int32_t eyes_cap = 0;
+        hipEvent_t copied = nullptr;    // recorded after the last eye-table upload
+        void *buf = nullptr;
+        size_t buf_bytes = 0;
+        unsigned long long *frame_t = nullptr;
+        int32_t n_eyes = 0;
+        // with profiling on, the graph holds event-record nodes around the
+        // persistent render kernel; each replay points them at fresh events
+        hipEvent_t ph_a = nullptr, ph_b = nullptr;
+        hipGraphNode_t node_a = nullptr, node_b = nullptr;
+        lf_tune tune{16, 16, 32};
+        bool tuned = false;
+    } batch;
 };
 
 namespace {
@@ -144,7 +165,7 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
     ch.tile_w = tw;
     ch.tile_h = th;
     const double tx = std::tan(0.5 * hfov_deg * M_PI / 180.0);
-    int32_t tiles = 0;
+    int32_t tiles = 0, supers = 0;
     for (int32_t k = 0; k < n; ++k) {
         EyeParam &E = ch.e[k];
         std::memcpy(E.pos, eyes[k].pos, sizeof E.pos);
@@ -156,11 +177,16 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
         E.tiles_x = (E.W + tw - 1) / tw;
         E.tiles_y = (E.H + th - 1) / th;
         E.tile_off = tiles;
+        E.supers_x = (E.tiles_x + kSuper - 1) / kSuper;
+        E.supers_y = (E.tiles_y + kSuper - 1) / kSuper;
+        E.super_off = supers;
         E.pix_off = pix_off;
         tiles += E.tiles_x * E.tiles_y;
+        supers += E.supers_x * E.supers_y;
         pix_off += (int64_t)E.W * E.H;
     }
     ch.total_tiles = tiles;
+    ch.total_supers = supers;
 }
 
 RenderArgs base_args(const lf_ctx *c, double R) {
@@ -448,6 +474,245 @@ int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W
     return LF_OK;
 }
 
+static void batch_release_graph(lf_ctx *c) {
+    if (c->batch.exec) (void)hipGraphExecDestroy(c->batch.exec);
+    if (c->batch.graph) (void)hipGraphDestroy(c->batch.graph);
+    c->batch.exec = nullptr;
+    c->batch.graph = nullptr;
+    c->batch.key.clear();
+}
+
+int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    float *out_rgb, float *out_wsum, uint8_t *out_count, const lf_tune *tune, void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_rgb) return fail(LF_EINVAL, "out_rgb must not be NULL");
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    const lf_tune t = tune ? *tune : c->batch.tune;
+    if (t.tile_w <= 0 || t.tile_h <= 0 || t.tile_w % 8 || t.tile_h % 8 || t.tile_w * t.tile_h > 256 || t.cap < 1 ||
+        t.cap > kStage)
+        return fail(LF_EINVAL, "invalid tune %dx%d cap %d", t.tile_w, t.tile_h, t.cap);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lf_ctx::Batch &B = c->batch;
+
+    // eye table (host side), with tile and super-tile offsets for this tile shape
+    std::vector<EyeParam> ep(n_eyes);
+    int32_t tiles = 0, supers = 0;
+    {
+        EyeChunk ch;
+        int64_t pix_off = 0;
+        for (int32_t k0 = 0; k0 < n_eyes; k0 += kMaxEyesPerLaunch) {
+            const int32_t nk = std::min(kMaxEyesPerLaunch, n_eyes - k0);
+            fill_chunk(c, ch, eyes + k0, nk, hfov_deg, res + 2 * k0, pix_off, t.tile_w, t.tile_h);
+            for (int32_t k = 0; k < nk; ++k) {
+                ep[k0 + k] = ch.e[k];
+                ep[k0 + k].tile_off += tiles;
+                ep[k0 + k].super_off += supers;
+                pix_off += (int64_t)ch.e[k].W * ch.e[k].H;
+            }
+            tiles += ch.total_tiles;
+            supers += ch.total_supers;
+        }
+    }
+    // device buffers: eye table, eye-view records, tile lists, counts, queue, stamps
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t ev_b = al(sizeof(EyeView) * (size_t)n_eyes * c->n);
+    const size_t tl_b = al(sizeof(uint16_t) * (size_t)kListCap * tiles);
+    const size_t tc_b = al(sizeof(int32_t) * (size_t)tiles);
+    const size_t q_b = 256, ft_b = al(sizeof(unsigned long long) * 2 * (size_t)n_eyes);
+    const size_t need = ev_b + tl_b + tc_b + q_b + ft_b;
+    if (need > B.buf_bytes || n_eyes > B.eyes_cap) {
+        if (B.copied) LF_HIP(hipEventSynchronize(B.copied), "hipEventSynchronize");
+        LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        batch_release_graph(c);
+        if (need > B.buf_bytes) {
+            if (B.buf) LF_HIP(hipFree(B.buf), "hipFree");
+            B.buf = nullptr;
+            B.buf_bytes = 0;
+            LF_HIP(hipMalloc(&B.buf, need), "hipMalloc(batch buffers)");
+            B.buf_bytes = need;
+        }
+        if (n_eyes > B.eyes_cap) {
+            if (B.eyes_dev) LF_HIP(hipFree(B.eyes_dev), "hipFree");
+            if (B.eyes_host) LF_HIP(hipHostFree(B.eyes_host), "hipHostFree");
+            B.eyes_dev = nullptr;
+            B.eyes_host = nullptr;
+            B.eyes_cap = 0;
+            LF_HIP(hipMalloc(&B.eyes_dev, sizeof(EyeParam) * n_eyes), "hipMalloc(eye table)");
+            LF_HIP(hipHostMalloc((void **)&B.eyes_host, sizeof(EyeParam) * n_eyes, hipHostMallocDefault),
+                   "hipHostMalloc(eye table)");
+            B.eyes_cap = n_eyes;
+        }
+    }
+    char *p = (char *)B.buf;
+    RenderArgs a = base_args(c, c->R);
+    a.ev = (const EyeView *)p;
+    a.tile_list = (const uint16_t *)(p + ev_b);
+    a.tile_count = (const int32_t *)(p + ev_b + tl_b);
+    a.out_rgb = out_rgb;
+    a.out_wsum = out_wsum;
+    a.out_count = out_count;
+    a.cap = t.cap;
+    BatchArgs b;
+    b.eyes = B.eyes_dev;
+    b.n_eyes = n_eyes;
+    b.total_tiles = tiles;
+    b.total_supers = supers;
+    b.tile_w = t.tile_w;
+    b.tile_h = t.tile_h;
+    b.queue = (unsigned int *)(p + ev_b + tl_b + tc_b);
+    b.frame_t = (unsigned long long *)(p + ev_b + tl_b + tc_b + q_b);
+    B.frame_t = b.frame_t;
+    B.n_eyes = n_eyes;
+
+    // the graph depends on the batch shape and buffers, not on the eye poses
+    std::string key;
+    {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%d|%.17g|%p|%p|%p|%p|%d|%d|%d|%d|", n_eyes, hfov_deg, (void *)out_rgb,
+                 (void *)out_wsum, (void *)out_count, B.buf, t.tile_w, t.tile_h, t.cap, c->profiling ? 1 : 0);
+        key = buf;
+        for (int32_t k = 0; k < n_eyes; ++k) key += std::to_string(res[2 * k]) + "x" + std::to_string(res[2 * k + 1]) + ",";
+    }
+    if (key != B.key) {
+        batch_release_graph(c);
+        if (!B.cap_stream) LF_HIP(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+        int per_cu = 0, n_cu = 0;
+        LF_HIP(persistent_occupancy(c->img_fmt, c->geo_fmt, t.tile_w * t.tile_h, &per_cu), "occupancy");
+        LF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
+        const int grid = std::max(1, std::min(per_cu * n_cu, tiles));
+        const float R_keep = (float)(c->R * (1.0 + 1e-4) + 1e-7);
+        if (c->profiling && !B.ph_a) {
+            LF_HIP(hipEventCreate(&B.ph_a), "hipEventCreate");
+            LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
+        }
+        LF_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, R_keep, c->img_fmt, c->geo_fmt, grid, B.cap_stream,
+                                    nullptr, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(B.cap_stream, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(e, "batch launch capture");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        B.graph = g;
+        B.node_a = B.node_b = nullptr;
+        if (c->profiling) {
+            // the capture is a chain ending in the persistent render kernel:
+            // put an event-record node right before it and one right after it
+            size_t nn = 0;
+            LF_HIP(hipGraphGetNodes(g, nullptr, &nn), "hipGraphGetNodes");
+            std::vector<hipGraphNode_t> nodes(nn);
+            LF_HIP(hipGraphGetNodes(g, nodes.data(), &nn), "hipGraphGetNodes");
+            hipGraphNode_t leaf = nullptr;
+            for (auto nd : nodes) {
+                size_t nd_out = 0;
+                LF_HIP(hipGraphNodeGetDependentNodes(nd, nullptr, &nd_out), "hipGraphNodeGetDependentNodes");
+                if (nd_out == 0) leaf = nd;
+            }
+            if (!leaf) return fail(LF_EHIP, "batch graph has no final node");
+            size_t nd_in = 0;
+            LF_HIP(hipGraphNodeGetDependencies(leaf, nullptr, &nd_in), "hipGraphNodeGetDependencies");
+            std::vector<hipGraphNode_t> deps(nd_in);
+            if (nd_in) LF_HIP(hipGraphNodeGetDependencies(leaf, deps.data(), &nd_in), "hipGraphNodeGetDependencies");
+            LF_HIP(hipGraphAddEventRecordNode(&B.node_a, g, deps.data(), nd_in, B.ph_a), "add event node");
+            for (auto d : deps) LF_HIP(hipGraphRemoveDependencies(g, &d, &leaf, 1), "hipGraphRemoveDependencies");
+            LF_HIP(hipGraphAddDependencies(g, &B.node_a, &leaf, 1), "hipGraphAddDependencies");
+            LF_HIP(hipGraphAddEventRecordNode(&B.node_b, g, &leaf, 1, B.ph_b), "add event node");
+        }
+        LF_HIP(hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        B.key = key;
+    }
+    // upload this batch's eye table through pinned staging, then replay the graph
+    if (B.copied) LF_HIP(hipEventSynchronize(B.copied), "hipEventSynchronize");
+    else LF_HIP(hipEventCreateWithFlags(&B.copied, hipEventDisableTiming), "hipEventCreate");
+    std::memcpy(B.eyes_host, ep.data(), sizeof(EyeParam) * n_eyes);
+    LF_HIP(hipMemcpyAsync(B.eyes_dev, B.eyes_host, sizeof(EyeParam) * n_eyes, hipMemcpyHostToDevice, s),
+           "upload eye table");
+    LF_HIP(hipEventRecord(B.copied, s), "hipEventRecord");
+    if (c->profiling) {
+        lf_ctx::Timed tm{2, nullptr, nullptr};
+        LF_HIP(hipEventCreate(&tm.a), "hipEventCreate");
+        LF_HIP(hipEventCreate(&tm.b), "hipEventCreate");
+        c->timed.push_back(tm);
+        LF_HIP(hipGraphExecEventRecordNodeSetEvent(B.exec, B.node_a, tm.a), "set event node");
+        LF_HIP(hipGraphExecEventRecordNodeSetEvent(B.exec, B.node_b, tm.b), "set event node");
+    }
+    LF_HIP(hipGraphLaunch(B.exec, s), "hipGraphLaunch");
+    return LF_OK;
+}
+
+int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                      float *out_rgb, int32_t reps, lf_tune *best, float *ms, void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (reps < 1 || reps > 100) return fail(LF_EINVAL, "reps must be in [1,100]");
+    static const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
+    static const int caps[3] = {8, 16, 32};
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t ea, eb;
+    LF_HIP(hipEventCreate(&ea), "hipEventCreate");
+    LF_HIP(hipEventCreate(&eb), "hipEventCreate");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    float best_ms = INFINITY;
+    lf_tune bt = c->batch.tune;
+    int rc = LF_OK;
+    for (int i = 0; i < 9 && rc == LF_OK; ++i) {
+        lf_tune t{shapes[i / 3][0], shapes[i / 3][1], caps[i % 3]};
+        rc = lf_render_batch(c, eyes, n_eyes, hfov_deg, res, out_rgb, nullptr, nullptr, &t, hip_stream);  // capture + warm
+        std::vector<float> times;
+        for (int r = 0; r < reps && rc == LF_OK; ++r) {
+            hipError_t e = hipEventRecord(ea, s);
+            if (e == hipSuccess) rc = lf_render_batch(c, eyes, n_eyes, hfov_deg, res, out_rgb, nullptr, nullptr, &t,
+                                                      hip_stream);
+            if (e == hipSuccess && rc == LF_OK) e = hipEventRecord(eb, s);
+            if (e == hipSuccess && rc == LF_OK) e = hipEventSynchronize(eb);
+            float m = 0.0f;
+            if (e == hipSuccess && rc == LF_OK) e = hipEventElapsedTime(&m, ea, eb);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+            times.push_back(m);
+        }
+        if (rc != LF_OK) break;
+        std::sort(times.begin(), times.end());
+        const float med = times[times.size() / 2];
+        if (ms) ms[i] = med;
+        if (med < best_ms) {
+            best_ms = med;
+            bt = t;
+        }
+    }
+    c->profiling = prof;
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (rc != LF_OK) return rc;
+    c->batch.tune = bt;
+    c->batch.tuned = true;
+    if (best) *best = bt;
+    return LF_OK;
+}
+
+int lf_batch_frame_times(lf_ctx *c, double *out_us, int32_t n_eyes) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_us) return fail(LF_EINVAL, "out_us must not be NULL");
+    if (!c->batch.frame_t || n_eyes != c->batch.n_eyes)
+        return fail(LF_ESTATE, "no batch of %d eyes has been rendered", n_eyes);
+    std::vector<unsigned long long> h(2 * (size_t)n_eyes);
+    LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    LF_HIP(hipMemcpy(h.data(), c->batch.frame_t, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
+           "read frame stamps");
+    int khz = 0;
+    LF_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device), "wall clock rate");
+    if (khz <= 0) return fail(LF_EHIP, "device reports no wall clock rate");
+    unsigned long long t0 = ~0ull;
+    for (int32_t k = 0; k < n_eyes; ++k) t0 = std::min(t0, h[2 * k]);
+    for (int32_t k = 0; k < n_eyes; ++k) {
+        out_us[2 * k] = (double)(h[2 * k] - t0) * 1e3 / khz;
+        out_us[2 * k + 1] = (double)(h[2 * k + 1] - t0) * 1e3 / khz;
+    }
+    return LF_OK;
+}
+
 int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
                     uint64_t counters[5], void *hip_stream) {
     if (!c) return fail(LF_EINVAL, "NULL context");
@@ -528,6 +793,14 @@ void lf_free(lf_ctx *c) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
+    batch_release_graph(c);
+    if (c->batch.copied) (void)hipEventDestroy(c->batch.copied);
+    if (c->batch.ph_a) (void)hipEventDestroy(c->batch.ph_a);
+    if (c->batch.ph_b) (void)hipEventDestroy(c->batch.ph_b);
+    if (c->batch.cap_stream) (void)hipStreamDestroy(c->batch.cap_stream);
+    if (c->batch.buf) (void)hipFree(c->batch.buf);
+    if (c->batch.eyes_dev) (void)hipFree(c->batch.eyes_dev);
+    if (c->batch.eyes_host) (void)hipHostFree(c->batch.eyes_host);
     delete c;
 }
 

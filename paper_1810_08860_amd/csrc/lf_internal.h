@@ -11,6 +11,9 @@ constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel argume
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
 constexpr int kStage = 64;             // candidate views staged in LDS per pass (upper bound of tune.cap)
 constexpr int kBlk = 8;                // mesh cells per side of an inverse-depth bounds block
+constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
+constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
+constexpr int kSuperCap = 256;         // super-tile survivor list capacity (exact beyond: every view)
 
 inline int num_blocks(int M) { return (M - 1 + kBlk - 1) / kBlk; }
 
@@ -22,13 +25,16 @@ struct EyeParam {
     int32_t W, H;
     int32_t tiles_x, tiles_y;
     int32_t tile_off;  // first tile of this eye within the launch
-    int32_t pad;
+    int32_t supers_x, supers_y;
+    int32_t super_off; // first culling super-tile of this eye within the launch
     int64_t pix_off;   // first output pixel of this eye
 };
 
 struct EyeChunk {
     int32_t n_eyes;
     int32_t total_tiles;
+    int32_t total_supers;
+    int32_t pad;
     int32_t tile_w, tile_h;
     EyeParam e[kMaxEyesPerLaunch];
 };
@@ -41,6 +47,16 @@ struct alignas(16) EyeView {
     float wmin, wmax;  // inverse-depth range of the view's mesh
     int32_t view;
     int32_t pad;
+};
+
+// A batch: eye table in device memory (sorted by tile_off / super_off), a
+// global tile queue and per-eye wall-clock stamps.
+struct BatchArgs {
+    const EyeParam *eyes;
+    int32_t n_eyes, total_tiles, total_supers;
+    int32_t tile_w, tile_h;
+    unsigned int *queue;
+    unsigned long long *frame_t;  // [n_eyes][2]: earliest tile start, latest tile end
 };
 
 enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3 };
@@ -85,5 +101,11 @@ hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R
                        int32_t *tile_count, hipStream_t s);
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
                          hipStream_t s);
+// reset + prep + cull + persistent render of a batch (a.ev / tile lists are the batch's buffers)
+// ev_a / ev_b (may be null) are recorded just before / after the persistent render kernel
+hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
+                        float R_keep, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
+                        hipEvent_t ev_b);
+hipError_t persistent_occupancy(int img_fmt, int geo_fmt, int block, int *per_cu);
 
 }  // namespace lf

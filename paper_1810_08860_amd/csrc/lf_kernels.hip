@@ -36,6 +36,15 @@
 
 namespace lf {
 
+// Work-group index -> work item, XCD-aware. Consecutive work-group ids are
+// dispatched round-robin over the 8 XCDs, each with its own L2; give XCD x
+// one contiguous range of items so neighbouring screen tiles (which read the
+// same source views) share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G / kXcds, r = G % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
+}
+
 __device__ __forceinline__ int find_eye(const EyeChunk &ch, int tile) {
     int e = 0;
     while (e + 1 < ch.n_eyes && tile >= ch.e[e + 1].tile_off) ++e;
@@ -138,14 +147,10 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
 }
 
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
-__global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
-                                              const float2 *__restrict__ wr, int32_t n, EyeView *__restrict__ ev) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    const int e = blockIdx.y;
-    if (v >= n || e >= ch.n_eyes) return;
+__device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__restrict__ vt,
+                                            const float2 *__restrict__ wr, int v) {
     const double *c = vt + 12 * (int64_t)v;
     const double *R = c + 3;
-    const EyeParam &E = ch.e[e];
     EyeView out;
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b) {
@@ -162,7 +167,15 @@ __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *_
     out.wmax = w.y;
     out.view = v;
     out.pad = 0;
-    ev[(int64_t)e * n + v] = out;
+    return out;
+}
+
+__global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
+                                              const float2 *__restrict__ wr, int32_t n, EyeView *__restrict__ ev) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.y;
+    if (v >= n || e >= ch.n_eyes) return;
+    ev[(int64_t)e * n + v] = eye_view(ch.e[e], vt, wr, v);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -232,57 +245,146 @@ __device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, f
     return allp || alln || best <= R * R;
 }
 
+__device__ __forceinline__ int find_eye_super(const EyeChunk &ch, int super) {
+    int e = 0;
+    while (e + 1 < ch.n_eyes && super >= ch.e[e + 1].super_off) ++e;
+    return e;
+}
+
+// Culling of one super-tile of kSuper x kSuper screen tiles by one workgroup.
+// Phase 1 tests every view against the super-tile's frustum and compacts the
+// survivors, in ascending view order, into LDS (per-wave ballot + prefix
+// popcount, with a cross-wave prefix of the four wave counts). Phase 2: each
+// wavefront takes tiles of the super-tile and tests only the survivors against
+// each tile, compacting that tile's list the same way. Lists stay ascending,
+// so every pixel later blends its views in the same order whatever the tile
+// shape.
+struct CullSmem {
+    uint16_t slist[kSuperCap];
+    uint16_t tlst[4][kListCap];
+    int wcnt[4];
+};
+
+__device__ __forceinline__ void cull_super(const EyeParam &E, int local, int tile_w, int tile_h,
+                                           const EyeView *__restrict__ eve, int32_t n, float R_keep,
+                                           uint16_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
+                                           CullSmem &sm) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int tx0 = (local % E.supers_x) * kSuper, ty0 = (local / E.supers_x) * kSuper;
+    const int tx1 = min(tx0 + kSuper, E.tiles_x), ty1 = min(ty0 + kSuper, E.tiles_y);
+    const float sxp = 2.0f * E.tx / E.W, syp = 2.0f * E.ty / E.H;
+
+    // phase 1: all views against the super-tile
+    {
+        const int x0 = tx0 * tile_w, x1 = min(tx1 * tile_w, E.W);
+        const int y0 = ty0 * tile_h, y1 = min(ty1 * tile_h, E.H);
+        const float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
+        const float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
+        int scount = 0;
+        for (int base = 0; base < n; base += 256) {
+            const int v = base + (int)threadIdx.x;
+            const bool keep = v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1, R_keep);
+            const uint64_t mask = __ballot(keep);
+            if (lane == 0) sm.wcnt[wave] = __popcll(mask);
+            __syncthreads();
+            int off = scount;
+            for (int w = 0; w < wave; ++w) off += sm.wcnt[w];
+            if (keep) {
+                const int slot = off + __popcll(mask & below);
+                if (slot < kSuperCap) sm.slist[slot] = (uint16_t)v;
+            }
+            scount += sm.wcnt[0] + sm.wcnt[1] + sm.wcnt[2] + sm.wcnt[3];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sm.wcnt[0] = scount;
+        __syncthreads();
+    }
+    const int scount = sm.wcnt[0];
+    __syncthreads();
+    const bool sover = scount > kSuperCap;
+    const int ns = sover ? n : scount;
+
+    // phase 2: each wavefront tests the survivors against its tiles
+    for (int t = wave; t < kSuper * kSuper; t += 4) {
+        const int tx = tx0 + t % kSuper, ty = ty0 + t / kSuper;
+        const bool active = tx < tx1 && ty < ty1;
+        int count = 0;
+        if (active) {
+            const int x0 = tx * tile_w, x1 = min(x0 + tile_w, E.W);
+            const int y0 = ty * tile_h, y1 = min(y0 + tile_h, E.H);
+            const float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
+            const float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
+            for (int b = 0; b < ns; b += 64) {
+                const int s = b + lane;
+                const int v = s < ns ? (sover ? s : (int)sm.slist[s]) : -1;
+                const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1, R_keep);
+                const uint64_t mask = __ballot(keep);
+                if (keep) {
+                    const int slot = count + __popcll(mask & below);
+                    if (slot < kListCap) sm.tlst[wave][slot] = (uint16_t)v;
+                }
+                count += __popcll(mask);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const int tile = E.tile_off + ty * E.tiles_x + tx;
+            const int m = min(count, kListCap);
+            for (int q = lane; q < m; q += 64) tile_list[(int64_t)tile * kListCap + q] = sm.tlst[wave][q];
+            if (lane == 0) tile_count[tile] = count;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const EyeView *__restrict__ ev, int32_t n,
                                               float R_keep, uint16_t *__restrict__ tile_list,
                                               int32_t *__restrict__ tile_count) {
-    __shared__ uint16_t lst[4][kListCap];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wave;
-    const bool active = tile < ch.total_tiles;
-    int count = 0;
-    if (active) {
-        const int e = find_eye(ch, tile);
-        const EyeParam &E = ch.e[e];
-        const int local = tile - E.tile_off;
-        const int x0 = (local % E.tiles_x) * ch.tile_w, y0 = (local / E.tiles_x) * ch.tile_h;
-        const int x1 = min(x0 + ch.tile_w, E.W), y1 = min(y0 + ch.tile_h, E.H);
-        const float X0 = (2.0f * x0 / E.W - 1.0f) * E.tx, X1 = (2.0f * x1 / E.W - 1.0f) * E.tx;
-        const float Y0 = (1.0f - 2.0f * y0 / E.H) * E.ty, Y1 = (1.0f - 2.0f * y1 / E.H) * E.ty;
-        const EyeView *eve = ev + (int64_t)e * n;
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        for (int base = 0; base < n; base += 64) {
-            const int v = base + lane;
-            const bool keep = v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1, R_keep);
-            const uint64_t mask = __ballot(keep);
-            if (keep) {
-                const int slot = count + __popcll(mask & below);
-                if (slot < kListCap) lst[wave][slot] = (uint16_t)v;
-            }
-            count += __popcll(mask);
-        }
+    __shared__ CullSmem sm;
+    const int super = blockIdx.x;
+    const int e = find_eye_super(ch, super);
+    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, R_keep, tile_list,
+               tile_count, sm);
+}
+
+// Eye whose range [off(e), off(e+1)) holds item t, for a device eye table
+// sorted by offset (binary search; uniform across the workgroup).
+__device__ __forceinline__ int find_eye_sorted(const EyeParam *__restrict__ eyes, int n_eyes, int t, bool super) {
+    int lo = 0, hi = n_eyes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int off = super ? eyes[mid].super_off : eyes[mid].tile_off;
+        if (off <= t) lo = mid;
+        else hi = mid - 1;
     }
-    __syncthreads();
-    if (active) {
-        const int m = min(count, kListCap);
-        for (int s = lane; s < m; s += 64) tile_list[(int64_t)tile * kListCap + s] = lst[wave][s];
-        if (lane == 0) tile_count[tile] = count;
-    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const EyeView *__restrict__ ev, int32_t n,
+                                                    float R_keep, uint16_t *__restrict__ tile_list,
+                                                    int32_t *__restrict__ tile_count) {
+    __shared__ CullSmem sm;
+    const int super = blockIdx.x;
+    const int e = find_eye_sorted(b.eyes, b.n_eyes, super, true);
+    const EyeParam E = b.eyes[e];
+    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, R_keep, tile_list, tile_count,
+               sm);
 }
 
 // ---------------------------------------------------------------------------------------------
 // fused reproject + gather + blend
 
+// One screen tile of eye E (index e) by one workgroup of tile_w x tile_h
+// threads; sv is the workgroup's LDS staging area for candidate views.
 template <int IMG, int GEO, int MODE>
-__global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderArgs a) {
-    __shared__ EyeView sv[kStage];
-    const int tile = blockIdx.x;
-    const int e = find_eye(ch, tile);
-    const EyeParam &E = ch.e[e];
+__device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, int tile_w, int tile_h,
+                                            const RenderArgs &a, EyeView *sv) {
     const int local = tile - E.tile_off;
-    const int tx0 = (local % E.tiles_x) * ch.tile_w, ty0 = (local / E.tiles_x) * ch.tile_h;
+    const int tx0 = (local % E.tiles_x) * tile_w, ty0 = (local / E.tiles_x) * tile_h;
     // one 8x8 pixel block per wavefront
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int bpr = ch.tile_w >> 3;
+    const int bpr = tile_w >> 3;
     const int px = tx0 + (wave % bpr) * 8 + (lane & 7);
     const int py = ty0 + (wave / bpr) * 8 + (lane >> 3);
     const bool inside = px < E.W && py < E.H;
@@ -359,6 +461,7 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
         }
         __syncthreads();
         if (threadIdx.x < 5) atomicAdd(&a.stats[threadIdx.x], red[threadIdx.x]);
+        __syncthreads();
         return;
     }
     if (!inside) return;
@@ -369,7 +472,7 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
         return;
     }
     // second pass of the paper: divide numerator by denominator
-    const float k = ws > 0.0f ? texel_scale<IMG>() / ws : 0.0f;
+    const float k = ws > 0.0f ? texel_scale<IMG>() * fast_rcp(ws) : 0.0f;
     float r = accr * k, g = accg * k, b = accb * k;
     float *o = a.out_rgb + pix * 3;
     if (MODE == MODE_SUBPIXEL) {
@@ -389,6 +492,75 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
         if (a.out_wsum) a.out_wsum[pix] = ws;
         if (a.out_count) a.out_count[pix] = (uint8_t)min(nh, 255);
     }
+}
+
+template <int IMG, int GEO, int MODE>
+__global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderArgs a) {
+    __shared__ EyeView sv[kStage];
+    const int tile = blockIdx.x;
+    const int e = find_eye(ch, tile);
+    render_tile<IMG, GEO, MODE>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a, sv);
+}
+
+// Persistent form for batches: a grid sized to the machine; each workgroup
+// takes tiles from a global atomic queue (all eyes of the batch, any sizes)
+// until the queue is empty -- every workgroup reaches the exit once the
+// counter passes the last tile. Per eye, the earliest start and latest end
+// wall-clock stamps of its tiles are kept (per-frame latency).
+template <int IMG, int GEO>
+__global__ __launch_bounds__(256) void k_render_persistent(const BatchArgs b, const RenderArgs a) {
+    __shared__ EyeView sv[kStage];
+    __shared__ int s_tile;
+    int cur_e = -1;
+    unsigned long long t0 = 0, t1 = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(b.queue, 1u);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= b.total_tiles) break;
+        const int e = find_eye_sorted(b.eyes, b.n_eyes, tile, false);
+        if (threadIdx.x == 0) {
+            const unsigned long long now = wall_clock64();
+            if (e != cur_e) {
+                if (cur_e >= 0 && b.frame_t) {
+                    atomicMin(&b.frame_t[2 * cur_e], t0);
+                    atomicMax(&b.frame_t[2 * cur_e + 1], t1);
+                }
+                cur_e = e;
+                t0 = now;
+            }
+        }
+        const EyeParam E = b.eyes[e];
+        render_tile<IMG, GEO, MODE_RENDER>(E, e, tile, b.tile_w, b.tile_h, a, sv);
+        if (threadIdx.x == 0) t1 = wall_clock64();
+    }
+    if (threadIdx.x == 0 && cur_e >= 0 && b.frame_t) {
+        atomicMin(&b.frame_t[2 * cur_e], t0);
+        atomicMax(&b.frame_t[2 * cur_e + 1], t1);
+    }
+}
+
+// Start-of-batch reset: empty queue, per-eye stamps at (max, 0). A kernel
+// (not a memset) so the batch graph holds kernels only.
+__global__ void k_batch_reset(unsigned int *queue, unsigned long long *frame_t, int n_eyes) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0u;
+    if (frame_t && i < n_eyes) {
+        frame_t[2 * i] = ~0ull;
+        frame_t[2 * i + 1] = 0ull;
+    }
+}
+
+// Per (eye, view) set-up for a batch whose eye table lives in device memory.
+__global__ __launch_bounds__(256) void k_prep_batch(const BatchArgs b, const double *__restrict__ vt,
+                                                    const float2 *__restrict__ wr, int32_t n,
+                                                    EyeView *__restrict__ ev) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.y;
+    if (v >= n || e >= b.n_eyes) return;
+    const EyeParam E = b.eyes[e];
+    ev[(int64_t)e * n + v] = eye_view(E, vt, wr, v);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -443,8 +615,7 @@ hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, i
 
 hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R_keep, uint16_t *tile_list,
                        int32_t *tile_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_cull, dim3((ch.total_tiles + 3) / 4), dim3(256), 0, s, ch, ev, n, R_keep, tile_list,
-                       tile_count);
+    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, ev, n, R_keep, tile_list, tile_count);
     return hipGetLastError();
 }
 
@@ -462,6 +633,46 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
         else LF_R(2, 1);
     }
 #undef LF_R
+}
+
+hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
+                        float R_keep, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
+                        hipEvent_t ev_b) {
+    hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
+    hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n,
+                       const_cast<EyeView *>(a.ev));
+    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n, R_keep,
+                       const_cast<uint16_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
+    const dim3 block(b.tile_w * b.tile_h);
+    if (ev_a) {
+        hipError_t e = hipEventRecordWithFlags(ev_a, s, hipEventRecordExternal);
+        if (e != hipSuccess) return e;
+    }
+#define LF_P(I, G) hipLaunchKernelGGL((k_render_persistent<I, G>), dim3(grid), block, 0, s, b, a)
+    if (geo_fmt == 0) {
+        if (img_fmt == 0) LF_P(0, 0);
+        else if (img_fmt == 1) LF_P(1, 0);
+        else LF_P(2, 0);
+    } else {
+        if (img_fmt == 0) LF_P(0, 1);
+        else if (img_fmt == 1) LF_P(1, 1);
+        else LF_P(2, 1);
+    }
+#undef LF_P
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ev_b) e = hipEventRecordWithFlags(ev_b, s, hipEventRecordExternal);
+    return e;
+}
+
+hipError_t persistent_occupancy(int img_fmt, int geo_fmt, int block, int *per_cu) {
+    const void *f;
+    if (geo_fmt == 0)
+        f = img_fmt == 0 ? (const void *)k_render_persistent<0, 0>
+                         : (img_fmt == 1 ? (const void *)k_render_persistent<1, 0> : (const void *)k_render_persistent<2, 0>);
+    else
+        f = img_fmt == 0 ? (const void *)k_render_persistent<0, 1>
+                         : (img_fmt == 1 ? (const void *)k_render_persistent<1, 1> : (const void *)k_render_persistent<2, 1>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, block, 0);
 }
 
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,

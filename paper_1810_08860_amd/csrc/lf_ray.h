@@ -14,6 +14,23 @@
 
 namespace lf {
 
+// Hardware reciprocal and square root (about 1 ulp) on the device; the host
+// build (CPU tests) uses the exact operations.
+LF_HD float fast_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+LF_HD float fast_sqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
 // ---------------------------------------------------------------------------------------------
 // storage formats
 
@@ -76,14 +93,14 @@ LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
                                           RayView &rv) {
     const float ez = fmaf(v.m[6], X, fmaf(v.m[7], Y, v.m[8]));
     if (!(ez > 0.0f)) return false;
-    const float iz = 1.0f / ez;
+    const float iz = fast_rcp(ez);
     const float Vx = fmaf(v.m[0], X, fmaf(v.m[1], Y, v.m[2])) * iz;
     const float Vy = fmaf(v.m[3], X, fmaf(v.m[4], Y, v.m[5])) * iz;
     const float Dx = fmaf(-v.o[2], Vx, v.o[0]);
     const float Dy = fmaf(-v.o[2], Vy, v.o[1]);
     const float r2 = fmaf(Dx, Dx, Dy * Dy);
     if (!(r2 < R * R)) return false;
-    const float rho = fmaf(-sqrtf(r2), invR, 1.0f);
+    const float rho = fmaf(-fast_sqrt(r2), invR, 1.0f);
     if (!(rho > 0.0f)) return false;
     rv.Vx = Vx; rv.Vy = Vy; rv.Dx = Dx; rv.Dy = Dy; rv.rho = rho;
     return true;
@@ -135,12 +152,12 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
         const float d0 = fx0 - fy0, d1 = fx1 - fy1;
         if ((d0 > 0.0f && d1 < 0.0f) || (d0 < 0.0f && d1 > 0.0f)) {
             // the segment crosses the cell diagonal: two linear pieces
-            const float s = d0 / (d0 - d1);
+            const float s = d0 * fast_rcp(d0 - d1);
             const float wd = fmaf(s, w1 - w0, w0);
             const float fd = fmaf(s, fx1 - fx0, fx0);
             const float gd = field(cw, fd, fd) - wd;
             if (crosses(g0, gd)) {
-                w_hit = fmaf(wd - w0, g0 / (g0 - gd), w0);
+                w_hit = fmaf(wd - w0, g0 * fast_rcp(g0 - gd), w0);
                 return true;
             }
             w0 = wd;
@@ -150,7 +167,7 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
         }
         const float g1 = field(cw, fx1, fy1) - w1;
         if (crosses(g0, g1)) {
-            w_hit = fmaf(w1 - w0, g0 / (g0 - g1), w0);
+            w_hit = fmaf(w1 - w0, g0 * fast_rcp(g0 - g1), w0);
             return true;
         }
         if (last) {
@@ -187,7 +204,7 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
     const float ax = fmaf(Vx, sM, cM), bx = Dx * sM;
     const float ay = fmaf(-Vy, sM, cM), by = -Dy * sM;
     const bool mx = fabsf(bx) > 1e-20f, my = fabsf(by) > 1e-20f;
-    const float ibx = mx ? 1.0f / bx : 0.0f, iby = my ? 1.0f / by : 0.0f;
+    const float ibx = mx ? fast_rcp(bx) : 0.0f, iby = my ? fast_rcp(by) : 0.0f;
     // clip to the mesh domain 0 <= g <= M-1 on both axes
     if (mx) {
         const float w1 = -ax * ibx, w2 = (lim - ax) * ibx;

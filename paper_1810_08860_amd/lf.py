@@ -69,11 +69,17 @@ def lib():
         L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
         L.lf_profile.argtypes = [vp, i32]
         L.lf_profile_read.argtypes = [vp, vp]
+        L.lf_render_batch.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp,
+                                      ctypes.POINTER(lf_tune), vp]
+        L.lf_autotune_batch.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, i32, ctypes.POINTER(lf_tune),
+                                        vp, vp]
+        L.lf_batch_frame_times.argtypes = [vp, vp, i32]
         L.lf_last_error.restype = ctypes.c_char_p
         L.lf_free.argtypes = [vp]
         L.lf_free.restype = None
         for name in ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
-                     "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read"):
+                     "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
+                     "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -207,6 +213,35 @@ def lf_debug_candidates(ctx: Context, eye, hfov_deg, W, H, cap, out_cand, out_co
                                      _ptr(out_contrib), _ptr(out_ncand), _stream(stream)))
 
 
+def lf_render_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, out_count=None, tune=None,
+                    stream=None):
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    t = ctypes.byref(lf_tune(*tune)) if tune is not None else None
+    _check(lib().lf_render_batch(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb),
+                                 _ptr(out_wsum), _ptr(out_count), t, _stream(stream)))
+
+
+TUNE_GRID = [(tw, th, cap) for tw, th in ((8, 8), (16, 16), (32, 8)) for cap in (8, 16, 32)]
+
+
+def lf_autotune_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, reps=5, stream=None):
+    """Returns ((tile_w, tile_h, cap) chosen, {config: median ms})."""
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    best = lf_tune()
+    ms = np.zeros(9, np.float32)
+    _check(lib().lf_autotune_batch(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb), int(reps),
+                                   ctypes.byref(best), ms.ctypes.data, _stream(stream)))
+    return (best.tile_w, best.tile_h, best.cap), dict(zip(TUNE_GRID, ms.tolist()))
+
+
+def lf_batch_frame_times(ctx: Context, n_eyes):
+    out = np.zeros((n_eyes, 2), np.float64)
+    _check(lib().lf_batch_frame_times(ctx.handle, out.ctypes.data, int(n_eyes)))
+    return out
+
+
 STAT_NAMES = ("pixels", "disk_tests", "candidates", "cells", "samples")
 
 
@@ -243,4 +278,4 @@ def lf_last_error() -> str:
 # names of every symbol include/lf.h declares (checked by the ABI test)
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
-           "lf_last_error", "lf_free")
+           "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_last_error", "lf_free")
