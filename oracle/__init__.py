@@ -239,3 +239,107 @@ def records(ov: OracleViews, o, e):
     recs = np.zeros(ov.n, REC_DTYPE)
     lib().orc_ray_records(ctypes.byref(ov.s), _p(o), _p(e), _p(recs))
     return recs
+
+
+# =========================================================================== corrector (conv) oracle
+#
+# A 4-layer 3x3 convolutional residual corrector of the rendered image
+# (5 input channels: R, G, B, W/4, n/8 with W the disk-weight sum and n the
+# number of contributing views; 32, 32, 32 hidden channels with ReLU; 3 output
+# channels = the residual added to the render). Layer weights are
+# w[ky][kx][ci][co] followed by b[co]; the flat parameter vector concatenates
+# the layers in order (20,835 values).
+
+CORRECTOR_LAYERS = ((5, 32, True), (32, 32, True), (32, 32, True), (32, 3, False))
+CORRECTOR_W_SCALE, CORRECTOR_N_SCALE = 4.0, 8.0
+
+
+def corrector_num_params():
+    return sum(9 * ci * co + co for ci, co, _ in CORRECTOR_LAYERS)
+
+
+def conv3x3_fwd(x, w, b, relu):
+    """x (N,H,W,Cin), w (3,3,Cin,Cout), b (Cout,) -> act(conv(x)) (N,H,W,Cout), FP64."""
+    x = np.ascontiguousarray(x, np.float64)
+    w = np.ascontiguousarray(w, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    N, H, W, Cin = x.shape
+    Cout = w.shape[3]
+    assert w.shape == (3, 3, Cin, Cout) and b.shape == (Cout,)
+    y = np.zeros((N, H, W, Cout))
+    lib().orc_conv3x3_fwd(_p(x), N, H, W, Cin, Cout, _p(w), _p(b), _p(y), 1 if relu else 0)
+    return y
+
+
+def conv3x3_bwd(x, y, w, dy, relu, want_dx=True):
+    """Gradients of a layer given dL/dy: (dx, dw, db)."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    w = np.ascontiguousarray(w, np.float64)
+    dy = np.ascontiguousarray(dy, np.float64)
+    N, H, W, Cin = x.shape
+    Cout = w.shape[3]
+    dx = np.zeros_like(x) if want_dx else None
+    dw = np.zeros_like(w)
+    db = np.zeros(Cout)
+    lib().orc_conv3x3_bwd(_p(x), _p(y), N, H, W, Cin, Cout, _p(w), _p(dy), _p(dx) if want_dx else None, _p(dw),
+                          _p(db), 1 if relu else 0)
+    return dx, dw, db
+
+
+def corrector_unpack(params):
+    params = np.asarray(params, np.float64)
+    out, o = [], 0
+    for ci, co, _ in CORRECTOR_LAYERS:
+        w = params[o:o + 9 * ci * co].reshape(3, 3, ci, co)
+        o += 9 * ci * co
+        b = params[o:o + co]
+        o += co
+        out.append((w, b))
+    assert o == params.size
+    return out
+
+
+def corrector_input(rgb, wsum, count):
+    """Network input (N,H,W,5) from the render's colour, weight sum and view count."""
+    rgb = np.asarray(rgb, np.float64)
+    return np.concatenate([rgb, np.asarray(wsum, np.float64)[..., None] / CORRECTOR_W_SCALE,
+                           np.asarray(count, np.float64)[..., None] / CORRECTOR_N_SCALE], -1)
+
+
+def corrector_forward(params, x):
+    """Residual (N,H,W,3) and the activations of every layer (input first)."""
+    acts = [np.asarray(x, np.float64)]
+    for (w, b), (_, _, relu) in zip(corrector_unpack(params), CORRECTOR_LAYERS):
+        acts.append(conv3x3_fwd(acts[-1], w, b, relu))
+    return acts[-1], acts
+
+
+def corrector_loss_grad(params, x, render, ref):
+    """Mean squared error of (render + residual) against ref over every pixel
+    and channel, and its gradient w.r.t. the flat parameters."""
+    resid, acts = corrector_forward(params, x)
+    diff = np.asarray(render, np.float64) + resid - np.asarray(ref, np.float64)
+    loss = float((diff ** 2).mean())
+    g = 2.0 * diff / diff.size
+    grads = []
+    layers = corrector_unpack(params)
+    for li in range(len(layers) - 1, -1, -1):
+        w, _ = layers[li]
+        relu = CORRECTOR_LAYERS[li][2]
+        dx, dw, db = conv3x3_bwd(acts[li], acts[li + 1], w, g, relu, want_dx=li > 0)
+        grads.append((dw, db))
+        g = dx
+    flat = []
+    for dw, db in reversed(grads):
+        flat += [dw.ravel(), db]
+    return loss, np.concatenate(flat)
+
+
+def corrector_apply(params, x, render, thresh):
+    """render + residual, except pixels whose largest |residual| component
+    exceeds thresh keep the render (fallback); returns (out, fallback mask)."""
+    resid, _ = corrector_forward(params, x)
+    fb = np.abs(resid).max(-1) > thresh
+    out = np.where(fb[..., None], render, render + resid)
+    return out, fb
