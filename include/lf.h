@@ -199,6 +199,46 @@ int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
 int lf_profile(lf_ctx *c, int32_t enable);
 int lf_profile_read(lf_ctx *c, double out[6]);
 
+/* ---------------------------------------------------------------------------
+ * Learned residual corrector (a post-process of the render; not in the paper,
+ * whose learning-based methods are related work only, Sec. 1.1).
+ *
+ * Network: four 3x3 convolutions with zero padding, 5 -> 32 -> 32 -> 32 -> 3
+ * channels, ReLU after the first three. Input per pixel: (R, G, B, W/4, n/8)
+ * from lf_render's colour, weight sum W and view count n. Output: the
+ * residual r; corrected pixel = render + r, except where max_c |r_c| >
+ * fallback_thresh, which keep the render. Parameters: 20,835 FP32 values,
+ * layer after layer, each layer w[ky][kx][ci][co] then b[co]. Kernels use
+ * BF16 weights and activations with FP32 accumulation (MFMA); the master
+ * parameters and Adam state are FP32.
+ * Images: n_images equally sized images, eyes concatenated as lf_render
+ * writes them (rgb [P][3] FP32, wsum [P] FP32, count [P] u8, all device).
+ * ------------------------------------------------------------------------- */
+typedef struct lf_corrector lf_corrector;
+
+/* Create with the given parameters (host, 20,835 floats) or zeros (NULL). */
+int lf_corrector_create(const float *params, lf_corrector **out);
+/* Replace the parameters (host) and reset the optimiser state. */
+int lf_corrector_set_params(lf_corrector *c, const float *params);
+/* Copy the current FP32 parameters to host memory; *step (may be NULL) = optimiser steps taken. Synchronous. */
+int lf_corrector_get_params(lf_corrector *c, float *params, int64_t *step);
+/* Corrected images (device out_rgb [P][3]); out_fallback (device [P] u8, 1 =
+ * kept the render) and out_resid (device [P][3] FP32) may be NULL. A
+ * threshold of 0 returns the render exactly. Asynchronous on hip_stream. */
+int lf_corrector_apply(lf_corrector *c, const float *rgb, const float *wsum, const uint8_t *count, int32_t n_images,
+                       int32_t W, int32_t H, float fallback_thresh, float *out_rgb, uint8_t *out_fallback,
+                       float *out_resid, void *hip_stream);
+/* One training step on a batch: loss = mean over pixels and channels of
+ * (render + r - ref)^2 (ref device [P][3]); gradients by the backward kernels;
+ * Adam (beta 0.9 / 0.999, eps 1e-8) with learning rate lr (lr = 0: gradients
+ * only, no update). loss_out / grad_out (host, 20,835 floats) may be NULL;
+ * when given the call synchronises. */
+int lf_corrector_train_step(lf_corrector *c, const float *rgb, const float *wsum, const uint8_t *count,
+                            const float *ref, int32_t n_images, int32_t W, int32_t H, float lr, float *loss_out,
+                            float *grad_out, void *hip_stream);
+/* Release (NULL is a no-op). */
+void lf_corrector_free(lf_corrector *c);
+
 /* Number of views, image and mesh sizes and formats of a context. */
 int lf_query(const lf_ctx *c, int32_t *n_views, int32_t *img_w, int32_t *mesh_m, int32_t *img_fmt,
              int32_t *geo_fmt);

@@ -15,9 +15,16 @@
 
 using namespace lf;
 
-namespace {
-
 thread_local std::string g_err;
+
+namespace lf {
+int fail_msg(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace lf
+
+namespace {
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];

@@ -1,0 +1,434 @@
+// Learned residual corrector of the rendered eye view: four 3x3 convolutions
+// (5 -> 32 -> 32 -> 32 -> 3 channels, ReLU after the first three, zero
+// padding), output = render + residual, except pixels whose largest residual
+// component exceeds a threshold keep the plain render. BF16 weights and
+// activations, FP32 accumulation on MFMA (v_mfma_f32_16x16x32_bf16); FP32
+// master weights trained with Adam by the kernels below.
+//
+// Convolution as an implicit GEMM: rows = output pixels (one 16-pixel run of
+// an image row per MFMA block), columns = output channels, reduction =
+// (tap, input channel) with the input channels of one tap contiguous. A
+// workgroup computes a 16 x 8 pixel tile for every output channel from an
+// LDS halo tile of the input and an LDS copy of the packed weights.
+//
+// Activation layout: NHWC, channels padded to a multiple of 8 (layer-1 input
+// 8 = R, G, B, W/4, n/8, 0, 0, 0; hidden 32; residual FP32 x 4).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lf_corrector.h"
+
+namespace lf {
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int TW = kCorrTileW, TH = kCorrTileH;  // output tile: 16 x 8 pixels
+
+template <int CIN>
+constexpr int kpad() { return ((9 * CIN + 31) / 32) * 32; }
+
+// ---------------------------------------------------------------------------------------------
+// forward / backward-data convolution
+
+enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_MASK_BF16 = 2 };
+
+// out = epilogue(conv3x3(in, w) [+ bias]) for one 16 x 8 tile per workgroup
+// (256 threads: wave w owns tile rows 2w, 2w+1). CIN, COUT: padded channel
+// counts of input and output (multiples of 8; COUT a multiple of 16 for the
+// MFMA columns, COUT_ST the stored channel count).
+template <int CIN, int COUT, int COUT_ST, int EPI>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, int32_t N, int32_t H, int32_t W,
+                                              const uint16_t *__restrict__ wpk, const float *__restrict__ bias,
+                                              void *__restrict__ out, const uint16_t *__restrict__ mask) {
+    constexpr int KP = kpad<CIN>();
+    constexpr int NB = COUT / 16;
+    constexpr int HX = TW + 2, HY = TH + 2;
+    // pixel stride padded by 8 bf16 so that the 16 lanes of an A read hit
+    // different LDS banks
+    constexpr int PS = CIN + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t tin[HY * HX * PS];
+    __shared__ __attribute__((aligned(16))) uint16_t tw[COUT * (KP + 8)];
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int b = blockIdx.x;
+    const int n = b / (tiles_x * tiles_y), r = b % (tiles_x * tiles_y);
+    const int x0 = (r % tiles_x) * TW, y0 = (r / tiles_x) * TH;
+    const int tid = threadIdx.x;
+
+    // weights: COUT rows of KP bf16, 16 bytes per thread and step
+    for (int q = tid; q < COUT * KP / 8; q += 256) {
+        const int row = q / (KP / 8), c8 = q % (KP / 8);
+        *reinterpret_cast<uint4 *>(&tw[row * (KP + 8) + 8 * c8]) =
+            *reinterpret_cast<const uint4 *>(&wpk[(int64_t)row * KP + 8 * c8]);
+    }
+    // input halo tile, zero outside the image
+    for (int q = tid; q < HY * HX * (CIN / 8); q += 256) {
+        const int pix = q / (CIN / 8), c8 = q % (CIN / 8);
+        const int yy = y0 - 1 + pix / HX, xx = x0 - 1 + pix % HX;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            v = *reinterpret_cast<const uint4 *>(&in[(((int64_t)n * H + yy) * W + xx) * CIN + 8 * c8]);
+        *reinterpret_cast<uint4 *>(&tin[pix * PS + 8 * c8]) = v;
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    floatx4 acc[2][NB];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s = 0; s < KP / 32; ++s) {
+        const int k0 = 32 * s + 8 * g;  // this lane's 8 reduction indices k0 .. k0+7
+        const int t = k0 / CIN, ci = k0 % CIN;
+        bf16x8 bv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = *reinterpret_cast<const bf16x8 *>(&tw[(16 * nb + i) * (KP + 8) + k0]);
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (t < 9) {
+                const int ky = t / 3, kx = t % 3;
+                const int row = 2 * wave + rr;
+                av = *reinterpret_cast<const bf16x8 *>(&tin[((row + ky) * HX + i + kx) * PS + ci]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[rr][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[rr][nb], 0, 0, 0);
+        }
+    }
+
+    // D[m][j]: m = 4 g + v (pixel along the row), j = i (output channel in the block)
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        const int yy = y0 + 2 * wave + rr;
+        if (yy >= H) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int c = 16 * nb + i;
+            if (c >= COUT_ST) continue;
+            const float bi = (EPI == EPI_MASK_BF16) ? 0.0f : bias[c];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int xx = x0 + 4 * g + v;
+                if (xx >= W) continue;
+                const int64_t o = (((int64_t)n * H + yy) * W + xx) * COUT_ST + c;
+                float val = acc[rr][nb][v] + bi;
+                if (EPI == EPI_RELU_BF16) {
+                    reinterpret_cast<uint16_t *>(out)[o] = f2bf(fmaxf(val, 0.0f));
+                } else if (EPI == EPI_F32) {
+                    reinterpret_cast<float *>(out)[o] = val;
+                } else {
+                    reinterpret_cast<uint16_t *>(out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? val : 0.0f);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// weight gradient: dW[t][ci][co] = sum_p x[p + d_t][ci] dz[p][co], db[co] = sum_p dz[p][co]
+//
+// GEMM with rows (t, ci), columns co and the reduction over pixels. A
+// workgroup strides over 16 x 8 tiles, staging x (with halo, one copy per
+// horizontal tap offset so that 8 consecutive pixels are one aligned 16-byte
+// LDS read) and dz channel-major, and keeps its partial sums in registers;
+// at the end it writes its partial dW / db to its own slot (reduced in a
+// fixed order by k_reduce_partials: deterministic).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
+                                                 int32_t N, int32_t H, int32_t W, int32_t cin_real,
+                                                 int32_t cout_real, float *__restrict__ partial) {
+    constexpr int MB = (9 * CIN + 15) / 16;  // row blocks of 16 (t, ci) pairs
+    constexpr int NBK = (COUT + 15) / 16;
+    constexpr int NBLK = MB * NBK;
+    constexpr int PER = (NBLK + 3) / 4;      // output blocks per wave
+    constexpr int HY = TH + 2;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3][CIN][HY][TW];
+    __shared__ __attribute__((aligned(16))) uint16_t dzs[16 * NBK][TH][TW];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int total = N * tiles_x * tiles_y;
+    floatx4 acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float db_acc = 0.0f;  // thread tid < COUT: its channel's sum
+
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int n = tile / (tiles_x * tiles_y), r = tile % (tiles_x * tiles_y);
+        const int x0 = (r % tiles_x) * TW, y0 = (r / tiles_x) * TH;
+        __syncthreads();
+        // x tile: xs[kx][c][row][col] = x[y0 - 1 + row][x0 + col + kx - 1][c]
+        for (int q = tid; q < 3 * CIN * HY * TW; q += 256) {
+            const int col = q % TW, row = (q / TW) % HY, c = (q / (TW * HY)) % CIN, kx = q / (TW * HY * CIN);
+            const int yy = y0 - 1 + row, xx = x0 + col + kx - 1;
+            uint16_t v = 0;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[(((int64_t)n * H + yy) * W + xx) * CIN + c];
+            xs[kx][c][row][col] = v;
+        }
+        for (int q = tid; q < 16 * NBK * TH * TW; q += 256) {
+            const int col = q % TW, row = (q / TW) % TH, c = q / (TW * TH);
+            const int yy = y0 + row, xx = x0 + col;
+            uint16_t v = 0;
+            if (c < COUT && yy < H && xx < W) v = dz[(((int64_t)n * H + yy) * W + xx) * COUT + c];
+            dzs[c][row][col] = v;
+        }
+        __syncthreads();
+        if (tid < COUT) {
+            float sacc = 0.0f;
+            for (int p = 0; p < TH * TW; ++p) sacc += bf2f(dzs[tid][p / TW][p % TW]);
+            db_acc += sacc;
+        }
+        // reduction over the tile's 128 pixels in 4 steps of 32 (two rows of 16)
+#pragma unroll
+        for (int s = 0; s < TH / 2; ++s) {
+            const int row = 2 * s + (g >> 1), col = 8 * (g & 1);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int blk = wave * PER + q;
+                if (blk >= NBLK) continue;
+                const int mb = blk / NBK, nb = blk % NBK;
+                const int m = 16 * mb + i;  // (t, ci) row of this lane
+                bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (m < 9 * CIN) {
+                    const int t = m / CIN, ci = m % CIN;
+                    const int ky = t / 3, kx = t % 3;
+                    av = *reinterpret_cast<const bf16x8 *>(&xs[kx][ci][row + ky][col]);
+                }
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&dzs[16 * nb + i][row][col]);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // partial result of this workgroup in the flat parameter layout (dw then db)
+    const int nw = 9 * cin_real * cout_real;
+    float *pw = partial + (int64_t)blockIdx.x * (nw + cout_real);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int blk = wave * PER + q;
+        if (blk >= NBLK) continue;
+        const int mb = blk / NBK, nb = blk % NBK;
+        const int co = 16 * nb + i;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = 16 * mb + 4 * g + v;
+            if (m >= 9 * CIN) continue;
+            const int t = m / CIN, ci = m % CIN;
+            if (ci < cin_real && co < cout_real) pw[(t * cin_real + ci) * cout_real + co] = acc[q][v];
+        }
+    }
+    if (tid < cout_real) pw[nw + tid] = db_acc;
+}
+
+// out[j] = sum over slots of partial[slot][j] (fixed order)
+__global__ void k_reduce_partials(const float *__restrict__ partial, int32_t slots, int32_t len,
+                                  float *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= len) return;
+    float s = 0.0f;
+    for (int k = 0; k < slots; ++k) s += partial[(int64_t)k * len + j];
+    out[j] = s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// element-wise pieces
+
+// Layer-1 input: (R, G, B, W / 4, n / 8, 0, 0, 0) in BF16.
+__global__ void k_corr_input(const float *__restrict__ rgb, const float *__restrict__ wsum,
+                             const uint8_t *__restrict__ count, int64_t P, uint16_t *__restrict__ a0) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t v[8];
+        v[0] = f2bf(rgb[3 * p]);
+        v[1] = f2bf(rgb[3 * p + 1]);
+        v[2] = f2bf(rgb[3 * p + 2]);
+        v[3] = f2bf(wsum[p] * (1.0f / kCorrWScale));
+        v[4] = f2bf((float)count[p] * (1.0f / kCorrNScale));
+        v[5] = v[6] = v[7] = 0;
+        uint4 o;
+        o.x = v[0] | ((uint32_t)v[1] << 16);
+        o.y = v[2] | ((uint32_t)v[3] << 16);
+        o.z = v[4];
+        o.w = 0;
+        reinterpret_cast<uint4 *>(a0)[p] = o;
+    }
+}
+
+// Training loss: diff = render + residual - ref; partial sums of diff^2 per
+// block, and dL/d(residual) = 2 diff / (3P) in BF16 (8-channel layout).
+__global__ __launch_bounds__(256) void k_corr_loss(const float *__restrict__ rgb, const float *__restrict__ resid,
+                                                   const float *__restrict__ ref, int64_t P,
+                                                   uint16_t *__restrict__ dz, float *__restrict__ loss_part) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    const float k = 2.0f / (3.0f * (float)P);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t d[3];
+        for (int c = 0; c < 3; ++c) {
+            const float df = rgb[3 * p + c] + resid[4 * p + c] - ref[3 * p + c];
+            s += df * df;
+            d[c] = f2bf(k * df);
+        }
+        uint4 o;
+        o.x = d[0] | ((uint32_t)d[1] << 16);
+        o.y = d[2];
+        o.z = 0;
+        o.w = 0;
+        reinterpret_cast<uint4 *>(dz)[p] = o;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// Adam on the FP32 master parameters.
+__global__ void k_adam(float *__restrict__ prm, const float *__restrict__ grad, float *__restrict__ m1,
+                       float *__restrict__ m2, int32_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = grad[j];
+    const float a = b1 * m1[j] + (1.0f - b1) * gj;
+    const float v = b2 * m2[j] + (1.0f - b2) * gj * gj;
+    m1[j] = a;
+    m2[j] = v;
+    prm[j] -= lr * (a * c1) / (sqrtf(v * c2) + eps);
+}
+
+// Pack the FP32 master parameters of every layer into the MFMA layouts:
+// forward wf[co][t * CINP + ci] (zero padded), FP32 bias, and for the
+// backward-data pass wb[ci][t' * COUTP_in + co] = w[8 - t'][ci][co].
+__global__ void k_corr_pack(const float *__restrict__ prm, CorrLayout L, uint16_t *__restrict__ wbuf,
+                            float *__restrict__ bbuf) {
+    const int layer = blockIdx.y;
+    const CorrLayer &ly = L.layer[layer];
+    const float *w = prm + ly.poff;
+    const float *b = w + 9 * ly.cin * ly.cout;
+    const int nf = ly.coutp * ly.kf, nb = ly.cinp_b * ly.kb;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nf + nb + ly.coutp; q += gridDim.x * blockDim.x) {
+        if (q < nf) {
+            const int co = q / ly.kf, k = q % ly.kf, t = k / ly.cinp, ci = k % ly.cinp;
+            float v = 0.0f;
+            if (t < 9 && ci < ly.cin && co < ly.cout) v = w[(t * ly.cin + ci) * ly.cout + co];
+            wbuf[ly.wf_off + q] = f2bf(v);
+        } else if (q < nf + nb) {
+            const int qq = q - nf;
+            const int ci = qq / ly.kb, k = qq % ly.kb, tp = k / ly.coutp_b, co = k % ly.coutp_b;
+            float v = 0.0f;
+            if (tp < 9 && ci < ly.cin && co < ly.cout) v = w[((8 - tp) * ly.cin + ci) * ly.cout + co];
+            wbuf[ly.wb_off + qq] = f2bf(v);
+        } else {
+            const int co = q - nf - nb;
+            bbuf[ly.b_off + co] = co < ly.cout ? b[co] : 0.0f;
+        }
+    }
+}
+
+// out = render + residual, or the render where max |residual| > thresh.
+__global__ void k_corr_finish(const float *__restrict__ rgb, const float *__restrict__ resid, int64_t P,
+                              float thresh, float *__restrict__ out, uint8_t *__restrict__ fb,
+                              float *__restrict__ resid_out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const float r0 = resid[4 * p], r1 = resid[4 * p + 1], r2 = resid[4 * p + 2];
+        const bool f = fmaxf(fabsf(r0), fmaxf(fabsf(r1), fabsf(r2))) > thresh;
+        out[3 * p] = f ? rgb[3 * p] : rgb[3 * p] + r0;
+        out[3 * p + 1] = f ? rgb[3 * p + 1] : rgb[3 * p + 1] + r1;
+        out[3 * p + 2] = f ? rgb[3 * p + 2] : rgb[3 * p + 2] + r2;
+        if (fb) fb[p] = f ? 1 : 0;
+        if (resid_out) {
+            resid_out[3 * p] = r0;
+            resid_out[3 * p + 1] = r1;
+            resid_out[3 * p + 2] = r2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+
+static int grid_elems(int64_t n) {
+    const int64_t g = (n + 255) / 256;
+    return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+hipError_t corr_input(const float *rgb, const float *wsum, const uint8_t *count, int64_t P, uint16_t *a0,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_input, dim3(grid_elems(P)), dim3(256), 0, s, rgb, wsum, count, P, a0);
+    return hipGetLastError();
+}
+
+hipError_t corr_pack(const float *prm, const CorrLayout &L, uint16_t *wbuf, float *bbuf, hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_pack, dim3(64, 4), dim3(256), 0, s, prm, L, wbuf, bbuf);
+    return hipGetLastError();
+}
+
+// Forward layer l (0..3) or backward-data pass of layer l (1..3: dz_l -> dz_{l-1}).
+hipError_t corr_conv(int layer, bool backward, const uint16_t *in, int32_t N, int32_t H, int32_t W,
+                     const uint16_t *wpk, const float *bias, void *out, const uint16_t *mask, hipStream_t s) {
+    const int tiles = N * ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
+    const dim3 g(tiles), b(256);
+    if (!backward) {
+        switch (layer) {
+        case 0: hipLaunchKernelGGL((k_conv<8, 32, 32, EPI_RELU_BF16>), g, b, 0, s, in, N, H, W, wpk, bias, out, mask); break;
+        case 1:
+        case 2: hipLaunchKernelGGL((k_conv<32, 32, 32, EPI_RELU_BF16>), g, b, 0, s, in, N, H, W, wpk, bias, out, mask); break;
+        default: hipLaunchKernelGGL((k_conv<32, 16, 4, EPI_F32>), g, b, 0, s, in, N, H, W, wpk, bias, out, mask); break;
+        }
+    } else {
+        switch (layer) {
+        case 3: hipLaunchKernelGGL((k_conv<8, 32, 32, EPI_MASK_BF16>), g, b, 0, s, in, N, H, W, wpk, bias, out, mask); break;
+        default: hipLaunchKernelGGL((k_conv<32, 32, 32, EPI_MASK_BF16>), g, b, 0, s, in, N, H, W, wpk, bias, out, mask); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t corr_dw(int layer, const uint16_t *x, const uint16_t *dz, int32_t N, int32_t H, int32_t W,
+                   int32_t cin_real, int32_t cout_real, float *partial, int slots, hipStream_t s) {
+    switch (layer) {
+    case 0: hipLaunchKernelGGL((k_conv_dw<8, 32>), dim3(slots), dim3(256), 0, s, x, dz, N, H, W, cin_real, cout_real, partial); break;
+    case 1:
+    case 2: hipLaunchKernelGGL((k_conv_dw<32, 32>), dim3(slots), dim3(256), 0, s, x, dz, N, H, W, cin_real, cout_real, partial); break;
+    default: hipLaunchKernelGGL((k_conv_dw<32, 8>), dim3(slots), dim3(256), 0, s, x, dz, N, H, W, cin_real, cout_real, partial); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t corr_reduce(const float *partial, int32_t slots, int32_t len, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, s, partial, slots, len, out);
+    return hipGetLastError();
+}
+
+hipError_t corr_loss(const float *rgb, const float *resid, const float *ref, int64_t P, uint16_t *dz,
+                     float *loss_part, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_loss, dim3(blocks), dim3(256), 0, s, rgb, resid, ref, P, dz, loss_part);
+    return hipGetLastError();
+}
+
+hipError_t corr_adam(float *prm, const float *grad, float *m1, float *m2, int32_t n, float lr, float b1, float b2,
+                     float eps, float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, prm, grad, m1, m2, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t corr_finish(const float *rgb, const float *resid, int64_t P, float thresh, float *out, uint8_t *fb,
+                       float *resid_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_finish, dim3(grid_elems(P)), dim3(256), 0, s, rgb, resid, P, thresh, out, fb, resid_out);
+    return hipGetLastError();
+}
+
+}  // namespace lf

@@ -89,6 +89,9 @@ struct RenderArgs {
     unsigned long long *stats;
 };
 
+// Record an error message for lf_last_error and return code (lf_api.cpp).
+int fail_msg(int code, const char *msg);
+
 // Launchers (lf_kernels.hip). All are asynchronous on `s` and return the
 // launch status.
 hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int64_t n_texels, hipStream_t s);

@@ -74,12 +74,21 @@ def lib():
         L.lf_autotune_batch.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, i32, ctypes.POINTER(lf_tune),
                                         vp, vp]
         L.lf_batch_frame_times.argtypes = [vp, vp, i32]
+        L.lf_corrector_create.argtypes = [vp, ctypes.POINTER(vp)]
+        L.lf_corrector_set_params.argtypes = [vp, vp]
+        L.lf_corrector_get_params.argtypes = [vp, vp, vp]
+        L.lf_corrector_apply.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp, vp]
+        L.lf_corrector_train_step.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
+        L.lf_corrector_free.argtypes = [vp]
+        L.lf_corrector_free.restype = None
         L.lf_last_error.restype = ctypes.c_char_p
         L.lf_free.argtypes = [vp]
         L.lf_free.restype = None
         for name in ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
                      "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
-                     "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times"):
+                     "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
+                     "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply",
+                     "lf_corrector_train_step"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -242,6 +251,68 @@ def lf_batch_frame_times(ctx: Context, n_eyes):
     return out
 
 
+CORRECTOR_PARAMS = 20835
+
+
+class Corrector:
+    """Owns an lf_corrector handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().lf_corrector_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lf_corrector_create(params=None) -> Corrector:
+    h = ctypes.c_void_p()
+    p = None
+    if params is not None:
+        params = np.ascontiguousarray(params, np.float32)
+        assert params.size == CORRECTOR_PARAMS
+        p = params.ctypes.data
+    _check(lib().lf_corrector_create(p, ctypes.byref(h)))
+    return Corrector(h.value)
+
+
+def lf_corrector_set_params(c: Corrector, params):
+    params = np.ascontiguousarray(params, np.float32)
+    assert params.size == CORRECTOR_PARAMS
+    _check(lib().lf_corrector_set_params(c.handle, params.ctypes.data))
+
+
+def lf_corrector_get_params(c: Corrector):
+    out = np.zeros(CORRECTOR_PARAMS, np.float32)
+    step = ctypes.c_int64()
+    _check(lib().lf_corrector_get_params(c.handle, out.ctypes.data, ctypes.byref(step)))
+    return out, step.value
+
+
+def lf_corrector_apply(c: Corrector, rgb, wsum, count, n_images, W, H, thresh, out_rgb, out_fallback=None,
+                       out_resid=None, stream=None):
+    _check(lib().lf_corrector_apply(c.handle, _ptr(rgb), _ptr(wsum), _ptr(count), int(n_images), int(W), int(H),
+                                    float(thresh), _ptr(out_rgb), _ptr(out_fallback), _ptr(out_resid),
+                                    _stream(stream)))
+
+
+def lf_corrector_train_step(c: Corrector, rgb, wsum, count, ref, n_images, W, H, lr, want_loss=True,
+                            want_grad=False, stream=None):
+    loss = ctypes.c_float()
+    grad = np.zeros(CORRECTOR_PARAMS, np.float32) if want_grad else None
+    _check(lib().lf_corrector_train_step(c.handle, _ptr(rgb), _ptr(wsum), _ptr(count), _ptr(ref), int(n_images),
+                                         int(W), int(H), float(lr), ctypes.byref(loss) if want_loss else None,
+                                         grad.ctypes.data if want_grad else None, _stream(stream)))
+    return (loss.value if want_loss else None), grad
+
+
 STAT_NAMES = ("pixels", "disk_tests", "candidates", "cells", "samples")
 
 
@@ -278,4 +349,6 @@ def lf_last_error() -> str:
 # names of every symbol include/lf.h declares (checked by the ABI test)
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
-           "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_last_error", "lf_free")
+           "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
+           "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",
+           "lf_corrector_free", "lf_last_error", "lf_free")
