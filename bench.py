@@ -183,6 +183,74 @@ def time_batched(lf, torch, ctx, w, steps, warmup, per_batch, profile=False):
 
 
 MIXED_SIZES = [(1080, 1200), (1440, 1600), (2160, 2160)]
+CORR_FLOP_PER_PX = 2 * 9 * (5 * 32 + 32 * 32 + 32 * 32 + 32 * 3)  # 41,472 multiply-adds x 2
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
+    """Train the residual corrector on pairs the method generates (real-time
+    FP16 render vs the offline reference: 4x4 sub-pixel rays, disks of twice
+    the radius), 20k crops by default; PSNR on held-out poses; inference time
+    on a stereo frame."""
+    import lfsynth
+    from paper_1810_08860_amd import corrector
+
+    def eyes(seed, n):
+        p, R = lfsynth.poses(seed, n, 0.25)
+        out = []
+        for k in range(n):
+            out += [(np.array(e.pos), np.array(e.rot).reshape(3, 3)) for e in lf.lf_stereo_eyes(p[k], R[k], IPD)]
+        return out
+
+    t0 = time.perf_counter()
+    train_frames = corrector.make_frames(ctx_rt, ctx_ref, eyes(500, 12), HFOV, EYE_W, EYE_H)
+    test_frames = corrector.make_frames(ctx_rt, ctx_ref, eyes(900, 2), HFOV, EYE_W, EYE_H)
+    t_pairs = time.perf_counter() - t0
+    corr = lf.lf_corrector_create(corrector.init_params(0))
+    t0 = time.perf_counter()
+    log = corrector.train(corr, train_frames, steps=steps, batch=batch, crop=crop, seed=1, log_every=250)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = corrector.evaluate(corr, test_frames)
+    # inference timing on one stereo frame (both eyes in one call)
+    f0, f1 = test_frames[0], test_frames[1]
+    rgb = torch.stack([f0.rgb, f1.rgb]).contiguous()
+    ws = torch.stack([f0.wsum, f1.wsum]).contiguous()
+    cnt = torch.stack([f0.count, f1.count]).contiguous()
+    out = torch.empty_like(rgb)
+    for _ in range(3):
+        lf.lf_corrector_apply(corr, rgb, ws, cnt, 2, EYE_W, EYE_H, 8.0 / 255.0, out)
+    reps = 20
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        lf.lf_corrector_apply(corr, rgb, ws, cnt, 2, EYE_W, EYE_H, 8.0 / 255.0, out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    tflops = CORR_FLOP_PER_PX * 2 * EYE_W * EYE_H / (ms * 1e-3) / 1e12
+    corr.close()
+    return {
+        "training_crops": steps * batch,
+        "crop": crop,
+        "train_eyes": len(train_frames),
+        "held_out_eyes": len(test_frames),
+        "pair_generation_s": t_pairs,
+        "train_s": t_train,
+        "loss_first_last": [log[0][1], log[-1][1]],
+        "psnr_plain_db": ev["psnr_plain"],
+        "psnr_corrected_db": ev["psnr_corrected"],
+        "psnr_gain_db": ev["psnr_gain_db"],
+        "max_err_plain": ev["max_err_plain"],
+        "max_err_corrected": ev["max_err_corrected"],
+        "fallback_threshold": 8.0 / 255.0,
+        "fallback_frac": ev["fallback_frac"],
+        "ms_per_stereo_frame": ms,
+        "achieved_tflops": tflops,
+        "mfma_bf16_peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+        "frac_of_peak": tflops / BF16_MFMA_PEAK_TFLOPS,
+    }
 
 
 def mixed_batch(lf, torch, ctx, seed, n_poses=64, reps=10):
@@ -242,6 +310,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
+    ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector leg")
+    ap.add_argument("--corrector-steps", type=int, default=1250)
     ap.add_argument("--variants", default="plain,fp16,rgba8,fp16_batched")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -312,6 +382,14 @@ def main():
         log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']}/{mixed['tune']['cap']}, "
             f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
+    corr = None
+    if not args.no_corrector and ("rgba16f", "f16") in ctxs and ("rgba32f", "f32") in ctxs:
+        log("[bench] corrector ...")
+        corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f16")], ctxs[("rgba32f", "f32")],
+                             steps=args.corrector_steps)
+        log(f"[bench] corrector: PSNR {corr['psnr_plain_db']:.2f} -> {corr['psnr_corrected_db']:.2f} dB, "
+            f"{corr['ms_per_stereo_frame']:.3f} ms / stereo frame, {corr['achieved_tflops']:.0f} TFLOP/s")
+
     m = results[main_name]
     roofline = None
     if m.get("prof") and m.get("stats_per_frame"):
@@ -369,6 +447,7 @@ def main():
                      for k, v in results.items()},
         "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
         "mixed_batch": mixed,
+        "corrector": corr,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
