@@ -86,11 +86,11 @@ typedef struct {
     double rot[9];
 } lf_eye;
 
-/* Launch shape: screen tile (tile_w x tile_h pixels, both multiples of 8,
- * tile_w * tile_h <= 256) and the number of candidate views staged in LDS per
- * pass (cap in [1, 64]). */
+/* Launch shape: screen tile of tile_w x tile_h pixels (both multiples of 8,
+ * tile_w * tile_h <= 256); one workgroup renders one tile, one wavefront one
+ * 8 x 8 pixel block of it. */
 typedef struct {
-    int32_t tile_w, tile_h, cap;
+    int32_t tile_w, tile_h;
 } lf_tune;
 
 /*
@@ -152,7 +152,7 @@ int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W
  * per-eye set-up, culling, persistent render) is captured once in a HIP graph
  * per batch shape (eye count, sizes, FOV, output buffers, tune) and replayed;
  * each call uploads only the eye poses. tune NULL = the context's tune (the
- * autotuned one after lf_autotune_batch, else 16x16 tiles, cap 32).
+ * autotuned one after lf_autotune_batch, else 16x16 tiles).
  * Output layout as lf_render. Per-eye start / end stamps of the last batch are
  * read with lf_batch_frame_times.
  */
@@ -161,10 +161,10 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
 
 /*
  * Autotuner of the batched path: times lf_render_batch on the given batch for
- * tiles {8x8, 16x16, 32x8} x cap {8, 16, 32} (median of reps runs each, after
- * a capture and warm-up run), stores the fastest in the context and returns it
- * in *best (may be NULL); ms[9] (may be NULL) receives the medians in the order
- * shape-major, cap-minor. Synchronous.
+ * tiles {8x8, 16x16, 32x8} (median of reps runs each, after a capture and
+ * warm-up run), stores the fastest in the context and returns it in *best (may
+ * be NULL); ms[3] (may be NULL) receives the medians in that order.
+ * Synchronous.
  */
 int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
                       float *out_rgb, int32_t reps, lf_tune *best, float *ms, void *hip_stream);

@@ -75,7 +75,7 @@ struct lf_ctx {
     // per-render scratch: eye-view table and tile lists, grown on demand
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
-    lf_tune tune{16, 16, 32};
+    lf_tune tune{16, 16};
     // optional per-kernel timing (lf_profile): event pairs around each launch
     struct Timed {
         int kind;
@@ -103,7 +103,7 @@ struct lf_ctx {
         // persistent render kernel; each replay points them at fresh events
         hipEvent_t ph_a = nullptr, ph_b = nullptr;
         hipGraphNode_t node_a = nullptr, node_b = nullptr;
-        lf_tune tune{16, 16, 32};
+        lf_tune tune{16, 16};
         bool tuned = false;
     } batch;
 };
@@ -217,7 +217,6 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.invR = (float)(1.0 / R);
     a.texels_per_view = (int64_t)c->img_w * c->img_h;
     a.cells_per_view = (int64_t)(c->M - 1) * (c->M - 1);
-    a.cap = c->tune.cap;
     a.scale = 1.0f;
     return a;
 }
@@ -384,12 +383,11 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
 int lf_set_tune(lf_ctx *c, const lf_tune *t) {
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (!t) {
-        c->tune = lf_tune{16, 16, 32};
+        c->tune = lf_tune{16, 16};
         return LF_OK;
     }
     if (t->tile_w <= 0 || t->tile_h <= 0 || t->tile_w % 8 || t->tile_h % 8 || t->tile_w * t->tile_h > 256)
         return fail(LF_EINVAL, "tile must be multiples of 8 with at most 256 pixels (got %dx%d)", t->tile_w, t->tile_h);
-    if (t->cap < 1 || t->cap > kStage) return fail(LF_EINVAL, "cap must be in [1, %d] (got %d)", kStage, t->cap);
     c->tune = *t;
     return LF_OK;
 }
@@ -496,9 +494,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
     if (rc) return rc;
     const lf_tune t = tune ? *tune : c->batch.tune;
-    if (t.tile_w <= 0 || t.tile_h <= 0 || t.tile_w % 8 || t.tile_h % 8 || t.tile_w * t.tile_h > 256 || t.cap < 1 ||
-        t.cap > kStage)
-        return fail(LF_EINVAL, "invalid tune %dx%d cap %d", t.tile_w, t.tile_h, t.cap);
+    if (t.tile_w <= 0 || t.tile_h <= 0 || t.tile_w % 8 || t.tile_h % 8 || t.tile_w * t.tile_h > 256)
+        return fail(LF_EINVAL, "invalid tune %dx%d", t.tile_w, t.tile_h);
     hipStream_t s = (hipStream_t)hip_stream;
     lf_ctx::Batch &B = c->batch;
 
@@ -559,7 +556,6 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     a.out_rgb = out_rgb;
     a.out_wsum = out_wsum;
     a.out_count = out_count;
-    a.cap = t.cap;
     BatchArgs b;
     b.eyes = B.eyes_dev;
     b.n_eyes = n_eyes;
@@ -576,8 +572,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     std::string key;
     {
         char buf[256];
-        snprintf(buf, sizeof buf, "%d|%.17g|%p|%p|%p|%p|%d|%d|%d|%d|", n_eyes, hfov_deg, (void *)out_rgb,
-                 (void *)out_wsum, (void *)out_count, B.buf, t.tile_w, t.tile_h, t.cap, c->profiling ? 1 : 0);
+        snprintf(buf, sizeof buf, "%d|%.17g|%p|%p|%p|%p|%d|%d|%d|", n_eyes, hfov_deg, (void *)out_rgb,
+                 (void *)out_wsum, (void *)out_count, B.buf, t.tile_w, t.tile_h, c->profiling ? 1 : 0);
         key = buf;
         for (int32_t k = 0; k < n_eyes; ++k) key += std::to_string(res[2 * k]) + "x" + std::to_string(res[2 * k + 1]) + ",";
     }
@@ -655,7 +651,6 @@ int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (reps < 1 || reps > 100) return fail(LF_EINVAL, "reps must be in [1,100]");
     static const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
-    static const int caps[3] = {8, 16, 32};
     hipStream_t s = (hipStream_t)hip_stream;
     hipEvent_t ea, eb;
     LF_HIP(hipEventCreate(&ea), "hipEventCreate");
@@ -665,8 +660,8 @@ int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov
     float best_ms = INFINITY;
     lf_tune bt = c->batch.tune;
     int rc = LF_OK;
-    for (int i = 0; i < 9 && rc == LF_OK; ++i) {
-        lf_tune t{shapes[i / 3][0], shapes[i / 3][1], caps[i % 3]};
+    for (int i = 0; i < 3 && rc == LF_OK; ++i) {
+        lf_tune t{shapes[i][0], shapes[i][1]};
         rc = lf_render_batch(c, eyes, n_eyes, hfov_deg, res, out_rgb, nullptr, nullptr, &t, hip_stream);  // capture + warm
         std::vector<float> times;
         for (int r = 0; r < reps && rc == LF_OK; ++r) {

@@ -41,7 +41,6 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
                 }
             }
     }
-    const void *cells = geo_fmt == 0 ? (const void *)c32.data() : (const void *)c16.data();
     for (int v = 0; v < n; ++v) {
         float lo = INFINITY, hi = -INFINITY;
         for (int b = 0; b < NB * NB; ++b) {
@@ -49,8 +48,9 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
             float blo = INFINITY, bhi = -INFINITY;
             for (int k = bk * kBlk; k < std::min(bk * kBlk + kBlk, Mc); ++k)
                 for (int j = bi * kBlk; j < std::min(bi * kBlk + kBlk, Mc); ++j) {
-                    const float4 q = geo_fmt == 0 ? load_cell<0>(cells, (int64_t)v * per + (int64_t)k * Mc + j)
-                                                  : load_cell<1>(cells, (int64_t)v * per + (int64_t)k * Mc + j);
+                    const uint32_t idx = (uint32_t)(k * Mc + j);
+                    const float4 q = geo_fmt == 0 ? load_cell<0>(c32.data() + (size_t)v * per, idx)
+                                                  : load_cell<1>(c16.data() + (size_t)v * per, idx);
                     blo = fminf(blo, fminf(fminf(q.x, q.y), fminf(q.z, q.w)));
                     bhi = fmaxf(bhi, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
                 }

@@ -9,7 +9,6 @@ namespace lf {
 
 constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
-constexpr int kStage = 64;             // candidate views staged in LDS per pass (upper bound of tune.cap)
 constexpr int kBlk = 8;                // mesh cells per side of an inverse-depth bounds block
 constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
 constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
@@ -78,7 +77,6 @@ struct RenderArgs {
     float *out_rgb;
     float *out_wsum;
     uint8_t *out_count;
-    int32_t cap;                // views staged per LDS pass
     // sub-pixel (reference) passes: ray through (x + sub_x, y + sub_y); out += scale * L
     float sub_x, sub_y, scale;
     int32_t accumulate;

@@ -9,7 +9,8 @@
 //             compacted into an LDS list with a wavefront ballot and prefix
 //             popcount, then written out (the GPU counterpart of the paper's
 //             per-tile visibility culling, Sec. 3.2.1 and Sec. 6.2).
-//   k_render  per screen tile: the tile's candidate views are staged in LDS;
+//   k_render  per screen tile: the tile's candidate list and each candidate's
+//             per-view record are wave-uniform and read by the scalar unit;
 //             every pixel tests each candidate's disk exactly, intersects its
 //             ray with the view's mesh, samples the view's image bilinearly and
 //             accumulates rho-weighted colour and rho in FP32 registers; the
@@ -24,9 +25,10 @@
 // inverse depths over the regular grid, and the ray is the straight line
 // w -> (V + w D, w). The nearest hit along the ray (intra-image occlusion,
 // Sec. 3.2.2) is the LARGEST w at which the line meets the field; the kernel
-// walks grid cells from the view's largest inverse depth downwards, finds the
-// first sign change of field(w) - w on each linear piece (cells split along
-// their diagonal), and interpolates it. (s, t) = V + w_hit D exactly.
+// walks grid cells from the view's largest inverse depth downwards (blocks of
+// cells first, skipping those whose inverse-depth range the line misses) and
+// solves, in each cell, the two triangles' planes against the line in closed
+// form; the first cell holding a root gives w_hit. (s, t) = V + w_hit D.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -101,11 +103,11 @@ __global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cell
 template <int GEO>
 __global__ __launch_bounds__(256) void k_geo_range(const void *__restrict__ cells, int32_t M,
                                                    float2 *__restrict__ wr) {
-    const int64_t per = (int64_t)(M - 1) * (M - 1);
-    const int64_t base = (int64_t)blockIdx.x * per;
+    const int per = (M - 1) * (M - 1);
+    const void *view = static_cast<const char *>(cells) + (int64_t)blockIdx.x * per * (GEO == 0 ? 16 : 8);
     float lo = INFINITY, hi = -INFINITY;
-    for (int64_t c = threadIdx.x; c < per; c += blockDim.x) {
-        const float4 q = load_cell<GEO>(cells, base + c);
+    for (int c = threadIdx.x; c < per; c += blockDim.x) {
+        const float4 q = load_cell<GEO>(view, (uint32_t)c);
         lo = fminf(lo, fminf(fminf(q.x, q.y), fminf(q.z, q.w)));
         hi = fmaxf(hi, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
     }
@@ -135,10 +137,11 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
         const int r = (int)(b % ((int64_t)NB * NB));
         const int bk = r / NB, bi = r % NB;
         const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc), k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc);
+        const void *view = static_cast<const char *>(cells) + v * Mc * Mc * (GEO == 0 ? 16 : 8);
         float lo = INFINITY, hi = -INFINITY;
         for (int k = k0; k < k1; ++k)
             for (int j = j0; j < j1; ++j) {
-                const float4 q = load_cell<GEO>(cells, v * (int64_t)Mc * Mc + (int64_t)k * Mc + j);
+                const float4 q = load_cell<GEO>(view, (uint32_t)(k * Mc + j));
                 lo = fminf(lo, fminf(fminf(q.x, q.y), fminf(q.z, q.w)));
                 hi = fmaxf(hi, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
             }
@@ -375,11 +378,36 @@ __global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const Eye
 // ---------------------------------------------------------------------------------------------
 // fused reproject + gather + blend
 
+// Read-only data at a wave-uniform address, fetched by the scalar unit into
+// SGPRs (a constant-address-space load). The data must not be written while
+// the kernel runs; every table read this way is produced by an earlier kernel.
+// Read dword by dword: the scalar unit loads 1, 2, 4, 8 or 16 dwords, and
+// adjacent dword loads are merged into those widths.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "dword-granular records only");
+#if defined(__HIP_DEVICE_COMPILE__)
+    union {
+        T t;
+        uint32_t w[sizeof(T) / 4];
+    } u;
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = q[i];
+    return u.t;
+#else
+    return *p;
+#endif
+}
+
 // One screen tile of eye E (index e) by one workgroup of tile_w x tile_h
-// threads; sv is the workgroup's LDS staging area for candidate views.
+// threads. Each candidate view's record and the per-view base addresses are
+// wave-uniform and live in SGPRs; a lane holds only its own ray's state.
 template <int IMG, int GEO, int MODE>
 __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, int tile_w, int tile_h,
-                                            const RenderArgs &a, EyeView *sv) {
+                                            const RenderArgs &a) {
+    tile = __builtin_amdgcn_readfirstlane(tile);
+    e = __builtin_amdgcn_readfirstlane(e);
     const int local = tile - E.tile_off;
     const int tx0 = (local % E.tiles_x) * tile_w, ty0 = (local / E.tiles_x) * tile_h;
     // one 8x8 pixel block per wavefront
@@ -394,58 +422,54 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     const float Y = (1.0f - 2.0f * ((float)py + sub_y) / (float)E.H) * E.ty;
     const int64_t pix = E.pix_off + (int64_t)py * E.W + px;
 
-    const int cnt = a.tile_count[tile];
+    const int cnt = uniform_load(a.tile_count + tile);
     const bool overflow = cnt > kListCap;
     const int total = overflow ? a.n_views : cnt;
     const EyeView *eve = a.ev + (int64_t)e * a.n_views;
-    const uint16_t *tl = a.tile_list + (int64_t)tile * kListCap;
+    // the list's 16-bit entries, read in pairs (the list of a tile starts 4-byte aligned)
+    const uint32_t *tl = reinterpret_cast<const uint32_t *>(a.tile_list + (int64_t)tile * kListCap);
+    const int64_t geo_bytes = a.cells_per_view * (GEO == 0 ? 16 : 8);
+    const int64_t img_bytes = a.texels_per_view * (IMG == 0 ? 4 : (IMG == 1 ? 8 : 16));
 
     float accr = 0.0f, accg = 0.0f, accb = 0.0f, ws = 0.0f;
     int nc = 0, nh = 0, n_tests = 0, n_cells = 0;
-    for (int base = 0; base < total; base += a.cap) {
-        const int nb = min(a.cap, total - base);
-        // stage nb EyeView entries (64 B each) as float4 quarters
-        for (int q = threadIdx.x; q < nb * 4; q += blockDim.x) {
-            const int s = q >> 2;
-            const int vid = overflow ? base + s : (int)tl[base + s];
-            reinterpret_cast<float4 *>(&sv[s])[q & 3] = reinterpret_cast<const float4 *>(&eve[vid])[q & 3];
-        }
-        __syncthreads();
-        if (inside) {
-            for (int c = 0; c < nb; ++c) {
-                const EyeView &v = sv[c];
-                RayView rv;
-                ++n_tests;
-                if (!disk_test(v, X, Y, a.R, a.invR, rv)) continue;
-                if (MODE == MODE_STATS) ++nc;
-                if (MODE == MODE_DEBUG) {
-                    if (nc < a.dbg_cap) a.dbg_cand[pix * a.dbg_cap + nc] = v.view;
-                    ++nc;
-                }
-                float wh;
-                const void *cells = reinterpret_cast<const char *>(a.geo) +
-                                    (int64_t)v.view * a.cells_per_view * (GEO == 0 ? 16 : 8);
-                if (!march<GEO>(cells, a.blk + (int64_t)v.view * a.NB * a.NB, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax,
-                                rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, n_cells))
-                    continue;
-                if (MODE == MODE_DEBUG) {
-                    if (nh < a.dbg_cap) a.dbg_contrib[pix * a.dbg_cap + nh] = v.view;
-                    ++nh;
-                    continue;
-                }
-                const float Xs = fmaf(wh, rv.Dx, rv.Vx), Ys = fmaf(wh, rv.Dy, rv.Vy);
-                const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
-                const void *img = reinterpret_cast<const char *>(a.img) +
-                                  (int64_t)v.view * a.texels_per_view * (IMG == 0 ? 4 : (IMG == 1 ? 8 : 16));
-                const Rgb col = bilinear<IMG>(img, a.img_w, a.img_h, tpx, tpy);
-                accr = fmaf(rv.rho, col.r, accr);
-                accg = fmaf(rv.rho, col.g, accg);
-                accb = fmaf(rv.rho, col.b, accb);
-                ws += rv.rho;
-                ++nh;
+    if (inside) {
+        for (int c = 0; c < total; ++c) {
+            int vid = c;
+            if (!overflow) {
+                const uint32_t pair = uniform_load(tl + (c >> 1));
+                vid = (c & 1) ? (int)(pair >> 16) : (int)(pair & 0xffffu);
             }
+            const EyeView v = uniform_load(eve + vid);
+            RayView rv;
+            ++n_tests;
+            if (!disk_test(v, X, Y, a.R, a.invR, rv)) continue;
+            if (MODE == MODE_STATS) ++nc;
+            if (MODE == MODE_DEBUG) {
+                if (nc < a.dbg_cap) a.dbg_cand[pix * a.dbg_cap + nc] = v.view;
+                ++nc;
+            }
+            float wh;
+            const void *cells = reinterpret_cast<const char *>(a.geo) + (int64_t)v.view * geo_bytes;
+            const float2 *blk = a.blk + (int64_t)v.view * a.NB * a.NB;
+            if (!march<GEO>(cells, blk, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh,
+                            n_cells))
+                continue;
+            if (MODE == MODE_DEBUG) {
+                if (nh < a.dbg_cap) a.dbg_contrib[pix * a.dbg_cap + nh] = v.view;
+                ++nh;
+                continue;
+            }
+            const float Xs = fmaf(wh, rv.Dx, rv.Vx), Ys = fmaf(wh, rv.Dy, rv.Vy);
+            const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
+            const void *img = reinterpret_cast<const char *>(a.img) + (int64_t)v.view * img_bytes;
+            const Rgb col = bilinear<IMG>(img, a.img_w, a.img_h, tpx, tpy);
+            accr = fmaf(rv.rho, col.r, accr);
+            accg = fmaf(rv.rho, col.g, accg);
+            accb = fmaf(rv.rho, col.b, accb);
+            ws += rv.rho;
+            ++nh;
         }
-        __syncthreads();
     }
     if (MODE == MODE_STATS) {
         // block-wide sums, one atomic per counter per block
@@ -496,10 +520,9 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
 
 template <int IMG, int GEO, int MODE>
 __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderArgs a) {
-    __shared__ EyeView sv[kStage];
     const int tile = blockIdx.x;
     const int e = find_eye(ch, tile);
-    render_tile<IMG, GEO, MODE>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a, sv);
+    render_tile<IMG, GEO, MODE>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a);
 }
 
 // Persistent form for batches: a grid sized to the machine; each workgroup
@@ -512,7 +535,6 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
 template <int IMG, int GEO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void
 k_render_persistent(const BatchArgs b, const RenderArgs a) {
-    __shared__ EyeView sv[kStage];
     __shared__ int s_tile;
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(b.queue, 1u);
     __syncthreads();
@@ -533,12 +555,12 @@ k_render_persistent(const BatchArgs b, const RenderArgs a) {
                 }
                 t0 = wall_clock64();
             }
-            E = b.eyes[e];
+            E = uniform_load(b.eyes + e);
             cur_e = e;
             lo = E.tile_off;
             hi = lo + E.tiles_x * E.tiles_y;
         }
-        render_tile<IMG, GEO, MODE_RENDER>(E, cur_e, tile, b.tile_w, b.tile_h, a, sv);
+        render_tile<IMG, GEO, MODE_RENDER>(E, cur_e, tile, b.tile_w, b.tile_h, a);
         if (threadIdx.x == 0) t1 = wall_clock64();
         __syncthreads();  // the prefetched index is visible
         tile = s_tile;

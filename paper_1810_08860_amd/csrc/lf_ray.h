@@ -38,24 +38,33 @@ struct Rgb {
     float r, g, b;
 };
 
+// Element idx of an array that starts at base, with the byte offset formed in
+// 32 bits: every array indexed this way is one view's share (well under
+// 4 GiB), so a wave-uniform base plus a 32-bit per-lane offset addresses it.
+template <typename T>
+LF_HD const T &at(const void *__restrict__ base, uint32_t idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (uint32_t)sizeof(T));
+}
+
+// Texel idx (row-major) of one view's image.
 template <int IMG>
-LF_HD Rgb texel(const void *__restrict__ img, int64_t idx);
+LF_HD Rgb texel(const void *__restrict__ img, uint32_t idx);
 
 template <>
-LF_HD Rgb texel<0>(const void *__restrict__ img, int64_t idx) {  // RGBA8, 0..255
-    const uint32_t p = reinterpret_cast<const uint32_t *>(img)[idx];
+LF_HD Rgb texel<0>(const void *__restrict__ img, uint32_t idx) {  // RGBA8, 0..255
+    const uint32_t p = at<uint32_t>(img, idx);
     return {(float)(p & 255u), (float)((p >> 8) & 255u), (float)((p >> 16) & 255u)};
 }
 template <>
-LF_HD Rgb texel<1>(const void *__restrict__ img, int64_t idx) {  // RGBA16F
-    uint2 p = reinterpret_cast<const uint2 *>(img)[idx];
+LF_HD Rgb texel<1>(const void *__restrict__ img, uint32_t idx) {  // RGBA16F
+    uint2 p = at<uint2>(img, idx);
     __half2 rg = *reinterpret_cast<__half2 *>(&p.x);
     __half2 ba = *reinterpret_cast<__half2 *>(&p.y);
     return {__low2float(rg), __high2float(rg), __low2float(ba)};
 }
 template <>
-LF_HD Rgb texel<2>(const void *__restrict__ img, int64_t idx) {  // RGBA32F
-    float4 p = reinterpret_cast<const float4 *>(img)[idx];
+LF_HD Rgb texel<2>(const void *__restrict__ img, uint32_t idx) {  // RGBA32F
+    float4 p = at<float4>(img, idx);
     return {p.x, p.y, p.z};
 }
 
@@ -65,16 +74,17 @@ LF_HD float texel_scale() { return IMG == 0 ? (1.0f / 255.0f) : 1.0f; }
 
 // Corner inverse depths of one mesh cell: (w00, w10, w01, w11) with j to the
 // right and k downwards.
+// idx is the cell's index within one view (k * (M - 1) + j).
 template <int GEO>
-LF_HD float4 load_cell(const void *__restrict__ cells, int64_t idx);
+LF_HD float4 load_cell(const void *__restrict__ cells, uint32_t idx);
 
 template <>
-LF_HD float4 load_cell<0>(const void *__restrict__ cells, int64_t idx) {
-    return reinterpret_cast<const float4 *>(cells)[idx];
+LF_HD float4 load_cell<0>(const void *__restrict__ cells, uint32_t idx) {
+    return at<float4>(cells, idx);
 }
 template <>
-LF_HD float4 load_cell<1>(const void *__restrict__ cells, int64_t idx) {
-    uint2 p = reinterpret_cast<const uint2 *>(cells)[idx];
+LF_HD float4 load_cell<1>(const void *__restrict__ cells, uint32_t idx) {
+    uint2 p = at<uint2>(cells, idx);
     __half2 a = *reinterpret_cast<__half2 *>(&p.x);
     __half2 b = *reinterpret_cast<__half2 *>(&p.y);
     return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
@@ -108,98 +118,95 @@ LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
 
 LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 
-// Inverse depth of the cell's mesh at local (fx, fy): triangle (00,10,11) where
-// fx >= fy, triangle (00,11,01) otherwise.
-LF_HD float field(const float4 &c, float fx, float fy) {
-    return fx >= fy ? fmaf(fy, c.w - c.y, fmaf(fx, c.y - c.x, c.x))
-                    : fmaf(fx, c.w - c.z, fmaf(fy, c.z - c.x, c.x));
+// Tolerances of the per-cell root test: a root counts if it lies on the
+// cell's piece of the line up to kTolW x (largest w of the walk) and on its
+// triangle's side of the diagonal up to kTolD cells. Both sit far below the
+// rounding of a sample position yet far above the rounding of the root, so a
+// crossing on an edge shared by two cells or triangles is found from either
+// side (the mesh is continuous, so both sides give the same point).
+constexpr float kTolW = 4e-6f;
+constexpr float kTolD = 1e-5f;
+
+// Largest root of (mesh inverse depth - w) on one cell's piece of the line.
+// The piece enters the cell at w0 with cell-local coordinates (fx0, fy0) and
+// leaves at w0 + T (T <= 0); fx, fy move by (bx, by) per unit of w and
+// dbb = bx - by. Triangle A (fx >= fy) interpolates (w00, w10, w11) and
+// triangle B (fx < fy) interpolates (w00, w11, w01); on each the difference
+// is linear in t = w - w0, so its root is g / (1 - beta) in closed form.
+LF_HD bool cell_root(const float4 &c, float fx0, float fy0, float w0, float T, float bx, float by, float dbb,
+                     float tol, float &t) {
+    const float d0 = fx0 - fy0;
+    const float a1 = c.y - c.x, a2 = c.w - c.y;
+    const float gA = fmaf(fy0, a2, fmaf(fx0, a1, c.x)) - w0;
+    const float tA = gA * fast_rcp(1.0f - fmaf(by, a2, bx * a1));
+    const float b1 = c.w - c.z, b2 = c.z - c.x;
+    const float gB = fmaf(fy0, b2, fmaf(fx0, b1, c.x)) - w0;
+    const float tB = gB * fast_rcp(1.0f - fmaf(by, b2, bx * b1));
+    const bool okA = tA <= tol && tA >= T - tol && fmaf(dbb, tA, d0) >= -kTolD;
+    const bool okB = tB <= tol && tB >= T - tol && fmaf(dbb, tB, d0) <= kTolD;
+    t = fmaxf(okA ? tA : -INFINITY, okB ? tB : -INFINITY);
+    return okA || okB;
 }
 
-LF_HD bool crosses(float g0, float g1) {
-    return (g0 < 0.0f && g1 >= 0.0f) || (g0 > 0.0f && g1 <= 0.0f);
-}
-
-// Walk the cells of one block from w = ws down to w = we (ws >= we), starting
-// in the cell that holds the line at ws (clamped to the block's cells
-// [j0, j1] x [k0, k1]). `sgn` is the sign of field - w just above ws (0 if
-// unknown); on return it holds the sign at we. True with w_hit on a crossing.
+// Walk the cells of one block, [j0, j1] x [k0, k1], along the line from
+// w = ws down to w = we (ws >= we), starting in the cell that holds the line
+// at ws. True with w_hit at the first (largest-w) root. wxe / wye hold the w
+// at which the line leaves the current cell through its x / y edge; a step
+// moves them by dwx = -|1/bx| / dwy = -|1/by| (0 for an axis the line does
+// not cross).
 template <int GEO>
-LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx, float ibx,
-                                           bool mx, float ay, float by, float iby, bool my, int j0, int j1, int k0,
-                                           int k1, float ws, float we, int &sgn, float &w_hit, int &n_cells) {
+LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx, float ibx, float ay, float by,
+                      float iby, float dwx, float dwy, float tol, int j0, int j1, int k0, int k1, float ws, float we,
+                      float &w_hit, int &n_cells) {
     const int sx = bx > 0.0f ? -1 : 1, sy = by > 0.0f ? -1 : 1;  // cell steps as w decreases
-    const float ox = bx > 0.0f ? 0.0f : 1.0f, oy = by > 0.0f ? 0.0f : 1.0f;
+    const float dbb = bx - by;
     float w0 = ws;
     const float gx = fmaf(w0, bx, ax), gy = fmaf(w0, by, ay);
     int j = min(max((int)floorf(gx), j0), j1);
     int k = min(max((int)floorf(gy), k0), k1);
-    float4 cw = load_cell<GEO>(cells, (int64_t)k * Mc + j);
-    ++n_cells;
-    float fx0 = sat01(gx - (float)j), fy0 = sat01(gy - (float)k);
-    float g0 = field(cw, fx0, fy0) - w0;
-    if (g0 == 0.0f || (sgn < 0 && g0 > 0.0f) || (sgn > 0 && g0 < 0.0f)) {
-        w_hit = w0;
-        return true;
-    }
-    for (int it = 0; it < 64; ++it) {
-        // inverse depth at which the line leaves cell (j, k)
-        const float wxe = mx ? ((float)j + ox - ax) * ibx : -INFINITY;
-        const float wye = my ? ((float)k + oy - ay) * iby : -INFINITY;
+    float fj = (float)j, fk = (float)k;
+    float fx0 = sat01(gx - fj), fy0 = sat01(gy - fk);
+    float wxe = dwx != 0.0f ? ((bx > 0.0f ? fj : fj + 1.0f) - ax) * ibx : -INFINITY;
+    float wye = dwy != 0.0f ? ((by > 0.0f ? fk : fk + 1.0f) - ay) * iby : -INFINITY;
+    for (int it = 0; it < 2 * kBlk + 2; ++it) {
         const float wn = fmaxf(wxe, wye);
         const bool last = !(wn > we);
         const float w1 = last ? we : fminf(wn, w0);
-        const float fx1 = sat01(fmaf(w1, bx, ax) - (float)j), fy1 = sat01(fmaf(w1, by, ay) - (float)k);
-        const float d0 = fx0 - fy0, d1 = fx1 - fy1;
-        if ((d0 > 0.0f && d1 < 0.0f) || (d0 < 0.0f && d1 > 0.0f)) {
-            // the segment crosses the cell diagonal: two linear pieces
-            const float s = d0 * fast_rcp(d0 - d1);
-            const float wd = fmaf(s, w1 - w0, w0);
-            const float fd = fmaf(s, fx1 - fx0, fx0);
-            const float gd = field(cw, fd, fd) - wd;
-            if (crosses(g0, gd)) {
-                w_hit = fmaf(wd - w0, g0 * fast_rcp(g0 - gd), w0);
-                return true;
-            }
-            w0 = wd;
-            g0 = gd;
-            fx0 = fd;
-            fy0 = fd;
-        }
-        const float g1 = field(cw, fx1, fy1) - w1;
-        if (crosses(g0, g1)) {
-            w_hit = fmaf(w1 - w0, g0 * fast_rcp(g0 - g1), w0);
+        const float4 c = load_cell<GEO>(cells, (uint32_t)(k * Mc + j));
+        ++n_cells;
+        float t;
+        if (cell_root(c, fx0, fy0, w0, w1 - w0, bx, by, dbb, tol, t)) {
+            w_hit = w0 + t;
             return true;
         }
-        if (last) {
-            sgn = g1 > 0.0f ? 1 : -1;
-            return false;
+        if (last) return false;
+        if (wxe == wn) {
+            j += sx;
+            fj += (float)sx;
+            wxe += dwx;
         }
-        if (wxe == wn) j += sx;
-        if (wye == wn) k += sy;
-        if (j < j0 || j > j1 || k < k0 || k > k1) {
-            sgn = g1 > 0.0f ? 1 : -1;
-            return false;
+        if (wye == wn) {
+            k += sy;
+            fk += (float)sy;
+            wye += dwy;
         }
-        cw = load_cell<GEO>(cells, (int64_t)k * Mc + j);
-        ++n_cells;
-        fx0 = sat01(fmaf(w1, bx, ax) - (float)j);
-        fy0 = sat01(fmaf(w1, by, ay) - (float)k);
+        if (j < j0 || j > j1 || k < k0 || k > k1) return false;
+        fx0 = sat01(fmaf(w1, bx, ax) - fj);
+        fy0 = sat01(fmaf(w1, by, ay) - fk);
         w0 = w1;
-        g0 = g1;
     }
-    sgn = g0 > 0.0f ? 1 : -1;
     return false;
 }
 
 // Largest w in [wlo, whi] at which the line (V + w D, w) meets the view's
 // mesh; false if it never does. Two levels: blocks of kBlk x kBlk cells
-// carry the min / max inverse depth of their vertices, and a crossing inside
-// a block must lie in that range, so each block's cells are walked only over
-// the part of the line whose w falls inside the block's range.
+// carry the min / max inverse depth of their vertices, and a root inside a
+// block lies in that range, so each block's cells are walked only over the
+// part of the line whose w falls inside the block's range.
 template <int GEO>
 LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk, int M, int NB, float sM,
-                      float cM, float wlo, float whi, float Vx, float Vy, float Dx, float Dy, float &w_hit,
-                      int &n_cells) {
+                 float cM, float wlo, float whi, float Vx, float Vy, float Dx, float Dy, float &w_hit,
+                 int &n_cells) {
     const float lim = (float)(M - 1);
     const float ax = fmaf(Vx, sM, cM), bx = Dx * sM;
     const float ay = fmaf(-Vy, sM, cM), by = -Dy * sM;
@@ -224,10 +231,11 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
 
     const int Mc = M - 1;
     const int sbx = bx > 0.0f ? -1 : 1, sby = by > 0.0f ? -1 : 1;
+    const float dwx = -fabsf(ibx), dwy = -fabsf(iby);
+    const float tol = kTolW * fabsf(whi);
     float w0 = whi;
-    int bi = min(max((int)floorf(fmaf(w0, bx, ax)), 0), M - 2) / kBlk;
-    int bk = min(max((int)floorf(fmaf(w0, by, ay)), 0), M - 2) / kBlk;
-    int sgn = 0;  // sign of field - w just above w0 (0: not known yet)
+    int bi = (int)((unsigned)min(max((int)floorf(fmaf(w0, bx, ax)), 0), Mc - 1) / kBlk);
+    int bk = (int)((unsigned)min(max((int)floorf(fmaf(w0, by, ay)), 0), Mc - 1) / kBlk);
     for (int it = 0; it < 2 * NB + 4; ++it) {
         const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc) - 1;
         const int k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc) - 1;
@@ -237,23 +245,11 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
         const float wn = fmaxf(wxe, wye);
         const bool last = !(wn > wlo);
         const float wb1 = last ? wlo : fminf(wn, w0);
-        const float2 bb = blk[bk * NB + bi];
+        const float2 bb = at<float2>(blk, (uint32_t)(bk * NB + bi));
         const float ws = fminf(w0, bb.y), we = fmaxf(wb1, bb.x);
-        if (ws >= we) {
-            // part of the line above the block's surface (w > max): field - w < 0
-            int s = ws < w0 ? -1 : sgn;
-            if (walk_cells<GEO>(cells, Mc, ax, bx, ibx, mx, ay, by, iby, my, j0, j1, k0, k1, ws, we, s, w_hit,
-                                n_cells))
-                return true;
-            sgn = we > wb1 ? 1 : s;  // below the block's surface (w < min): field - w > 0
-        } else {
-            const int s = w0 < bb.x ? 1 : -1;
-            if (sgn != 0 && s != sgn) {  // sign flips exactly on the block boundary
-                w_hit = w0;
-                return true;
-            }
-            sgn = s;
-        }
+        if (ws >= we && walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, dwx, dwy, tol, j0, j1, k0, k1, ws, we,
+                                        w_hit, n_cells))
+            return true;
         if (last) return false;
         if (wxe == wn) bi += sbx;
         if (wye == wn) bk += sby;
@@ -273,8 +269,9 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float p
     int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
     x0 = min(max(x0, 0), W - 1);
     y0 = min(max(y0, 0), H - 1);
-    const Rgb a = texel<IMG>(img, (int64_t)y0 * W + x0), b = texel<IMG>(img, (int64_t)y0 * W + x1);
-    const Rgb c = texel<IMG>(img, (int64_t)y1 * W + x0), d = texel<IMG>(img, (int64_t)y1 * W + x1);
+    const uint32_t r0 = (uint32_t)(y0 * W), r1 = (uint32_t)(y1 * W);
+    const Rgb a = texel<IMG>(img, r0 + x0), b = texel<IMG>(img, r0 + x1);
+    const Rgb c = texel<IMG>(img, r1 + x0), d = texel<IMG>(img, r1 + x1);
     const float tr = fmaf(fx, b.r - a.r, a.r), tg = fmaf(fx, b.g - a.g, a.g), tb = fmaf(fx, b.b - a.b, a.b);
     const float br = fmaf(fx, d.r - c.r, c.r), bg = fmaf(fx, d.g - c.g, c.g), bb = fmaf(fx, d.b - c.b, c.b);
     return {fmaf(fy, br - tr, tr), fmaf(fy, bg - tg, tg), fmaf(fy, bb - tb, tb)};

@@ -35,7 +35,7 @@ class lf_eye(ctypes.Structure):
 
 
 class lf_tune(ctypes.Structure):
-    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("cap", ctypes.c_int32)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
 class LFError(RuntimeError):
@@ -185,10 +185,10 @@ def lf_stereo_eyes(head_pos, head_rot, ipd_m):
     return out
 
 
-def lf_set_tune(ctx: Context, tile_w=None, tile_h=None, cap=None):
+def lf_set_tune(ctx: Context, tile_w=None, tile_h=None):
     if tile_w is None:
         return _check(lib().lf_set_tune(ctx.handle, None))
-    t = lf_tune(int(tile_w), int(tile_h), int(cap))
+    t = lf_tune(int(tile_w), int(tile_h))
     return _check(lib().lf_set_tune(ctx.handle, ctypes.byref(t)))
 
 
@@ -231,18 +231,18 @@ def lf_render_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, o
                                  _ptr(out_wsum), _ptr(out_count), t, _stream(stream)))
 
 
-TUNE_GRID = [(tw, th, cap) for tw, th in ((8, 8), (16, 16), (32, 8)) for cap in (8, 16, 32)]
+TUNE_GRID = [(8, 8), (16, 16), (32, 8)]
 
 
 def lf_autotune_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, reps=5, stream=None):
-    """Returns ((tile_w, tile_h, cap) chosen, {config: median ms})."""
+    """Returns ((tile_w, tile_h) chosen, {tile shape: median ms})."""
     e = make_eyes(eyes)
     r = _res(res, len(e))
     best = lf_tune()
-    ms = np.zeros(9, np.float32)
+    ms = np.zeros(len(TUNE_GRID), np.float32)
     _check(lib().lf_autotune_batch(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb), int(reps),
                                    ctypes.byref(best), ms.ctypes.data, _stream(stream)))
-    return (best.tile_w, best.tile_h, best.cap), dict(zip(TUNE_GRID, ms.tolist()))
+    return (best.tile_w, best.tile_h), dict(zip(TUNE_GRID, ms.tolist()))
 
 
 def lf_batch_frame_times(ctx: Context, n_eyes):
