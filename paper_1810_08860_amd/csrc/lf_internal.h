@@ -9,7 +9,7 @@ namespace lf {
 
 constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
-constexpr int kBlk = 8;                // mesh cells per side of an inverse-depth bounds block
+constexpr int kBlk = 16;               // mesh cells per side of an inverse-depth bounds block
 constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
 constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
 constexpr int kSuperCap = 256;         // super-tile survivor list capacity (exact beyond: every view)

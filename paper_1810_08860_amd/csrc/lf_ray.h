@@ -272,9 +272,11 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float p
     const uint32_t r0 = (uint32_t)(y0 * W), r1 = (uint32_t)(y1 * W);
     const Rgb a = texel<IMG>(img, r0 + x0), b = texel<IMG>(img, r0 + x1);
     const Rgb c = texel<IMG>(img, r1 + x0), d = texel<IMG>(img, r1 + x1);
-    const float tr = fmaf(fx, b.r - a.r, a.r), tg = fmaf(fx, b.g - a.g, a.g), tb = fmaf(fx, b.b - a.b, a.b);
-    const float br = fmaf(fx, d.r - c.r, c.r), bg = fmaf(fx, d.g - c.g, c.g), bb = fmaf(fx, d.b - c.b, c.b);
-    return {fmaf(fy, br - tr, tr), fmaf(fy, bg - tg, tg), fmaf(fy, bb - tb, tb)};
+    // the four tap weights; FP16 taps then feed mixed-precision FMAs directly
+    const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+    return {fmaf(w11, d.r, fmaf(w01, c.r, fmaf(w10, b.r, fmaf(w00, a.r, 0.0f)))),
+            fmaf(w11, d.g, fmaf(w01, c.g, fmaf(w10, b.g, fmaf(w00, a.g, 0.0f)))),
+            fmaf(w11, d.b, fmaf(w01, c.b, fmaf(w10, b.b, fmaf(w00, a.b, 0.0f))))};
 }
 
 }  // namespace lf
