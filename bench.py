@@ -42,11 +42,58 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+RENDER_SOURCES = ("lf_kernels.hip", "lf_ray.h", "lf_internal.h")
+RENDER_KERNEL = "k_render_persistent<1, 1>"
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the render kernels are compiled from."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1810_08860_amd", "csrc", "lf_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in RENDER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_08860_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def _counter_means(path):
+    """{kernel name: {counter: mean value per dispatch}} from a rocprofv3 --pmc CSV."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            acc.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, out_path, commands):
+    """HBM bytes per launch of the batched render kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for a device copy of copy_bytes (the kernel with the largest reading in the
+    calibration runs)."""
+    def pick(path, counter, name=None):
+        m = _counter_means(path)
+        if name is None:
+            return max(v[counter] for v in m.values())
+        hits = [v[counter] for k, v in m.items() if name in k]
+        if not hits:
+            raise SystemExit(f"no kernel matching {name!r} in {path}")
+        return hits[0]
+    cf, cw = pick(copy_fetch_csv, "FETCH_SIZE"), pick(copy_write_csv, "WRITE_SIZE")
+    rf, rw = pick(fetch_csv, "FETCH_SIZE", RENDER_KERNEL), pick(write_csv, "WRITE_SIZE", RENDER_KERNEL)
+    fs, wsc = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    t = {
+        "kernel": f"{RENDER_KERNEL} (FP16 images and geometry, 16 stereo frames of 2 x {EYE_W} x {EYE_H} per launch)",
+        "kernel_hash": kernel_source_hash(),
+        "calibration": {"copy_bytes": copy_bytes, "fetch_kib_read": cf, "write_kib_read": cw,
+                        "fetch_scale": fs, "write_scale": wsc},
+        "variants": {"fp16_batched": {"fetch_kib_raw": rf, "write_kib_raw": rw,
+                                      "fetch_bytes": rf * 1024.0 * fs, "write_bytes": rw * 1024.0 * wsc}},
+        "commands": commands,
+    }
+    with open(out_path, "w") as f:
+        json.dump(t, f, indent=1)
+        f.write("\n")
+    return t
 
 
 def load_traffic(path, variant):
@@ -334,7 +381,17 @@ def main():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="only write --traffic from rocprofv3 --pmc CSVs of the batched render (FETCH_SIZE, "
+                         "WRITE_SIZE) and of --copy-calibration runs (same counters); no GPU use")
+    ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--traffic-commands", default="", help="the profiler commands, ';'-separated, recorded as-is")
     args = ap.parse_args()
+    if args.traffic_from:
+        t = write_traffic(*args.traffic_from, args.traffic_copy_bytes, args.traffic,
+                          [c.strip() for c in args.traffic_commands.split(";") if c.strip()])
+        print(json.dumps(t))
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration // 4

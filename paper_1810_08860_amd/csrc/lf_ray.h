@@ -101,19 +101,18 @@ struct RayView {
 // in the view's tangent plane). False for a back-facing disk or rho <= 0.
 LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
                                           RayView &rv) {
+    // evaluated without early exits (a back-facing view gives garbage that the
+    // final test discards, NaN included)
     const float ez = fmaf(v.m[6], X, fmaf(v.m[7], Y, v.m[8]));
-    if (!(ez > 0.0f)) return false;
     const float iz = fast_rcp(ez);
     const float Vx = fmaf(v.m[0], X, fmaf(v.m[1], Y, v.m[2])) * iz;
     const float Vy = fmaf(v.m[3], X, fmaf(v.m[4], Y, v.m[5])) * iz;
     const float Dx = fmaf(-v.o[2], Vx, v.o[0]);
     const float Dy = fmaf(-v.o[2], Vy, v.o[1]);
     const float r2 = fmaf(Dx, Dx, Dy * Dy);
-    if (!(r2 < R * R)) return false;
     const float rho = fmaf(-fast_sqrt(r2), invR, 1.0f);
-    if (!(rho > 0.0f)) return false;
     rv.Vx = Vx; rv.Vy = Vy; rv.Dx = Dx; rv.Dy = Dy; rv.rho = rho;
-    return true;
+    return ez > 0.0f && r2 < R * R && rho > 0.0f;
 }
 
 LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
@@ -159,6 +158,7 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
                       float iby, float dwx, float dwy, float tol, int j0, int j1, int k0, int k1, float ws, float we,
                       float &w_hit, int &n_cells) {
     const int sx = bx > 0.0f ? -1 : 1, sy = by > 0.0f ? -1 : 1;  // cell steps as w decreases
+    const float fsx = (float)sx, fsy = (float)sy;
     const float dbb = bx - by;
     float w0 = ws;
     const float gx = fmaf(w0, bx, ax), gy = fmaf(w0, by, ay);
@@ -168,34 +168,29 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
     float fx0 = sat01(gx - fj), fy0 = sat01(gy - fk);
     float wxe = dwx != 0.0f ? ((bx > 0.0f ? fj : fj + 1.0f) - ax) * ibx : -INFINITY;
     float wye = dwy != 0.0f ? ((by > 0.0f ? fk : fk + 1.0f) - ay) * iby : -INFINITY;
-    for (int it = 0; it < 2 * kBlk + 2; ++it) {
-        const float wn = fmaxf(wxe, wye);
+    bool found = false, more = true;
+    for (int it = 0; it < 2 * kBlk + 2 && more; ++it) {
+        const bool xs = wxe >= wye, ys = wye >= wxe;  // exit edge(s): both at a corner
+        const float wn = xs ? wxe : wye;
         const bool last = !(wn > we);
-        const float w1 = last ? we : fminf(wn, w0);
+        const float w1 = last ? we : (wn < w0 ? wn : w0);
         const float4 c = load_cell<GEO>(cells, (uint32_t)(k * Mc + j));
         ++n_cells;
         float t;
-        if (cell_root(c, fx0, fy0, w0, w1 - w0, bx, by, dbb, tol, t)) {
-            w_hit = w0 + t;
-            return true;
-        }
-        if (last) return false;
-        if (wxe == wn) {
-            j += sx;
-            fj += (float)sx;
-            wxe += dwx;
-        }
-        if (wye == wn) {
-            k += sy;
-            fk += (float)sy;
-            wye += dwy;
-        }
-        if (j < j0 || j > j1 || k < k0 || k > k1) return false;
+        found = cell_root(c, fx0, fy0, w0, w1 - w0, bx, by, dbb, tol, t);
+        w_hit = w0 + t;
+        j += xs ? sx : 0;
+        fj += xs ? fsx : 0.0f;
+        wxe += xs ? dwx : 0.0f;
+        k += ys ? sy : 0;
+        fk += ys ? fsy : 0.0f;
+        wye += ys ? dwy : 0.0f;
+        more = !found && !last && j >= j0 && j <= j1 && k >= k0 && k <= k1;
         fx0 = sat01(fmaf(w1, bx, ax) - fj);
         fy0 = sat01(fmaf(w1, by, ay) - fk);
         w0 = w1;
     }
-    return false;
+    return found;
 }
 
 // Largest w in [wlo, whi] at which the line (V + w D, w) meets the view's
@@ -212,20 +207,16 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
     const float ay = fmaf(-Vy, sM, cM), by = -Dy * sM;
     const bool mx = fabsf(bx) > 1e-20f, my = fabsf(by) > 1e-20f;
     const float ibx = mx ? fast_rcp(bx) : 0.0f, iby = my ? fast_rcp(by) : 0.0f;
-    // clip to the mesh domain 0 <= g <= M-1 on both axes
-    if (mx) {
-        const float w1 = -ax * ibx, w2 = (lim - ax) * ibx;
-        wlo = fmaxf(wlo, fminf(w1, w2));
-        whi = fminf(whi, fmaxf(w1, w2));
-    } else if (!(ax >= 0.0f && ax <= lim)) {
-        return false;
-    }
-    if (my) {
-        const float w1 = -ay * iby, w2 = (lim - ay) * iby;
-        wlo = fmaxf(wlo, fminf(w1, w2));
-        whi = fminf(whi, fmaxf(w1, w2));
-    } else if (!(ay >= 0.0f && ay <= lim)) {
-        return false;
+    // clip to the mesh domain 0 <= g <= M-1 on both axes (an axis the line does
+    // not move along either keeps every w or none)
+    {
+        const float x1 = -ax * ibx, x2 = (lim - ax) * ibx;
+        const float y1 = -ay * iby, y2 = (lim - ay) * iby;
+        const bool inx = ax >= 0.0f && ax <= lim, iny = ay >= 0.0f && ay <= lim;
+        wlo = fmaxf(wlo, fmaxf(mx ? fminf(x1, x2) : (inx ? -INFINITY : INFINITY),
+                               my ? fminf(y1, y2) : (iny ? -INFINITY : INFINITY)));
+        whi = fminf(whi, fminf(mx ? fmaxf(x1, x2) : (inx ? INFINITY : -INFINITY),
+                               my ? fmaxf(y1, y2) : (iny ? INFINITY : -INFINITY)));
     }
     if (!(wlo <= whi)) return false;
 
@@ -236,7 +227,8 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
     float w0 = whi;
     int bi = (int)((unsigned)min(max((int)floorf(fmaf(w0, bx, ax)), 0), Mc - 1) / kBlk);
     int bk = (int)((unsigned)min(max((int)floorf(fmaf(w0, by, ay)), 0), Mc - 1) / kBlk);
-    for (int it = 0; it < 2 * NB + 4; ++it) {
+    bool found = false, more = true;
+    for (int it = 0; it < 2 * NB + 4 && more; ++it) {
         const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc) - 1;
         const int k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc) - 1;
         // inverse depth at which the line leaves the block
@@ -247,16 +239,15 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
         const float wb1 = last ? wlo : fminf(wn, w0);
         const float2 bb = at<float2>(blk, (uint32_t)(bk * NB + bi));
         const float ws = fminf(w0, bb.y), we = fmaxf(wb1, bb.x);
-        if (ws >= we && walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, dwx, dwy, tol, j0, j1, k0, k1, ws, we,
-                                        w_hit, n_cells))
-            return true;
-        if (last) return false;
-        if (wxe == wn) bi += sbx;
-        if (wye == wn) bk += sby;
-        if (bi < 0 || bi >= NB || bk < 0 || bk >= NB) return false;
+        if (ws >= we)
+            found = walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, dwx, dwy, tol, j0, j1, k0, k1, ws, we, w_hit,
+                                    n_cells);
+        bi += wxe == wn ? sbx : 0;
+        bk += wye == wn ? sby : 0;
+        more = !found && !last && bi >= 0 && bi < NB && bk >= 0 && bk < NB;
         w0 = wb1;
     }
-    return false;
+    return found;
 }
 
 // Bilinear sample at normalised image-plane point (Xs, Ys): texel centres at
