@@ -37,7 +37,11 @@ hipError_t corr_loss(const float *rgb, const float *resid, const float *ref, int
                      float *loss_part, int blocks, hipStream_t s);
 hipError_t corr_adam(float *prm, const float *grad, float *m1, float *m2, int32_t n, float lr, float b1, float b2,
                      float eps, float c1, float c2, hipStream_t s);
-hipError_t corr_finish(const float *rgb, const float *resid, int64_t P, float thresh, float *out, uint8_t *fb,
-                       float *resid_out, hipStream_t s);
+// Inference in one persistent kernel (all layers and the finish; grid workgroups).
+hipError_t corr_fused(const float *rgb, const float *wsum, const uint8_t *count, int32_t N, int32_t H, int32_t W,
+                      const uint16_t *wbuf, const float *bbuf, const CorrLayout &L, float thresh, float *out,
+                      uint8_t *fb, float *resid_out, int grid, hipStream_t s);
+int corr_fused_tiles(int32_t N, int32_t H, int32_t W);
+hipError_t corr_fused_occupancy(int *per_cu);
 
 }  // namespace lf

@@ -231,14 +231,27 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
     if (tid < cout_real) pw[nw + tid] = db_acc;
 }
 
-// out[j] = sum over slots of partial[slot][j] (fixed order)
-__global__ void k_reduce_partials(const float *__restrict__ partial, int32_t slots, int32_t len,
-                                  float *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= len) return;
-    float s = 0.0f;
-    for (int k = 0; k < slots; ++k) s += partial[(int64_t)k * len + j];
-    out[j] = s;
+// out[j] = sum over slots of partial[slot][j], in a fixed order: a workgroup
+// covers 64 consecutive j; its 4 waves each sum every 4th slot with 8
+// independent accumulators (8 loads in flight per lane), and the 4 x 8 partial
+// sums of each j are then added in one fixed order.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float *__restrict__ partial, int32_t slots,
+                                                         int32_t len, float *__restrict__ out) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (j < len) {
+        int k = wave;
+        for (; k + 28 < slots; k += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += partial[(int64_t)(k + 4 * u) * len + j];
+        }
+        for (int u = 0; k < slots; k += 4, ++u) acc[u & 7] += partial[(int64_t)k * len + j];
+    }
+    part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (wave == 0 && j < len) out[j] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -338,22 +351,168 @@ __global__ void k_corr_pack(const float *__restrict__ prm, CorrLayout L, uint16_
     }
 }
 
-// out = render + residual, or the render where max |residual| > thresh.
-__global__ void k_corr_finish(const float *__restrict__ rgb, const float *__restrict__ resid, int64_t P,
-                              float thresh, float *__restrict__ out, uint8_t *__restrict__ fb,
-                              float *__restrict__ resid_out) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const float r0 = resid[4 * p], r1 = resid[4 * p + 1], r2 = resid[4 * p + 2];
-        const bool f = fmaxf(fabsf(r0), fmaxf(fabsf(r1), fabsf(r2))) > thresh;
-        out[3 * p] = f ? rgb[3 * p] : rgb[3 * p] + r0;
-        out[3 * p + 1] = f ? rgb[3 * p + 1] : rgb[3 * p + 1] + r1;
-        out[3 * p + 2] = f ? rgb[3 * p + 2] : rgb[3 * p + 2] + r2;
-        if (fb) fb[p] = f ? 1 : 0;
-        if (resid_out) {
-            resid_out[3 * p] = r0;
-            resid_out[3 * p + 1] = r1;
-            resid_out[3 * p + 2] = r2;
+// ---------------------------------------------------------------------------------------------
+// fused inference: all four layers and the finish in one kernel
+//
+// A persistent workgroup takes 16 x 16 output tiles. The layer-1 input is
+// built straight from the render (R, G, B, W / 4, n / 8, zero outside the
+// image) over the tile grown by 4 pixels per side; each layer then computes
+// its output over a region one pixel smaller per side (22^2, 20^2, 18^2,
+// 16^2), entirely in LDS, with activations outside the image set to zero as
+// the per-layer zero padding requires. Every lane holds its B fragments of all
+// four layers in registers for the life of the workgroup (loaded once), so LDS
+// traffic is the A operand only. Regions are linearised row-major and cut into
+// 16-pixel MFMA row blocks; K-steps and packing match k_conv, so each layer
+// accumulates in the same order as the layer-by-layer path.
+constexpr int FT = 16;                                   // output tile side
+constexpr int FR0 = FT + 8, FR1 = FT + 6, FR2 = FT + 4, FR3 = FT + 2;
+constexpr int FPS = 40;                                  // hidden pixel stride: 32 channels + 8 pad
+
+struct FusedTile {
+    int n, x0, y0;  // image and top-left output pixel of the tile
+};
+
+// Two FP32 values as packed BF16 (hardware round to nearest even).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, b16x2));
+}
+
+// One hidden layer (or the last): output region side SOUT from the input
+// region side SOUT + 2; IN8: 8-channel layer-1 input; NBO blocks of 16 output
+// channels. The weights are the MFMA's A operand and the activations its B
+// operand, so D[4 g + v][i] is channel 16 nb + 4 g + v of pixel 16 b + i:
+// each lane stores four consecutive channels of one pixel at once.
+template <int SOUT, bool IN8, int KS, int NBO, bool LAST>
+__device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, uint16_t *__restrict__ dst,
+                                            float *__restrict__ res, const bf16x8 (&w)[KS][NBO],
+                                            const float *__restrict__ s_bias, int ox0, int oy0, int H, int W) {
+    constexpr int SIN = SOUT + 2, NOUT = SOUT * SOUT, NBLK = (NOUT + 15) / 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    for (int b = wave; b < NBLK; b += 4) {
+        const int mm = 16 * b + i;  // this lane's pixel
+        const int m = min(mm, NOUT - 1);
+        const int x = m % SOUT, y = m / SOUT;
+        floatx4 acc[NBO];
+#pragma unroll
+        for (int nb = 0; nb < NBO; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (IN8) {
+                const int t = 4 * s + g;  // four taps of 8 channels per K-step
+                if (t < 9)
+                    av = *reinterpret_cast<const bf16x8 *>(&src[((y + t / 3) * SIN + x + t % 3) * 8]);
+            } else {
+                av = *reinterpret_cast<const bf16x8 *>(&src[((y + s / 3) * SIN + x + s % 3) * FPS + 8 * g]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NBO; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], av, acc[nb], 0, 0, 0);
         }
+        if (mm >= NOUT) continue;
+#pragma unroll
+        for (int nb = 0; nb < NBO; ++nb) {
+            const float4 bi = *reinterpret_cast<const float4 *>(&s_bias[16 * nb + 4 * g]);
+            const float v0 = acc[nb][0] + bi.x, v1 = acc[nb][1] + bi.y, v2 = acc[nb][2] + bi.z, v3 = acc[nb][3] + bi.w;
+            if (LAST) {
+                if (g == 0) *reinterpret_cast<float4 *>(&res[mm * 4]) = make_float4(v0, v1, v2, v3);
+            } else {
+                const int xx = ox0 + x, yy = oy0 + y;
+                uint2 o = make_uint2(0u, 0u);
+                if (xx >= 0 && xx < W && yy >= 0 && yy < H)
+                    o = make_uint2(pack_bf16x2(fmaxf(v0, 0.0f), fmaxf(v1, 0.0f)), pack_bf16x2(fmaxf(v2, 0.0f), fmaxf(v3, 0.0f)));
+                *reinterpret_cast<uint2 *>(&dst[mm * FPS + 16 * nb + 4 * g]) = o;
+            }
+        }
+    }
+}
+
+// Two workgroups per CU (each 80 KB of LDS and at most 256 registers per
+// lane) so that one's global loads and barriers overlap the other's MFMAs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_corr_fused(const float *__restrict__ rgb, const float *__restrict__ wsum,
+                                                    const uint8_t *__restrict__ count, int32_t N, int32_t H,
+                                                    int32_t W, const uint16_t *__restrict__ wbuf,
+                                                    const float *__restrict__ bbuf, CorrLayout L, float thresh,
+                                                    float *__restrict__ out, uint8_t *__restrict__ fb,
+                                                    float *__restrict__ resid_out) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[FR0 * FR0 * 8];
+    __shared__ __attribute__((aligned(16))) uint16_t s_a[FR1 * FR1 * FPS];  // layer 1, then layer 3
+    __shared__ __attribute__((aligned(16))) uint16_t s_b[FR2 * FR2 * FPS];  // layer 2, then the residual
+    __shared__ __attribute__((aligned(16))) float s_bias[4][32];
+    float *s_res = reinterpret_cast<float *>(s_b);
+    const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, g = lane >> 4;
+
+    // padded biases of the four layers
+    if (tid < 128) {
+        const int l = tid >> 5, c = tid & 31;
+        s_bias[l][c] = (l < 3 || c < 16) ? bbuf[L.layer[l].b_off + c] : 0.0f;
+    }
+    // this lane's weight fragments (row 16 nb + i, columns 32 s + 8 g ..)
+    bf16x8 w1[3][2], w2[9][2], w3[9][2], w4[9][1];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int co = 16 * nb + i;
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+            w1[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[0].wf_off + co * L.layer[0].kf + 32 * s + 8 * g]);
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            w2[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[1].wf_off + co * L.layer[1].kf + 32 * s + 8 * g]);
+            w3[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[2].wf_off + co * L.layer[2].kf + 32 * s + 8 * g]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 9; ++s)
+        w4[s][0] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[3].wf_off + i * L.layer[3].kf + 32 * s + 8 * g]);
+
+    const int tx = (W + FT - 1) / FT, ty = (H + FT - 1) / FT;
+    const int total = N * tx * ty;
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int n = tile / (tx * ty), r = tile % (tx * ty);
+        const int x0 = (r % tx) * FT, y0 = (r / tx) * FT;
+        const int64_t img = (int64_t)n * H * W;
+        // layer-1 input over the tile grown by 4 pixels per side
+        for (int q = tid; q < FR0 * FR0; q += 256) {
+            const int xx = x0 - 4 + q % FR0, yy = y0 - 4 + q / FR0;
+            uint4 o = make_uint4(0, 0, 0, 0);
+            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                const int64_t p = img + (int64_t)yy * W + xx;
+                o.x = f2bf(rgb[3 * p]) | ((uint32_t)f2bf(rgb[3 * p + 1]) << 16);
+                o.y = f2bf(rgb[3 * p + 2]) | ((uint32_t)f2bf(wsum[p] * (1.0f / kCorrWScale)) << 16);
+                o.z = f2bf((float)count[p] * (1.0f / kCorrNScale));
+            }
+            *reinterpret_cast<uint4 *>(&s_in[q * 8]) = o;
+        }
+        __syncthreads();
+        fused_layer<FR1, true, 3, 2, false>(s_in, s_a, nullptr, w1, s_bias[0], x0 - 3, y0 - 3, H, W);
+        __syncthreads();
+        fused_layer<FR2, false, 9, 2, false>(s_a, s_b, nullptr, w2, s_bias[1], x0 - 2, y0 - 2, H, W);
+        __syncthreads();
+        fused_layer<FR3, false, 9, 2, false>(s_b, s_a, nullptr, w3, s_bias[2], x0 - 1, y0 - 1, H, W);
+        __syncthreads();
+        fused_layer<FT, false, 9, 1, true>(s_a, nullptr, s_res, w4, s_bias[3], x0, y0, H, W);
+        __syncthreads();
+        // finish: out = render + residual, or the render where max |residual| > thresh
+        {
+            const int xx = x0 + tid % FT, yy = y0 + tid / FT;
+            if (xx < W && yy < H) {
+                const int64_t p = img + (int64_t)yy * W + xx;
+                const float r0 = s_res[tid * 4], r1 = s_res[tid * 4 + 1], r2 = s_res[tid * 4 + 2];
+                const bool f = fmaxf(fabsf(r0), fmaxf(fabsf(r1), fabsf(r2))) > thresh;
+                const float c0 = rgb[3 * p], c1 = rgb[3 * p + 1], c2 = rgb[3 * p + 2];
+                out[3 * p] = f ? c0 : c0 + r0;
+                out[3 * p + 1] = f ? c1 : c1 + r1;
+                out[3 * p + 2] = f ? c2 : c2 + r2;
+                if (fb) fb[p] = f ? 1 : 0;
+                if (resid_out) {
+                    resid_out[3 * p] = r0;
+                    resid_out[3 * p + 1] = r1;
+                    resid_out[3 * p + 2] = r2;
+                }
+            }
+        }
+        __syncthreads();  // s_res (aliasing s_b) is read before the next tile's layer 2 writes s_b
     }
 }
 
@@ -409,7 +568,7 @@ hipError_t corr_dw(int layer, const uint16_t *x, const uint16_t *dz, int32_t N, 
 }
 
 hipError_t corr_reduce(const float *partial, int32_t slots, int32_t len, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, s, partial, slots, len, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 63) / 64), dim3(256), 0, s, partial, slots, len, out);
     return hipGetLastError();
 }
 
@@ -425,10 +584,18 @@ hipError_t corr_adam(float *prm, const float *grad, float *m1, float *m2, int32_
     return hipGetLastError();
 }
 
-hipError_t corr_finish(const float *rgb, const float *resid, int64_t P, float thresh, float *out, uint8_t *fb,
-                       float *resid_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_corr_finish, dim3(grid_elems(P)), dim3(256), 0, s, rgb, resid, P, thresh, out, fb, resid_out);
+hipError_t corr_fused(const float *rgb, const float *wsum, const uint8_t *count, int32_t N, int32_t H, int32_t W,
+                      const uint16_t *wbuf, const float *bbuf, const CorrLayout &L, float thresh, float *out,
+                      uint8_t *fb, float *resid_out, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_fused, dim3(grid), dim3(256), 0, s, rgb, wsum, count, N, H, W, wbuf, bbuf, L, thresh,
+                       out, fb, resid_out);
     return hipGetLastError();
+}
+
+int corr_fused_tiles(int32_t N, int32_t H, int32_t W) { return N * ((W + FT - 1) / FT) * ((H + FT - 1) / FT); }
+
+hipError_t corr_fused_occupancy(int *per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void *)k_corr_fused, 256, 0);
 }
 
 }  // namespace lf

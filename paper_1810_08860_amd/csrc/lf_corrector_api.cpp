@@ -84,6 +84,7 @@ struct lf_corrector {
     uint16_t *dzA = nullptr, *dzB = nullptr;                  // [P][32]
     float *partial = nullptr;
     float *loss_part = nullptr;
+    int fused_grid = 0;  // resident workgroups of the fused inference kernel (CUs x per CU)
 };
 
 namespace {
@@ -171,6 +172,13 @@ int lf_corrector_create(const float *params, lf_corrector **out) {
     if (e == hipSuccess) e = hipMemset(c->prm, 0, sizeof(float) * kCorrParams);
     if (e == hipSuccess && params)
         e = hipMemcpy(c->prm, params, sizeof(float) * kCorrParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        int dev = 0, n_cu = 0, per_cu = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = corr_fused_occupancy(&per_cu);
+        c->fused_grid = std::max(1, n_cu * std::max(1, per_cu));
+    }
     if (e != hipSuccess)
         return bail(cfail(e == hipErrorOutOfMemory ? LF_ENOMEM : LF_EHIP, "corrector create: %s", hipGetErrorString(e)));
     *out = c;
@@ -204,10 +212,12 @@ int lf_corrector_apply(lf_corrector *c, const float *rgb, const float *wsum, con
     if (!out_rgb) return cfail(LF_EINVAL, "out_rgb must not be NULL");
     if (std::isnan(fallback_thresh) || fallback_thresh < 0.0f) return cfail(LF_EINVAL, "fallback_thresh must be >= 0");
     hipStream_t s = (hipStream_t)hip_stream;
-    rc = forward(c, rgb, wsum, count, n_images, W, H, s);
+    rc = pack(c, s);
     if (rc) return rc;
-    CF_HIP(corr_finish(rgb, c->resid, (int64_t)n_images * W * H, fallback_thresh, out_rgb, out_fallback, out_resid, s),
-           "corrector finish");
+    const int grid = std::min(c->fused_grid, corr_fused_tiles(n_images, H, W));
+    CF_HIP(corr_fused(rgb, wsum, count, n_images, H, W, c->wbuf, c->bbuf, c->L, fallback_thresh, out_rgb, out_fallback,
+                      out_resid, grid, s),
+           "corrector inference");
     return LF_OK;
 }
 

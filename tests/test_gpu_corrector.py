@@ -71,6 +71,35 @@ def test_forward_matches_oracle():
     c.close()
 
 
+@pytest.mark.parametrize("shape", [(2, 28, 40), (1, 97, 161)])
+def test_fused_inference_matches_training_forward(shape):
+    """Inference runs all four layers in one fused kernel over 16 x 16 tiles
+    with LDS halos; training runs them layer by layer. The training step's
+    loss (from its own forward) must equal the MSE of the fused residual
+    against the same reference, up to the summation order of the loss."""
+    import torch
+    from paper_1810_08860_amd import lf
+    n, h, w = shape
+    prm = _params(11)
+    rng = np.random.default_rng(12)
+    rgb = rng.uniform(0, 1, (n, h, w, 3)).astype(np.float32)
+    ws = rng.uniform(0, 3, (n, h, w)).astype(np.float32)
+    cnt = rng.integers(0, 10, (n, h, w)).astype(np.uint8)
+    ref = np.clip(rgb + rng.normal(size=rgb.shape) * 0.05, 0, 1).astype(np.float32)
+    c = lf.lf_corrector_create(prm)
+    d_rgb, d_ws, d_cnt, d_ref = _dev(rgb, ws, cnt, ref)
+    out = torch.zeros_like(d_rgb)
+    resid = torch.zeros_like(d_rgb)
+    lf.lf_corrector_apply(c, d_rgb, d_ws, d_cnt, n, w, h, float("inf"), out, None, resid)
+    torch.cuda.synchronize()
+    r = resid.cpu().numpy().astype(np.float64)
+    mse_fused = float(np.mean((rgb.astype(np.float64) + r - ref) ** 2))
+    loss, _ = lf.lf_corrector_train_step(c, d_rgb, d_ws, d_cnt, d_ref, n, w, h, 0.0)
+    print(f"{shape}: train-step loss {loss:.9g}, fused MSE {mse_fused:.9g}")
+    assert abs(loss - mse_fused) <= 1e-5 * mse_fused
+    c.close()
+
+
 def test_fallback_threshold_rule():
     import torch
     from paper_1810_08860_amd import lf
