@@ -2,19 +2,19 @@
  * lf.h -- C ABI of the MI355X light field renderer (liblf.so).
  *
  * The library answers the disk-blended light field query of Overbeck et al.
- * 2018 (Sec. 3.1, Eq. (2)) for every pixel of one or more eye views:
+ * 2018 (Sec. 4.1, Eq. (2)) for every pixel of one or more eye views:
  *
  *   L(o, e) = sum_i I_i(s_i, t_i) rho_i(u_i, v_i) / sum_i rho_i(u_i, v_i)
  *
  * over a set of source views captured on a sphere. Each view i has a centre of
  * projection c_i, an orthonormal frame R_i (columns r_i, u_i, f_i: image +x,
  * image up, optical axis), an RGBA8 image and a z-depth map that defines the
- * view's own triangle mesh (Sec. 3.5: two triangles per depth pixel, vertices
+ * view's own triangle mesh (Sec. 4.5: two triangles per depth pixel, vertices
  * at depth-pixel centres, cell (j,k) split along its (j,k)-(j+1,k+1) diagonal).
  * The disk of view i lies in the plane through c_i with normal f_i, with local
- * axes r_i, u_i, and weights rays by rho = 1 - r/R (Sec. 3.1 linear falloff).
+ * axes r_i, u_i, and weights rays by rho = 1 - r/R (Sec. 4.1 linear falloff).
  * (s_i, t_i) is the image-i position of the nearest intersection of the ray
- * with view i's mesh (intra-image occlusion only, Sec. 3.2.2); a view whose
+ * with view i's mesh (intra-image occlusion only, Sec. 4.2.2); a view whose
  * disk or mesh the ray misses contributes to neither sum. A pixel no view
  * contributes to is (0,0,0).
  *
@@ -96,7 +96,7 @@ typedef struct {
 /*
  * Copy a light field to the device and prepare it for rendering: convert the
  * images to img_fmt, turn each depth map into per-cell inverse-depth corners
- * (the vertex set of the view's mesh, Sec. 3.5) and record each view's
+ * (the vertex set of the view's mesh, Sec. 4.5) and record each view's
  * inverse-depth range. The caller may free every input on return.
  * Errors: LF_EINVAL for a null pointer, non-positive size, mesh_m < 2,
  * img_w != img_h, FOV outside (0,180), a frame not orthonormal to 1e-6, a
@@ -113,7 +113,7 @@ int lf_stereo_eyes(const double head_pos[3], const double head_rot[9], double ip
 int lf_set_tune(lf_ctx *c, const lf_tune *t);
 
 /*
- * Render n_eyes eye views (Sec. 3.1, Eqs. (1)-(2)). res[2k], res[2k+1] are the
+ * Render n_eyes eye views (Sec. 4.1, Eqs. (1)-(2)). res[2k], res[2k+1] are the
  * width and height of eye k; hfov_deg is the horizontal FOV of every eye.
  * out_rgb is a DEVICE buffer of sum_k W_k H_k RGB float triples, eyes
  * concatenated in order, each eye row-major from the top row. out_wsum
@@ -127,7 +127,7 @@ int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, co
 
 /*
  * Offline reference render (the analogue of the high-quality offline query of
- * Sec. 4.1): ss x ss regular sub-pixel rays per pixel, disks of radius
+ * Sec. 5.1): ss x ss regular sub-pixel rays per pixel, disks of radius
  * disk_scale * R, box-averaged; a sub-ray no view covers counts as 0.
  * Same buffers and layout as lf_render (out_rgb only).
  */
@@ -201,7 +201,7 @@ int lf_profile_read(lf_ctx *c, double out[6]);
 
 /* ---------------------------------------------------------------------------
  * Learned residual corrector (a post-process of the render; not in the paper,
- * whose learning-based methods are related work only, Sec. 1.1).
+ * whose learning-based methods are related work only, Sec. 2).
  *
  * Network: four 3x3 convolutions with zero padding, 5 -> 32 -> 32 -> 32 -> 3
  * channels, ReLU after the first three. Input per pixel: (R, G, B, W/4, n/8)

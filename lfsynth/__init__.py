@@ -5,9 +5,9 @@ views and depth maps; this module wraps it with numpy. Nothing here implements
 the reconstruction itself: the FP64 oracle and the HIP path both consume what
 this module writes, and neither shares any other code with the other.
 
-Workload recipes follow the paper's capture geometry (Sec. 2, a 70 cm capture
-sphere; Sec. 5, about a thousand views of about a megapixel; Sec. 6.1,
-120-degree views; Sec. 3.5, per-view meshes from per-view depth maps):
+Workload recipes follow the paper's capture geometry (Sec. 3, a 70 cm capture
+sphere; Sec. 6, about a thousand views of about a megapixel; Sec. 7.1,
+120-degree views; Sec. 4.5, per-view meshes from per-view depth maps):
 
 * ``tiny``  -- 64 views, 128x128 RGBA8 images, 128x128 depth, 3 spheres in a
   6 m box; one 256x256 mono eye, 90 deg, head in a 0.2 m ball.

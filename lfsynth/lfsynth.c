@@ -8,9 +8,9 @@
  * mesh intersection, reprojection, sampling, blending); both the FP64 oracle
  * and the HIP path consume the bytes it writes.
  *
- * Shapes follow the paper's capture setup (Sec. 2: a 70 cm capture sphere;
- * Sec. 5: about a thousand views of about a megapixel; Sec. 6.1: 120-degree
- * source views; Sec. 3.5: per-view meshes from per-view depth maps).
+ * Shapes follow the paper's capture setup (Sec. 3: a 70 cm capture sphere;
+ * Sec. 6: about a thousand views of about a megapixel; Sec. 7.1: 120-degree
+ * source views; Sec. 4.5: per-view meshes from per-view depth maps).
  *
  * Camera convention shared by every consumer (a convention, not code):
  *   a camera frame is an orthonormal 3x3 matrix R, row-major, whose columns

@@ -5,14 +5,14 @@ leg of the benchmark are the only users. The product path never imports it.
 It shares no code with the HIP library (see ``oracle.c`` for the readings of
 the paper it implements).
 
-Paper passages followed (all Sec. 3 of the paper):
-  * eye rays .............. Sec. 3.1, Eq. (1)
-  * disk-blended query .... Sec. 3.1, Eq. (2); linear kernel and disk placement
-  * point-splat reading ... Sec. 3.1, Eq. (3) (constant-colour special case)
-  * two-pass accumulate ... Sec. 3.2 (numerator / denominator, then divide)
-  * intra-image occlusion . Sec. 3.2.2 (nearest hit within one view's mesh)
-  * per-view mesh ......... Sec. 3.5 (depth map, two triangles per pixel)
-  * offline query L-bar ... Sec. 4.1 (denser / larger support reconstruction),
+Paper passages followed (all Sec. 4 of the paper):
+  * eye rays .............. Sec. 4.1, Eq. (1)
+  * disk-blended query .... Sec. 4.1, Eq. (2); linear kernel and disk placement
+  * point-splat reading ... Sec. 4.1, Eq. (3) (constant-colour special case)
+  * two-pass accumulate ... Sec. 4.2 (numerator / denominator, then divide)
+  * intra-image occlusion . Sec. 4.2.2 (nearest hit within one view's mesh)
+  * per-view mesh ......... Sec. 4.5 (depth map, two triangles per pixel)
+  * offline query L-bar ... Sec. 5.1 (denser / larger support reconstruction),
     used here as the supersampled reference render.
 """
 from __future__ import annotations
@@ -34,7 +34,7 @@ class _Views(ctypes.Structure):
         ("src_fov_deg", ctypes.c_double),
         ("centres", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("rgba8", ctypes.c_void_p),
         ("zdepth", ctypes.c_void_p), ("zrange", ctypes.c_void_p),
-        ("disk_radius", ctypes.c_double),
+        ("disk_radius", ctypes.c_double), ("disk_ext", ctypes.c_void_p),
         ("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
     ]
 
@@ -109,7 +109,8 @@ def max_threads() -> int:
 class OracleViews:
     """Light field as the oracle sees it: arrays kept alive for the C side."""
 
-    def __init__(self, centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, mode="traversal", threads=0):
+    def __init__(self, centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, mode="traversal", threads=0,
+                 disk_ext=None):
         self.centres = np.ascontiguousarray(centres, np.float64)
         self.rot = np.ascontiguousarray(np.asarray(rot, np.float64).reshape(-1, 9))
         self.rgba8 = np.ascontiguousarray(rgba8, np.uint8)
@@ -119,14 +120,16 @@ class OracleViews:
         assert self.centres.shape == (n, 3) and self.rot.shape == (n, 9) and self.zdepth.shape == (n, m, m)
         self.zrange = np.zeros((n, 2), np.float64)
         lib().orc_zrange(n, m, _p(self.zdepth), _p(self.zrange))
+        self.disk_ext = None if disk_ext is None else np.ascontiguousarray(disk_ext, np.float64).reshape(n, 4)
         self.s = _Views(n, w, h, m, float(src_fov_deg), _p(self.centres), _p(self.rot), _p(self.rgba8),
                         _p(self.zdepth), _p(self.zrange), float(disk_radius),
+                        None if self.disk_ext is None else _p(self.disk_ext),
                         1 if mode == "brute" else 0, int(threads))
 
     @classmethod
-    def from_views(cls, v, mode="traversal", threads=0, disk_radius=None):
+    def from_views(cls, v, mode="traversal", threads=0, disk_radius=None, disk_ext=None):
         return cls(v.centres, v.rot, v.rgba8, v.zdepth, v.src_fov_deg,
-                   v.disk_radius if disk_radius is None else disk_radius, mode, threads)
+                   v.disk_radius if disk_radius is None else disk_radius, mode, threads, disk_ext)
 
     @property
     def n(self):
@@ -137,6 +140,14 @@ class OracleViews:
         o.__dict__.update(self.__dict__)
         o.s = _Views.from_buffer_copy(self.s)
         o.s.disk_radius = float(r)
+        return o
+
+    def with_disk_extents(self, ext):
+        """Oval disks of Sec. 4.4 with per-view extents [n][4] (e+u, e-u, e+v, e-v);
+        None restores circles of the disk radius."""
+        o = self.with_disk_radius(self.s.disk_radius)
+        o.disk_ext = None if ext is None else np.ascontiguousarray(ext, np.float64).reshape(self.n, 4)
+        o.s.disk_ext = None if o.disk_ext is None else _p(o.disk_ext)
         return o
 
     def with_mode(self, mode):
@@ -211,8 +222,38 @@ def render_reference(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, ss: in
     sub = np.stack(np.meshgrid(offs, offs, indexing="xy"), -1).reshape(-1, 2)  # (ss*ss, 2) as (x, y)
     pxy = (base[:, None, :] + sub[None, :, :]).reshape(-1, 2)
     o, e = eye_rays(pos, rot, hfov_deg, W, H, pxy)
-    r = render_rays(ov.with_disk_radius(ov.s.disk_radius * disk_scale), o, e)
+    big = ov.with_disk_radius(ov.s.disk_radius * disk_scale)
+    if ov.disk_ext is not None:
+        big = big.with_disk_extents(ov.disk_ext * disk_scale)
+    r = render_rays(big, o, e)
     return r["rgb"].reshape(len(idx), ss * ss, 3).mean(1)
+
+
+def disk_extents(centres, rot):
+    """Extents (e+u, e-u, e+v, e-v) of each view's asymmetric oval disk
+    (Sec. 4.4): the disk reaches the centres of its 1-ring neighbours in a
+    Delaunay triangulation of the disk centres, and each extent is the furthest
+    1-ring neighbour along that direction of the disk's (u, v) axes (the
+    neighbour's centre offset projected on the view's r and u axes). For
+    centres on a sphere about the origin the Delaunay triangulation is the
+    convex hull of the centres' directions. Returns [n][4] and the 1-ring sets."""
+    from scipy.spatial import ConvexHull
+    c = np.asarray(centres, np.float64).reshape(-1, 3)
+    R = np.asarray(rot, np.float64).reshape(-1, 3, 3)
+    unit = c / np.linalg.norm(c, axis=1, keepdims=True)
+    ring = [set() for _ in range(len(c))]
+    for a, b, d in ConvexHull(unit).simplices:
+        ring[a] |= {b, d}
+        ring[b] |= {a, d}
+        ring[d] |= {a, b}
+    ext = np.zeros((len(c), 4))
+    for i in range(len(c)):
+        q = c[sorted(ring[i])] - c[i]
+        du, dv = q @ R[i][:, 0], q @ R[i][:, 1]
+        ext[i] = (du.max(), (-du).max(), dv.max(), (-dv).max())
+    if not (ext > 0).all():
+        raise ValueError("a disk has no 1-ring neighbour on one side of an axis")
+    return ext, ring
 
 
 def disk(ov: OracleViews, i, o, e):

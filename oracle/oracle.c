@@ -7,18 +7,18 @@
  * table or helper with the HIP library; the only thing both consume is the
  * synthetic input data written by the seeded generator.
  *
- * What it computes (paper, Sec. 3.1, Eqs. (1)-(2)): for an eye ray (o, e)
+ * What it computes (paper, Sec. 4.1, Eqs. (1)-(2)): for an eye ray (o, e)
  *
  *     L(o, e) = sum_i I_i(s_i, t_i) rho_i(u_i, v_i) / sum_i rho_i(u_i, v_i)
  *
  * where (u_i, v_i) is where the ray crosses view i's disk (centred on the
  * view's centre of projection, tangent to the capture sphere, normal along the
- * optical axis, u and v along the image axes: Sec. 3.1 and Sec. 3.4), rho_i is
- * the linear-falloff kernel (1 at the centre, 0 at the rim: Sec. 3.1), and
+ * optical axis, u and v along the image axes: Sec. 4.1 and Sec. 4.4), rho_i is
+ * the linear-falloff kernel (1 at the centre, 0 at the rim: Sec. 4.1), and
  * (s_i, t_i) is the image-i position of the nearest intersection of the ray
- * with view i's own triangle mesh (Sec. 3.1; intra-image occlusion only,
- * Sec. 3.2.2; the mesh is the depth map tessellated with two triangles per
- * depth pixel, Sec. 3.5). Pass 1 / pass 2 of Sec. 3.2 (accumulate numerator and
+ * with view i's own triangle mesh (Sec. 4.1; intra-image occlusion only,
+ * Sec. 4.2.2; the mesh is the depth map tessellated with two triangles per
+ * depth pixel, Sec. 4.5). Pass 1 / pass 2 of Sec. 4.2 (accumulate numerator and
  * denominator, then divide) become two running sums and one division.
  *
  * The geometry is deliberately evaluated in WORLD space with the published
@@ -32,6 +32,11 @@
  *   - disk: a planar circle of radius R in the tangent plane at c_i, normal f_i;
  *     rho = 1 - r/R, a candidate iff rho > 0; a ray with e.f_i <= 0 never uses
  *     view i (back-facing disk);
+ *   - asymmetric oval disk (Sec. 4.4, "Disk Shape"), when per-view extents
+ *     (e+u, e-u, e+v, e-v) are given: the union of four elliptic quarters, one
+ *     per quadrant of the disk plane around c_i; the linear falloff runs in the
+ *     quadrant's normalised radius, rho = 1 - sqrt((u/e_u)^2 + (v/e_v)^2) with
+ *     e_u = e+u for u >= 0 else e-u and e_v likewise;
  *   - mesh: vertices at depth-pixel centres, V_jk = c_i + z_jk R_i (X_j, Y_k, 1),
  *     cell (j,k) split along (j,k)-(j+1,k+1); both faces count; barycentric
  *     tests inclusive;
@@ -58,6 +63,7 @@ typedef struct {
     const float *zdepth;     /* [n][mesh_m][mesh_m] z along f, metres */
     const double *zrange;    /* [n][2] min,max of each depth map (orc_zrange) */
     double disk_radius;
+    const double *disk_ext;  /* [n][4] oval extents e+u, e-u, e+v, e-v (metres), or NULL: circles of disk_radius */
     int32_t mode;            /* 0 = traversal, 1 = brute force over all triangles */
     int32_t threads;
 } orc_views;
@@ -103,7 +109,7 @@ void orc_zrange(int32_t n, int32_t m, const float *z, double *out) {
 }
 
 /*
- * Eye rays (Sec. 3.1, Eq. (1)): origin o = eye centre, direction through the
+ * Eye rays (Sec. 4.1, Eq. (1)): origin o = eye centre, direction through the
  * continuous pixel position (x, y), where pixel (px, py) has its centre at
  * (px + 1/2, py + 1/2). The FOV is horizontal; the vertical half-angle follows
  * from the aspect ratio (square pixels).
@@ -122,10 +128,11 @@ void orc_eye_rays(const double pos[3], const double *rot, double hfov_deg, int32
 }
 
 /*
- * Disk of view i (Sec. 3.1 and Sec. 3.4): plane through c_i with normal f_i,
+ * Disk of view i (Sec. 4.1 and Sec. 4.4): plane through c_i with normal f_i,
  * local axes r_i, u_i. Returns a = e.f_i, the local intersection (u, v) and
- * rho = 1 - |(u,v)| / R (not clamped). For a <= 0 the disk faces away and
- * u, v, rho are set to NaN.
+ * rho = 1 - |(u,v)| / R, or for an oval disk (Sec. 4.4) 1 minus the radius
+ * normalised by the extents of (u, v)'s quadrant (not clamped). For a <= 0 the
+ * disk faces away and u, v, rho are set to NaN.
  */
 void orc_disk(const orc_views *V, int32_t i, const double o[3], const double e[3],
               double *a_out, double *u_out, double *v_out, double *rho_out) {
@@ -140,7 +147,13 @@ void orc_disk(const orc_views *V, int32_t i, const double o[3], const double e[3
     double q[3] = {o[0] + ts * e[0] - c[0], o[1] + ts * e[1] - c[1], o[2] + ts * e[2] - c[2]};
     double uu = dot3(q, r), vv = dot3(q, u);
     *u_out = uu; *v_out = vv;
-    *rho_out = 1.0 - sqrt(uu * uu + vv * vv) / V->disk_radius;
+    if (V->disk_ext) {
+        const double *x = V->disk_ext + 4 * i;
+        const double su = uu / (uu >= 0.0 ? x[0] : x[1]), sv = vv / (vv >= 0.0 ? x[2] : x[3]);
+        *rho_out = 1.0 - sqrt(su * su + sv * sv);
+    } else {
+        *rho_out = 1.0 - sqrt(uu * uu + vv * vv) / V->disk_radius;
+    }
 }
 
 /* World-space vertex (j, k) of view i's mesh: c_i + z_jk R_i (X_j, Y_k, 1). */
@@ -203,8 +216,8 @@ static void test_cell(const orc_views *V, int32_t i, int32_t j, int32_t k, const
 }
 
 /*
- * Nearest intersection of the ray with view i's mesh (Sec. 3.1, Sec. 3.2.2,
- * Sec. 3.5). Returns t (INFINITY when the mesh is missed).
+ * Nearest intersection of the ray with view i's mesh (Sec. 4.1, Sec. 4.2.2,
+ * Sec. 4.5). Returns t (INFINITY when the mesh is missed).
  */
 double orc_mesh_hit(const orc_views *V, int32_t i, const double o[3], const double e[3]) {
     const int32_t M = V->mesh_m;

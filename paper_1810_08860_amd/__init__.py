@@ -1,4 +1,4 @@
-"""MI355X-native disk-blended light field renderer (Overbeck et al. 2018, Sec. 3).
+"""MI355X-native disk-blended light field renderer (Overbeck et al. 2018, Sec. 4).
 
 The product is the HIP library ``liblf.so`` behind the C ABI in
 ``include/lf.h``; :mod:`paper_1810_08860_amd.lf` is its thin ctypes binding.

@@ -3,7 +3,7 @@
 The corrector (include/lf.h, lf_corrector_*) refines the real-time render
 towards an offline reference of the same pose: the same disk-blended query
 with 4x4 sub-pixel rays and disks of twice the radius over all views (the
-analogue of the high-quality offline query of Sec. 4.1 of the paper). Pairs
+analogue of the high-quality offline query of Sec. 5.1 of the paper). Pairs
 are produced on the GPU by the library itself; this module only orchestrates
 them (pose selection, crop gathering, learning-rate schedule) and measures
 PSNR. Every forward, backward and optimiser step runs in the library's kernels.

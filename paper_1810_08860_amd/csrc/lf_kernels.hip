@@ -1,6 +1,6 @@
 // HIP kernels for disk-blended light field reconstruction on CDNA4 (gfx950).
 //
-// Data path for one eye (Sec. 3.1, Eqs. (1)-(2); Sec. 3.2):
+// Data path for one eye (Sec. 4.1, Eqs. (1)-(2); Sec. 4.2):
 //   k_prep    per (eye, view): the 3x3 map taking an eye-image point (X, Y, 1)
 //             to the ray direction in the view's frame, and the eye centre in
 //             that frame (FP64 set-up, stored FP32).
@@ -8,7 +8,7 @@
 //             against the tile's frustum (conservatively); survivors are
 //             compacted into an LDS list with a wavefront ballot and prefix
 //             popcount, then written out (the GPU counterpart of the paper's
-//             per-tile visibility culling, Sec. 3.2.1 and Sec. 6.2).
+//             per-tile visibility culling, Sec. 4.2.1 and Sec. 7.2).
 //   k_render  per screen tile: the tile's candidate list and each candidate's
 //             per-view record are wave-uniform and read by the scalar unit;
 //             every pixel tests each candidate's disk exactly, intersects its
@@ -21,10 +21,10 @@
 // D = (o'x, o'y) - o'z V (exactly the (u, v) at which the ray crosses the disk
 // plane), the ray point at inverse depth w = 1/z projects to V + w D. A planar
 // triangle stays planar in (X, Y, w), so view i's mesh (vertices at
-// depth-pixel centres, Sec. 3.5) is the piecewise-linear field of vertex
+// depth-pixel centres, Sec. 4.5) is the piecewise-linear field of vertex
 // inverse depths over the regular grid, and the ray is the straight line
 // w -> (V + w D, w). The nearest hit along the ray (intra-image occlusion,
-// Sec. 3.2.2) is the LARGEST w at which the line meets the field; the kernel
+// Sec. 4.2.2) is the LARGEST w at which the line meets the field; the kernel
 // walks grid cells from the view's largest inverse depth downwards (blocks of
 // cells first, skipping those whose inverse-depth range the line misses) and
 // solves, in each cell, the two triangles' planes against the line in closed

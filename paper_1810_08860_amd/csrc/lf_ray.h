@@ -97,7 +97,7 @@ struct RayView {
     float Vx, Vy, Dx, Dy, rho;
 };
 
-// Exact disk test of one ray against one view (Sec. 3.1: linear falloff, disk
+// Exact disk test of one ray against one view (Sec. 4.1: linear falloff, disk
 // in the view's tangent plane). False for a back-facing disk or rho <= 0.
 LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
                                           RayView &rv) {

@@ -1,6 +1,6 @@
 """Pins of the FP64 oracle against what the paper and plain geometry fix.
 
-Each test names the paper passage (Sec. 3 of the paper) it holds the oracle to.
+Each test names the paper passage (Sec. 4 of the paper) it holds the oracle to.
 None of these re-types the oracle's formulas: they use constructed geometry
 with known answers, special cases that reduce to exact results, invariances,
 and an independent brute-force evaluation on a tiny light field.
@@ -42,7 +42,7 @@ def test_eye_ray_axes_and_fov():
     assert en[3] @ R[:, 0] < 0 and en[3] @ R[:, 1] < 0
 
 
-# ----------------------------------------------------------------------------- Sec. 3.1: disk kernel
+# ----------------------------------------------------------------------------- Sec. 4.1: disk kernel
 
 def test_disk_unit_cases(tiny, tiny_oracle):
     V, ov = tiny.views, tiny_oracle
@@ -135,7 +135,7 @@ def test_constant_colour_views_reproduce_colour(tiny):
 
 
 def test_weights_and_records_consistent(tiny, tiny_oracle, rng):
-    """Sec. 3.2: numerator and denominator gather exactly the views whose
+    """Sec. 4.2: numerator and denominator gather exactly the views whose
     disk covers the ray and whose mesh is hit; W > 0 iff some view contributes."""
     ov = tiny_oracle
     pxy = rng.uniform(0, 256, (40, 2))
@@ -200,7 +200,7 @@ def _plane_views(texture, period=2.0, rgb=(0.2, 0.5, 0.8), img=128, mesh=64):
 
 
 def test_planar_scene_hits_are_exact():
-    """Sec. 3.5: the depth-map mesh of a plane is the plane itself, so every
+    """Sec. 4.5: the depth-map mesh of a plane is the plane itself, so every
     view's nearest hit is the analytic ray/plane point and its reprojection is
     that point's projection."""
     sc, ov, c, R = _plane_views(2)
