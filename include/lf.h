@@ -12,7 +12,10 @@
  * view's own triangle mesh (Sec. 4.5: two triangles per depth pixel, vertices
  * at depth-pixel centres, cell (j,k) split along its (j,k)-(j+1,k+1) diagonal).
  * The disk of view i lies in the plane through c_i with normal f_i, with local
- * axes r_i, u_i, and weights rays by rho = 1 - r/R (Sec. 4.1 linear falloff).
+ * axes r_i, u_i, and weights rays by rho = 1 - r/R (Sec. 4.1 linear falloff),
+ * or, for an asymmetric oval disk (Sec. 4.4) with extents (e+u, e-u, e+v,
+ * e-v), by rho = 1 - sqrt((u/e_u)^2 + (v/e_v)^2) where e_u is e+u for u >= 0
+ * and e-u otherwise (e_v likewise).
  * (s_i, t_i) is the image-i position of the nearest intersection of the ray
  * with view i's mesh (intra-image occlusion only, Sec. 4.2.2); a view whose
  * disk or mesh the ray misses contributes to neither sum. A pixel no view
@@ -74,11 +77,30 @@ typedef struct {
     const double *rot;        /* [N][9] frames R_i, row-major, columns (r,u,f) (host memory) */
     const uint8_t *rgba8;     /* [N][img_h][img_w][4] images, UNORM8; alpha is ignored */
     const float *zdepth;      /* [N][mesh_m][mesh_m] z along f_i at depth-pixel centres, metres, > 0 */
-    double disk_radius;       /* R, metres, > 0 */
+    double disk_radius;       /* R, metres, > 0: circular disks (and the unit of lf_render_reference's scale) */
+    const double *disk_ext;   /* NULL for circular disks of radius R, else [N][4] oval extents e+u, e-u, e+v,
+                                 e-v in metres, each finite and > 0 (host memory; see lf_disk_extents) */
     int32_t img_fmt;          /* LF_IMG_* */
     int32_t geo_fmt;          /* LF_GEO_* */
     int32_t flags;            /* LF_SRC_DEVICE or 0 */
 } lf_views_desc;
+
+/*
+ * Extents of asymmetric oval disks (Sec. 4.4): every disk reaches the centres
+ * of its 1-ring neighbours in a Delaunay triangulation of the disk centres;
+ * its extent towards +u, -u, +v and -v (the frame's r and u axes) is the
+ * furthest 1-ring neighbour on that side, measured as the neighbour's centre
+ * offset projected on the axis. The views are taken to lie on a capture sphere
+ * about the origin, whose Delaunay triangulation is the convex hull of the
+ * centres' directions. centres [N][3], rot [N][9] as in lf_views_desc (host);
+ * out_ext [N][4] (host) receives scale * (e+u, e-u, e+v, e-v) in metres. Where
+ * four centres are (nearly) co-circular both diagonals are Delaunay and either
+ * may be chosen. Host computation, synchronous, no device use.
+ * LF_EINVAL: NULL pointer, N outside [4, 65535], scale not finite and > 0, a
+ * centre at the origin, directions that do not close a sphere (coplanar,
+ * duplicated), or a view with no neighbour on one side of an axis.
+ */
+int lf_disk_extents(int32_t n_views, const double *centres, const double *rot, double scale, double *out_ext);
 
 /* One eye: centre of projection and frame (columns r, u, f). */
 typedef struct {

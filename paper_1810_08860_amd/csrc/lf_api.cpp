@@ -71,6 +71,8 @@ struct lf_ctx {
     double *vt = nullptr;    // device [n][12]: centre, frame
     float2 *wr = nullptr;    // device [n]: inverse-depth range
     float2 *blk = nullptr;   // device [n][NB][NB]: inverse-depth range per block of cells
+    float4 *ext_inv = nullptr;  // device [n]: oval disks' inverse extents (null: circles of radius R)
+    float *vrad = nullptr;      // device [n]: oval disks' largest extent (culling bound)
     std::vector<double> h_vt;  // host copy of the view table (eye validation)
     // per-render scratch: eye-view table and tile lists, grown on demand
     void *scratch = nullptr;
@@ -215,6 +217,9 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.cH = (float)(0.5 * (c->img_h - 1));
     a.R = (float)R;
     a.invR = (float)(1.0 / R);
+    // R is the context's radius times the call's disk scale; oval extents scale alike
+    a.ext_inv = c->ext_inv;
+    a.ext_inv_scale = (float)(c->R / R);
     a.texels_per_view = (int64_t)c->img_w * c->img_h;
     a.cells_per_view = (int64_t)(c->M - 1) * (c->M - 1);
     a.scale = 1.0f;
@@ -233,10 +238,10 @@ int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t 
     EyeView *ev = (EyeView *)p;
     uint16_t *tl = (uint16_t *)(p + al(ev_bytes));
     int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
-    LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, ev, s); }), "k_prep launch");
-    // conservative radius: the exact per-ray test decides in k_render
-    const float R_keep = (float)(R * (1.0 + 1e-4) + 1e-7);
-    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, R_keep, tl, tc, s); }), "k_cull launch");
+    // conservative disk bounds for the tile test; the exact per-ray test decides in k_render
+    const DiskBound db{c->vrad, R, R / c->R};
+    LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, ev, s); }), "k_prep launch");
+    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, tl, tc, s); }), "k_cull launch");
     a.ev = ev;
     a.tile_list = tl;
     a.tile_count = tc;
@@ -275,6 +280,11 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
     if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
     const int32_t n = d->n_views, M = d->mesh_m;
+    if (d->disk_ext)
+        for (int64_t k = 0; k < 4 * (int64_t)n; ++k)
+            if (!(d->disk_ext[k] > 0.0) || !std::isfinite(d->disk_ext[k]))
+                return fail(LF_EINVAL, "view %d: oval disk extent %d is not finite and positive", (int)(k / 4),
+                            (int)(k % 4));
     for (int32_t v = 0; v < n; ++v) {
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(d->centres[3 * v + a])) return fail(LF_EINVAL, "view %d: centre not finite", v);
@@ -314,6 +324,20 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if ((e = hipMalloc(&c->wr, sizeof(float2) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(w range)"));
     if ((e = hipMemcpy(c->vt, c->h_vt.data(), c->h_vt.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(hip_fail(e, "copy view table"));
+    if (d->disk_ext) {
+        std::vector<float4> inv(n);
+        std::vector<float> big(n);
+        for (int32_t v = 0; v < n; ++v) {
+            const double *x = d->disk_ext + 4 * (size_t)v;
+            inv[v] = make_float4((float)(1.0 / x[0]), (float)(1.0 / x[1]), (float)(1.0 / x[2]), (float)(1.0 / x[3]));
+            big[v] = (float)std::max(std::max(x[0], x[1]), std::max(x[2], x[3]));
+        }
+        if ((e = hipMalloc(&c->ext_inv, sizeof(float4) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(disks)"));
+        if ((e = hipMalloc(&c->vrad, sizeof(float) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(disks)"));
+        if ((e = hipMemcpy(c->ext_inv, inv.data(), sizeof(float4) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->vrad, big.data(), sizeof(float) * n, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(hip_fail(e, "copy disks"));
+    }
 
     // images: RGBA8 upload, converted on the device when another format is asked for
     void *rgba_dev = nullptr;
@@ -584,13 +608,13 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
         LF_HIP(persistent_occupancy(c->img_fmt, c->geo_fmt, t.tile_w * t.tile_h, &per_cu), "occupancy");
         LF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
         const int grid = std::max(1, std::min(per_cu * n_cu, tiles));
-        const float R_keep = (float)(c->R * (1.0 + 1e-4) + 1e-7);
+        const DiskBound db{c->vrad, c->R, 1.0};
         if (c->profiling && !B.ph_a) {
             LF_HIP(hipEventCreate(&B.ph_a), "hipEventCreate");
             LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
         }
         LF_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, R_keep, c->img_fmt, c->geo_fmt, grid, B.cap_stream,
+        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, c->img_fmt, c->geo_fmt, grid, B.cap_stream,
                                     nullptr, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(B.cap_stream, &g);
@@ -790,6 +814,8 @@ void lf_free(lf_ctx *c) {
     if (c->vt) (void)hipFree(c->vt);
     if (c->wr) (void)hipFree(c->wr);
     if (c->blk) (void)hipFree(c->blk);
+    if (c->ext_inv) (void)hipFree(c->ext_inv);
+    if (c->vrad) (void)hipFree(c->vrad);
     if (c->scratch) (void)hipFree(c->scratch);
     for (auto &t : c->timed) {
         (void)hipEventDestroy(t.a);

@@ -45,7 +45,15 @@ struct alignas(16) EyeView {
     float o[3];
     float wmin, wmax;  // inverse-depth range of the view's mesh
     int32_t view;
-    int32_t pad;
+    float rk;          // radius bounding the view's disk, padded for the conservative tile test
+};
+
+// Bound of every disk for culling: the radius of view v's disk is
+// vrad[v] * vscale (oval disks: the largest of the four extents) or R
+// (circles); both already include the disk scale of the call.
+struct DiskBound {
+    const float *vrad;  // [n] or null
+    double R, vscale;
 };
 
 // A batch: eye table in device memory (sorted by tile_off / super_off), a
@@ -72,7 +80,9 @@ struct RenderArgs {
     int32_t M, img_w, img_h;
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
     float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
-    float R, invR;
+    float R, invR;              // circular disks
+    const float4 *ext_inv;      // oval disks (null: circles): [n] 1/e+u, 1/e-u, 1/e+v, 1/e-v
+    float ext_inv_scale;        // multiplies ext_inv (1 / disk scale)
     int64_t texels_per_view, cells_per_view;
     float *out_rgb;
     float *out_wsum;
@@ -96,16 +106,16 @@ hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);
-hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, EyeView *ev,
+hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
+                       EyeView *ev, hipStream_t s);
+hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_t *tile_list, int32_t *tile_count,
                        hipStream_t s);
-hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R_keep, uint16_t *tile_list,
-                       int32_t *tile_count, hipStream_t s);
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
                          hipStream_t s);
 // reset + prep + cull + persistent render of a batch (a.ev / tile lists are the batch's buffers)
 // ev_a / ev_b (may be null) are recorded just before / after the persistent render kernel
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        float R_keep, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
+                        const DiskBound &db, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
                         hipEvent_t ev_b);
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, int block, int *per_cu);
 

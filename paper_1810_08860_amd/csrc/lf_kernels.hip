@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
 
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
 __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__restrict__ vt,
-                                            const float2 *__restrict__ wr, int v) {
+                                            const float2 *__restrict__ wr, int v, const DiskBound &db) {
     const double *c = vt + 12 * (int64_t)v;
     const double *R = c + 3;
     EyeView out;
@@ -169,28 +169,31 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     out.wmin = w.x;
     out.wmax = w.y;
     out.view = v;
-    out.pad = 0;
+    // padded by 1e-4 relative and 1e-7 m: the FP32 tile test may not drop a
+    // disk that the exact per-ray test keeps
+    out.rk = (float)((db.vrad ? (double)db.vrad[v] * db.vscale : db.R) * (1.0 + 1e-4) + 1e-7);
     return out;
 }
 
 __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
-                                              const float2 *__restrict__ wr, int32_t n, EyeView *__restrict__ ev) {
+                                              const float2 *__restrict__ wr, int32_t n, const DiskBound db,
+                                              EyeView *__restrict__ ev) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = blockIdx.y;
     if (v >= n || e >= ch.n_eyes) return;
-    ev[(int64_t)e * n + v] = eye_view(ch.e[e], vt, wr, v);
+    ev[(int64_t)e * n + v] = eye_view(ch.e[e], vt, wr, v, db);
 }
 
 // ---------------------------------------------------------------------------------------------
 // culling
 
 // Does any ray of the tile's pixel rectangle [X0,X1] x [Y1,Y0] cross the disk
-// (radius R) of view v? Conservative: the tile's rays hit the disk plane
+// of view v (inside the circle of radius R = v.rk)? Conservative: the tile's rays hit the disk plane
 // inside the convex quad spanned by the four corner rays (a central
 // projection of a rectangle), so the test is circle-vs-convex-quad; a tile
 // that straddles the plane's horizon is kept.
-__device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, float X1, float Y0, float Y1,
-                                                   float R) {
+__device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, float X1, float Y0, float Y1) {
+    const float R = v.rk;
     const float cx[4] = {X0, X1, X1, X0}, cy[4] = {Y0, Y0, Y1, Y1};
     float dx[4], dy[4];
     int npos = 0;
@@ -269,7 +272,7 @@ struct CullSmem {
 };
 
 __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int tile_w, int tile_h,
-                                           const EyeView *__restrict__ eve, int32_t n, float R_keep,
+                                           const EyeView *__restrict__ eve, int32_t n,
                                            uint16_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
                                            CullSmem &sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -287,7 +290,7 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
         int scount = 0;
         for (int base = 0; base < n; base += 256) {
             const int v = base + (int)threadIdx.x;
-            const bool keep = v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1, R_keep);
+            const bool keep = v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
             const uint64_t mask = __ballot(keep);
             if (lane == 0) sm.wcnt[wave] = __popcll(mask);
             __syncthreads();
@@ -321,7 +324,7 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
             for (int b = 0; b < ns; b += 64) {
                 const int s = b + lane;
                 const int v = s < ns ? (sover ? s : (int)sm.slist[s]) : -1;
-                const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1, R_keep);
+                const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
                 const uint64_t mask = __ballot(keep);
                 if (keep) {
                     const int slot = count + __popcll(mask & below);
@@ -342,12 +345,12 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
 }
 
 __global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const EyeView *__restrict__ ev, int32_t n,
-                                              float R_keep, uint16_t *__restrict__ tile_list,
+                                              uint16_t *__restrict__ tile_list,
                                               int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_super(ch, super);
-    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, R_keep, tile_list,
+    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, tile_list,
                tile_count, sm);
 }
 
@@ -365,13 +368,13 @@ __device__ __forceinline__ int find_eye_sorted(const EyeParam *__restrict__ eyes
 }
 
 __global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const EyeView *__restrict__ ev, int32_t n,
-                                                    float R_keep, uint16_t *__restrict__ tile_list,
+                                                    uint16_t *__restrict__ tile_list,
                                                     int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_sorted(b.eyes, b.n_eyes, super, true);
     const EyeParam E = b.eyes[e];
-    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, R_keep, tile_list, tile_count,
+    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, tile_list, tile_count,
                sm);
 }
 
@@ -443,7 +446,9 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             const EyeView v = uniform_load(eve + vid);
             RayView rv;
             ++n_tests;
-            if (!disk_test(v, X, Y, a.R, a.invR, rv)) continue;
+            const bool cand = a.ext_inv ? disk_test_oval(v, X, Y, uniform_load(a.ext_inv + v.view), a.ext_inv_scale, rv)
+                                        : disk_test(v, X, Y, a.R, a.invR, rv);
+            if (!cand) continue;
             if (MODE == MODE_STATS) ++nc;
             if (MODE == MODE_DEBUG) {
                 if (nc < a.dbg_cap) a.dbg_cand[pix * a.dbg_cap + nc] = v.view;
@@ -584,13 +589,13 @@ __global__ void k_batch_reset(unsigned int *queue, unsigned long long *frame_t, 
 
 // Per (eye, view) set-up for a batch whose eye table lives in device memory.
 __global__ __launch_bounds__(256) void k_prep_batch(const BatchArgs b, const double *__restrict__ vt,
-                                                    const float2 *__restrict__ wr, int32_t n,
+                                                    const float2 *__restrict__ wr, int32_t n, const DiskBound db,
                                                     EyeView *__restrict__ ev) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = blockIdx.y;
     if (v >= n || e >= b.n_eyes) return;
     const EyeParam E = b.eyes[e];
-    ev[(int64_t)e * n + v] = eye_view(E, vt, wr, v);
+    ev[(int64_t)e * n + v] = eye_view(E, vt, wr, v, db);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -637,15 +642,15 @@ hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, EyeView *ev,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_prep, dim3((n + 255) / 256, ch.n_eyes), dim3(256), 0, s, ch, vt, wr, n, ev);
+hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
+                       EyeView *ev, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3((n + 255) / 256, ch.n_eyes), dim3(256), 0, s, ch, vt, wr, n, db, ev);
     return hipGetLastError();
 }
 
-hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, float R_keep, uint16_t *tile_list,
-                       int32_t *tile_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, ev, n, R_keep, tile_list, tile_count);
+hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_t *tile_list, int32_t *tile_count,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, ev, n, tile_list, tile_count);
     return hipGetLastError();
 }
 
@@ -666,12 +671,12 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
 }
 
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        float R_keep, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
+                        const DiskBound &db, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
                         hipEvent_t ev_b) {
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
-    hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n,
+    hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n, db,
                        const_cast<EyeView *>(a.ev));
-    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n, R_keep,
+    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n,
                        const_cast<uint16_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
     const dim3 block(b.tile_w * b.tile_h);
     if (ev_a) {

@@ -97,22 +97,38 @@ struct RayView {
     float Vx, Vy, Dx, Dy, rho;
 };
 
-// Exact disk test of one ray against one view (Sec. 4.1: linear falloff, disk
-// in the view's tangent plane). False for a back-facing disk or rho <= 0.
-LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR,
-                                          RayView &rv) {
-    // evaluated without early exits (a back-facing view gives garbage that the
-    // final test discards, NaN included)
+// The ray's vanishing point V and disk-plane coordinates D in view v's frame;
+// returns e'z (> 0 for a disk facing the ray).
+LF_HD float disk_coords(const EyeView &v, float X, float Y, RayView &rv) {
     const float ez = fmaf(v.m[6], X, fmaf(v.m[7], Y, v.m[8]));
     const float iz = fast_rcp(ez);
-    const float Vx = fmaf(v.m[0], X, fmaf(v.m[1], Y, v.m[2])) * iz;
-    const float Vy = fmaf(v.m[3], X, fmaf(v.m[4], Y, v.m[5])) * iz;
-    const float Dx = fmaf(-v.o[2], Vx, v.o[0]);
-    const float Dy = fmaf(-v.o[2], Vy, v.o[1]);
-    const float r2 = fmaf(Dx, Dx, Dy * Dy);
-    const float rho = fmaf(-fast_sqrt(r2), invR, 1.0f);
-    rv.Vx = Vx; rv.Vy = Vy; rv.Dx = Dx; rv.Dy = Dy; rv.rho = rho;
-    return ez > 0.0f && r2 < R * R && rho > 0.0f;
+    rv.Vx = fmaf(v.m[0], X, fmaf(v.m[1], Y, v.m[2])) * iz;
+    rv.Vy = fmaf(v.m[3], X, fmaf(v.m[4], Y, v.m[5])) * iz;
+    rv.Dx = fmaf(-v.o[2], rv.Vx, v.o[0]);
+    rv.Dy = fmaf(-v.o[2], rv.Vy, v.o[1]);
+    return ez;
+}
+
+// Exact disk test of one ray against one view (Sec. 4.1: linear falloff, disk
+// in the view's tangent plane). False for a back-facing disk or rho <= 0.
+// Evaluated without early exits (a back-facing view gives garbage that the
+// final test discards, NaN included).
+LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR, RayView &rv) {
+    const float ez = disk_coords(v, X, Y, rv);
+    const float r2 = fmaf(rv.Dx, rv.Dx, rv.Dy * rv.Dy);
+    rv.rho = fmaf(-fast_sqrt(r2), invR, 1.0f);
+    return ez > 0.0f && r2 < R * R && rv.rho > 0.0f;
+}
+
+// Asymmetric oval disk (Sec. 4.4): the linear falloff runs in the radius
+// normalised by the extents of D's quadrant; ie = (1/e+u, 1/e-u, 1/e+v,
+// 1/e-v) times s.
+LF_HD bool disk_test_oval(const EyeView &v, float X, float Y, float4 ie, float s, RayView &rv) {
+    const float ez = disk_coords(v, X, Y, rv);
+    const float su = rv.Dx * (rv.Dx >= 0.0f ? ie.x : ie.y) * s, sv = rv.Dy * (rv.Dy >= 0.0f ? ie.z : ie.w) * s;
+    const float q2 = fmaf(su, su, sv * sv);
+    rv.rho = 1.0f - fast_sqrt(q2);
+    return ez > 0.0f && q2 < 1.0f && rv.rho > 0.0f;
 }
 
 LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }

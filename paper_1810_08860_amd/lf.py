@@ -25,7 +25,7 @@ class lf_views_desc(ctypes.Structure):
         ("n_views", ctypes.c_int32), ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32),
         ("mesh_m", ctypes.c_int32), ("src_fov_deg", ctypes.c_double),
         ("centres", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("rgba8", ctypes.c_void_p),
-        ("zdepth", ctypes.c_void_p), ("disk_radius", ctypes.c_double),
+        ("zdepth", ctypes.c_void_p), ("disk_radius", ctypes.c_double), ("disk_ext", ctypes.c_void_p),
         ("img_fmt", ctypes.c_int32), ("geo_fmt", ctypes.c_int32), ("flags", ctypes.c_int32),
     ]
 
@@ -61,6 +61,7 @@ def lib():
         vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         L.lf_load_views.argtypes = [ctypes.POINTER(lf_views_desc), ctypes.POINTER(vp)]
         L.lf_stereo_eyes.argtypes = [vp, vp, f64, ctypes.POINTER(lf_eye)]
+        L.lf_disk_extents.argtypes = [i32, vp, vp, f64, vp]
         L.lf_set_tune.argtypes = [vp, ctypes.POINTER(lf_tune)]
         L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
         L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
@@ -84,7 +85,8 @@ def lib():
         L.lf_last_error.restype = ctypes.c_char_p
         L.lf_free.argtypes = [vp]
         L.lf_free.restype = None
-        for name in ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
+        for name in ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render",
+                     "lf_render_reference",
                      "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
                      "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
                      "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply",
@@ -156,7 +158,8 @@ class Context:
 
 
 def lf_load_views(centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, img_fmt="rgba8", geo_fmt="f32",
-                  device_src=False) -> Context:
+                  device_src=False, disk_ext=None) -> Context:
+    """disk_ext: None for circular disks of disk_radius, else [n][4] oval extents (see lf_disk_extents)."""
     img_fmt = IMG_FORMATS.get(img_fmt, img_fmt)
     geo_fmt = GEO_FORMATS.get(geo_fmt, geo_fmt)
     centres = np.ascontiguousarray(centres, np.float64)
@@ -169,12 +172,22 @@ def lf_load_views(centres, rot, rgba8, zdepth, src_fov_deg, disk_radius, img_fmt
         zdepth = np.ascontiguousarray(zdepth, np.float32)
         n, h, w, _ = rgba8.shape
         m = zdepth.shape[1]
+    ext = None if disk_ext is None else np.ascontiguousarray(disk_ext, np.float64).reshape(n, 4)
     d = lf_views_desc(n, w, h, m, float(src_fov_deg), centres.ctypes.data, rot.ctypes.data, _ptr(rgba8),
-                      _ptr(zdepth), float(disk_radius), int(img_fmt), int(geo_fmt),
-                      LF_SRC_DEVICE if device_src else 0)
+                      _ptr(zdepth), float(disk_radius), None if ext is None else ext.ctypes.data, int(img_fmt),
+                      int(geo_fmt), LF_SRC_DEVICE if device_src else 0)
     h_ = ctypes.c_void_p()
     _check(lib().lf_load_views(ctypes.byref(d), ctypes.byref(h_)))
     return Context(h_.value, n, img_fmt, geo_fmt)
+
+
+def lf_disk_extents(centres, rot, scale=1.0):
+    """[n][4] extents (e+u, e-u, e+v, e-v) of the views' asymmetric oval disks."""
+    c = np.ascontiguousarray(centres, np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(np.asarray(rot, np.float64).reshape(-1, 9))
+    out = np.zeros((len(c), 4), np.float64)
+    _check(lib().lf_disk_extents(len(c), c.ctypes.data, r.ctypes.data, float(scale), out.ctypes.data))
+    return out
 
 
 def lf_stereo_eyes(head_pos, head_rot, ipd_m):
@@ -347,7 +360,7 @@ def lf_last_error() -> str:
 
 
 # names of every symbol include/lf.h declares (checked by the ABI test)
-EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_set_tune", "lf_render", "lf_render_reference",
+EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_reference",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
            "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",

@@ -31,11 +31,11 @@ def torch_mod():
     return torch
 
 
-def gpu_context(views, img_fmt="rgba32f", geo_fmt="f32", disk_radius=None):
+def gpu_context(views, img_fmt="rgba32f", geo_fmt="f32", disk_radius=None, disk_ext=None):
     from paper_1810_08860_amd import lf
     return lf.lf_load_views(views.centres, views.rot, views.rgba8, views.zdepth, views.src_fov_deg,
                             views.disk_radius if disk_radius is None else disk_radius, img_fmt=img_fmt,
-                            geo_fmt=geo_fmt)
+                            geo_fmt=geo_fmt, disk_ext=disk_ext)
 
 
 def gpu_render(ctx, eyes, hfov, res, want_aux=True):

@@ -77,6 +77,16 @@ def test_load_views_rejects_bad_frame_and_depth():
     assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL
 
 
+def test_load_views_rejects_bad_oval_extents():
+    for bad in (0.0, -0.1, np.inf, np.nan):
+        ext = np.full((2, 4), 0.05)
+        ext[1, 2] = bad
+        d, keep = _desc(disk_ext=ext.ctypes.data)
+        h = ctypes.c_void_p()
+        assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL and h.value is None
+        assert "extent 2" in lf.lf_last_error() and "view 1" in lf.lf_last_error()
+
+
 def test_null_context_and_arguments():
     L = lf.lib()
     assert L.lf_set_tune(None, None) == lf.LF_EINVAL
@@ -85,6 +95,7 @@ def test_null_context_and_arguments():
     res = np.array([8, 8], np.int32)
     assert L.lf_render(None, e, 1, 90.0, res.ctypes.data, 1, None, None, None) == lf.LF_EINVAL
     assert "context" in lf.lf_last_error()
+    assert L.lf_disk_extents(8, None, None, 1.0, None) == lf.LF_EINVAL
     L.lf_free(None)  # no-op
 
 
