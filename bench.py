@@ -14,7 +14,10 @@ Prints ONE JSON line. `value` is eye-view Mpix/s of the FP16/batched path
 graph-captured launch); the plain FP32 path (FP32 images and geometry, one
 launch sequence per stereo frame) is timed beside it, as are a mixed-size
 batch (64 stereo poses at 1080x1200 / 1440x1600 / 2160x2160 per eye, autotuned
-tile shape) and the FP64 oracle on the host cores.
+tile shape) and the FP64 oracle on the host cores. The batched FP16 path is
+also timed with the asymmetric oval disks of Sec. 4.4 (extents from the
+Delaunay 1-ring of each view) in place of the workload's circular disks: a
+different blending field, reported beside the headline, never as it.
 """
 from __future__ import annotations
 
@@ -377,7 +380,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
-    ap.add_argument("--variants", default="plain,fp16,rgba8,fp16_batched")
+    ap.add_argument("--variants", default="plain,fp16,rgba8,fp16_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
@@ -420,27 +423,31 @@ def main():
         f"in {time.perf_counter() - t0:.1f} s")
     eyes_all = [lf.lf_stereo_eyes(w.head_pos[k], w.head_rot[k], IPD) for k in range(len(w.head_pos))]
 
-    storage = {"plain": ("rgba32f", "f32"), "fp16": ("rgba16f", "f16"), "rgba8": ("rgba8", "f16"),
-               "fp16_batched": ("rgba16f", "f16")}
+    # (images, geometry, disks): "circle" = radius 1.5 x mean nearest-neighbour spacing, the workload's
+    # definition; "oval" = the asymmetric Delaunay 1-ring ovals of Sec. 4.4 (a different blending field)
+    storage = {"plain": ("rgba32f", "f32", "circle"), "fp16": ("rgba16f", "f16", "circle"),
+               "rgba8": ("rgba8", "f16", "circle"), "fp16_batched": ("rgba16f", "f16", "circle"),
+               "fp16_batched_oval": ("rgba16f", "f16", "oval")}
     chosen = [v for v in args.variants.split(",") if v]
     main_name = "fp16_batched" if "fp16_batched" in chosen else chosen[0]
     results, ctxs = {}, {}
     mixed = None
     for name in chosen:
-        img, geo = storage[name]
-        if (img, geo) not in ctxs:
+        key = storage[name]
+        if key not in ctxs:
             t0 = time.perf_counter()
-            ctxs[(img, geo)] = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
-                                                img_fmt=img, geo_fmt=geo)
-            log(f"[bench] loaded ({img}, {geo}) in {time.perf_counter() - t0:.1f} s")
-        ctx = ctxs[(img, geo)]
+            ext = lf.lf_disk_extents(V.centres, V.rot) if key[2] == "oval" else None
+            ctxs[key] = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
+                                         img_fmt=key[0], geo_fmt=key[1], disk_ext=ext)
+            log(f"[bench] loaded {key} in {time.perf_counter() - t0:.1f} s")
+        ctx = ctxs[key]
         prof = name == main_name
-        if name.endswith("_batched"):
+        if "_batched" in name:
             r = time_batched(lf, torch, ctx, w, args.steps, args.warmup, args.per_batch, profile=prof)
         else:
             r = time_variant(lf, torch, ctx, eyes_all, args.steps, args.warmup, profile=prof)
             del r["out"]
-        if prof:
+        if prof or key[2] == "oval":
             # work counters of the same frames (outside the timed region)
             acc = {k: 0 for k in lf.STAT_NAMES}
             n_stat = min(64, len(eyes_all))
@@ -451,16 +458,16 @@ def main():
             r["stats_per_frame"] = {k: v / n_stat for k, v in acc.items()}
         results[name] = r
         log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.4f} ms/stereo frame")
-    if not args.no_mixed and ("rgba16f", "f16") in ctxs:
+    if not args.no_mixed and ("rgba16f", "f16", "circle") in ctxs:
         log("[bench] mixed-size batch ...")
-        mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f16")], seed=4242)
+        mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f16", "circle")], seed=4242)
         log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']}, "
             f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
     corr = None
-    if not args.no_corrector and ("rgba16f", "f16") in ctxs and ("rgba32f", "f32") in ctxs:
+    if not args.no_corrector and ("rgba16f", "f16", "circle") in ctxs and ("rgba32f", "f32", "circle") in ctxs:
         log("[bench] corrector ...")
-        corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f16")], ctxs[("rgba32f", "f32")],
+        corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f16", "circle")], ctxs[("rgba32f", "f32", "circle")],
                              steps=args.corrector_steps)
         log(f"[bench] corrector: PSNR {corr['psnr_plain_db']:.2f} -> {corr['psnr_corrected_db']:.2f} dB, "
             f"{corr['ms_per_stereo_frame']:.3f} ms / stereo frame, {corr['achieved_tflops']:.0f} TFLOP/s")
@@ -482,7 +489,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_render_persistent" if main_name.endswith("_batched") else "k_render",
+            "kernel": "k_render_persistent" if "_batched" in main_name else "k_render",
             "kernel_ms": render_ms,
             "stereo_frames_per_launch": per_launch,
             "algorithmic_flop_per_launch": flops,
@@ -491,9 +498,10 @@ def main():
         }
 
     cpu = None
-    if not args.no_cpu_baseline and ("rgba32f", "f32") in ctxs:
+    if not args.no_cpu_baseline and ("rgba32f", "f32", "circle") in ctxs:
         log("[bench] cpu baseline (FP64 oracle) ...")
-        cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctxs[("rgba32f", "f32")], args.cpu_seconds)
+        cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctxs[("rgba32f", "f32", "circle")],
+                           args.cpu_seconds)
     for c in ctxs.values():
         c.close()
 
@@ -514,12 +522,12 @@ def main():
             "workload": "stereo 2x1440x1600 eye views at 100 deg from 1024 views of 1024^2 RGBA8 with 256^2 "
                         "depth meshes, 12 spheres + box, 3000 seeded head poses",
             "path": main_name,
-            "storage": dict(zip(("images", "geometry"), storage[main_name])),
+            "storage": dict(zip(("images", "geometry", "disks"), storage[main_name])),
             "stereo_frames_per_launch": m.get("frames_per_launch", 1),
         },
         "ms_per_stereo_frame": m["ms_per_stereo_frame"],
-        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms") if kk in v}
-                     for k, v in results.items()},
+        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms", "stats_per_frame")
+                         if kk in v} for k, v in results.items()},
         "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
         "mixed_batch": mixed,
         "corrector": corr,
