@@ -547,7 +547,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     const size_t ev_b = al(sizeof(EyeView) * (size_t)n_eyes * c->n);
     const size_t tl_b = al(sizeof(uint16_t) * (size_t)kListCap * tiles);
     const size_t tc_b = al(sizeof(int32_t) * (size_t)tiles);
-    const size_t q_b = 256, ft_b = al(sizeof(unsigned long long) * 2 * (size_t)n_eyes);
+    const size_t q_b = al(sizeof(unsigned int) * kQueueStride * kXcds), ft_b = al(sizeof(unsigned long long) * 2 * (size_t)n_eyes);
     const size_t need = ev_b + tl_b + tc_b + q_b + ft_b;
     if (need > B.buf_bytes || n_eyes > B.eyes_cap) {
         if (B.copied) LF_HIP(hipEventSynchronize(B.copied), "hipEventSynchronize");

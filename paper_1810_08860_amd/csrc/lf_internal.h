@@ -11,6 +11,7 @@ constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel argume
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
 constexpr int kBlk = 16;               // mesh cells per side of an inverse-depth bounds block
 constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
+constexpr int kQueueStride = 32;       // batch queue counters: one per XCD, 128 bytes apart
 constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
 constexpr int kSuperCap = 256;         // super-tile survivor list capacity (exact beyond: every view)
 
@@ -56,8 +57,9 @@ struct DiskBound {
     double R, vscale;
 };
 
-// A batch: eye table in device memory (sorted by tile_off / super_off), a
-// global tile queue and per-eye wall-clock stamps.
+// A batch: eye table in device memory (sorted by tile_off / super_off), the
+// tile queues (kXcds counters, kQueueStride apart) and per-eye wall-clock
+// stamps.
 struct BatchArgs {
     const EyeParam *eyes;
     int32_t n_eyes, total_tiles, total_supers;

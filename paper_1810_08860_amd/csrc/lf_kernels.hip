@@ -38,15 +38,6 @@
 
 namespace lf {
 
-// Work-group index -> work item, XCD-aware. Consecutive work-group ids are
-// dispatched round-robin over the 8 XCDs, each with its own L2; give XCD x
-// one contiguous range of items so neighbouring screen tiles (which read the
-// same source views) share an L2.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    const int q = G / kXcds, r = G % kXcds, x = b % kXcds;
-    return x * q + min(x, r) + b / kXcds;
-}
-
 __device__ __forceinline__ int find_eye(const EyeChunk &ch, int tile) {
     int e = 0;
     while (e + 1 < ch.n_eyes && tile >= ch.e[e + 1].tile_off) ++e;
@@ -530,10 +521,31 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
     render_tile<IMG, GEO, MODE>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a);
 }
 
+// Next tile of a persistent workgroup. The launch's tiles are cut into kXcds
+// contiguous ranges, each with its own queue counter (on its own 128-byte
+// line). Work-group ids are dispatched round-robin over the XCDs, so
+// workgroup b runs on XCD b % kXcds and drains that range first: the XCD's
+// CUs then work on neighbouring tiles of the same eyes, whose source texels
+// their shared L2 already holds, instead of every XCD fetching every eye's
+// texels from HBM into its own L2. A workgroup whose range is empty takes
+// tiles from the other ranges in turn (load balance). `probe` counts the
+// ranges found empty; once all are, the result is total_tiles (the exit).
+__device__ __forceinline__ int next_tile(const BatchArgs &b, int home, int &probe) {
+    while (probe < kXcds) {
+        const int q = (home + probe) % kXcds;
+        const int lo = (int)((int64_t)b.total_tiles * q / kXcds);
+        const int hi = (int)((int64_t)b.total_tiles * (q + 1) / kXcds);
+        const int t = lo + (int)atomicAdd(b.queue + q * kQueueStride, 1u);
+        if (t < hi) return t;
+        ++probe;
+    }
+    return b.total_tiles;
+}
+
 // Persistent form for batches: a grid sized to the machine; each workgroup
-// takes tiles from a global atomic queue (all eyes of the batch, any sizes)
-// until the queue is empty -- every workgroup reaches the exit once the
-// counter passes the last tile. Per eye, the earliest start and latest end
+// takes tiles from the queues above (all eyes of the batch, any sizes) until
+// every queue is empty -- each workgroup reaches the exit after at most
+// kXcds probes of empty queues. Per eye, the earliest start and latest end
 // wall-clock stamps of its tiles are kept (per-frame latency).
 // Seven waves per SIMD: the register budget that leaves room for a small
 // spill but hides more of the mesh walk's load latency than the default five.
@@ -541,7 +553,9 @@ template <int IMG, int GEO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void
 k_render_persistent(const BatchArgs b, const RenderArgs a) {
     __shared__ int s_tile;
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(b.queue, 1u);
+    const int home = blockIdx.x % kXcds;
+    int probe = 0;  // used by thread 0 only
+    if (threadIdx.x == 0) s_tile = next_tile(b, home, probe);
     __syncthreads();
     int tile = s_tile;
     int cur_e = -1, lo = 0, hi = 0;  // tiles [lo, hi) belong to eye cur_e
@@ -550,7 +564,7 @@ k_render_persistent(const BatchArgs b, const RenderArgs a) {
     while (tile < b.total_tiles) {
         __syncthreads();  // every thread has read s_tile
         // fetch the next tile now; the atomic's round trip overlaps this tile's work
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(b.queue, 1u);
+        if (threadIdx.x == 0) s_tile = next_tile(b, home, probe);
         if (tile < lo || tile >= hi) {
             const int e = find_eye_sorted(b.eyes, b.n_eyes, tile, false);
             if (threadIdx.x == 0) {
@@ -576,11 +590,11 @@ k_render_persistent(const BatchArgs b, const RenderArgs a) {
     }
 }
 
-// Start-of-batch reset: empty queue, per-eye stamps at (max, 0). A kernel
+// Start-of-batch reset: empty queues, per-eye stamps at (max, 0). A kernel
 // (not a memset) so the batch graph holds kernels only.
 __global__ void k_batch_reset(unsigned int *queue, unsigned long long *frame_t, int n_eyes) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *queue = 0u;
+    if (i < kXcds) queue[i * kQueueStride] = 0u;
     if (frame_t && i < n_eyes) {
         frame_t[2 * i] = ~0ull;
         frame_t[2 * i + 1] = 0ull;
