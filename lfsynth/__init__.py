@@ -179,6 +179,22 @@ def uniform(seed: int, count: int) -> np.ndarray:
     return out
 
 
+def prefilter_samples(seed: int, count: int, half_width: float):
+    """Seeded sample pattern for a Monte Carlo prefilter: count points uniform
+    in the unit disk (count,2) and count offsets uniform in the square
+    [-half_width, half_width]^2 (count,2). Samples come in antithetic pairs
+    (p, -p) for both sets, so the pattern is point-symmetric (count even)."""
+    if count % 2:
+        raise ValueError("count must be even (antithetic pairs)")
+    h = count // 2
+    u = uniform(seed, 4 * h).reshape(h, 4)
+    r = np.sqrt(u[:, 0])
+    a = 2.0 * np.pi * u[:, 1]
+    disk = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+    offs = (2.0 * u[:, 2:4] - 1.0) * half_width
+    return np.concatenate([disk, -disk]), np.concatenate([offs, -offs])
+
+
 # ----------------------------------------------------------------------------- workloads
 
 @dataclass

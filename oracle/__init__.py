@@ -14,6 +14,9 @@ Paper passages followed (all Sec. 4 of the paper):
   * per-view mesh ......... Sec. 4.5 (depth map, two triangles per pixel)
   * offline query L-bar ... Sec. 5.1 (denser / larger support reconstruction),
     used here as the supersampled reference render.
+  * prefilter ............. Sec. 5.1, Eqs. (4)-(5): Monte Carlo ratio estimate
+    over disk points x pixel-basis points, rays through the real-time mesh,
+    evaluated with the offline query.
 """
 from __future__ import annotations
 
@@ -78,6 +81,10 @@ def lib():
         L.orc_sample.argtypes = [ctypes.POINTER(_Views), i32, f64, f64, vp]
         L.orc_render_rays.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, vp, vp, vp, ctypes.POINTER(_Lists)]
         L.orc_ray_records.argtypes = [ctypes.POINTER(_Views), vp, vp, vp]
+        L.orc_prefilter.argtypes = [ctypes.POINTER(_Views), ctypes.POINTER(_Views), i32, f64, i32, vp, vp, i32,
+                                    i64, vp, vp, vp]
+        L.orc_basis.argtypes = [i32, f64]
+        L.orc_basis.restype = f64
         L.orc_views_size.restype = i32
         L.orc_rec_size.restype = i32
         L.orc_max_threads.restype = i32
@@ -254,6 +261,38 @@ def disk_extents(centres, rot):
     if not (ext > 0).all():
         raise ValueError("a disk has no 1-ring neighbour on one side of an axis")
     return ext, ring
+
+
+BASIS = {"box": 0, "lanczos2": 1}
+
+
+def basis(kind, d):
+    """Pixel reconstruction basis of the prefilter (one axis): box or Lanczos-2."""
+    return float(lib().orc_basis(BASIS[kind], float(d)))
+
+
+def prefilter(lbar: OracleViews, target: OracleViews, i, radius, disk_pts, pix_offs, kind="lanczos2", idx=None):
+    """Prefiltered colour (Sec. 5.1, Eq. (5)) of the pixels idx (all if None) of
+    view i of the real-time model `target`: J samples pair the unit-disk points
+    disk_pts (J,2) (scaled by the target disk radius) with pixel offsets
+    pix_offs (J,2) (pixels from the pixel centre); each ray starts at the disk
+    point and passes through target view i's mesh point at the offset image
+    position; `lbar` (the offline model) answers the ray query. A sample
+    without a mesh point or whose ray no offline disk covers is left out of
+    both sums. Returns
+    {"rgb": (n,3), "wsum": (n,)} with wsum the denominator of Eq. (5)."""
+    W, H = target.s.img_w, target.s.img_h
+    if idx is None:
+        idx = np.arange(W * H)
+    idx = np.ascontiguousarray(idx, np.int64)
+    dp = np.ascontiguousarray(disk_pts, np.float64).reshape(-1, 2)
+    po = np.ascontiguousarray(pix_offs, np.float64).reshape(-1, 2)
+    assert dp.shape == po.shape
+    rgb = np.zeros((len(idx), 3))
+    ws = np.zeros(len(idx))
+    lib().orc_prefilter(ctypes.byref(lbar.s), ctypes.byref(target.s), int(i), float(radius), dp.shape[0], _p(dp),
+                        _p(po), BASIS[kind], len(idx), _p(idx), _p(rgb), _p(ws))
+    return {"rgb": rgb, "wsum": ws}
 
 
 def disk(ov: OracleViews, i, o, e):

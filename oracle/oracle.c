@@ -21,6 +21,9 @@
  * depth pixel, Sec. 4.5). Pass 1 / pass 2 of Sec. 4.2 (accumulate numerator and
  * denominator, then divide) become two running sums and one division.
  *
+ * The prefilter of Sec. 5 (Eqs. (4)-(5)) is built on the same query: see
+ * orc_prefilter below.
+ *
  * The geometry is deliberately evaluated in WORLD space with the published
  * watertight ray/triangle test (Woop, Benthin & Wald 2013), over either all
  * triangles ("brute") or the cells visited by an Amanatides-Woo 2-D grid walk
@@ -399,6 +402,87 @@ void orc_render_rays(const orc_views *V, int64_t n_rays, const double *o, const 
         for (int a = 0; a < 3; ++a) rgb[3 * k + a] = ws > 0.0 ? acc[a] / ws : 0.0;
         if (wsum) wsum[k] = ws;
         if (count) count[k] = cnt;
+    }
+}
+
+/*
+ * Light field prefilter (Sec. 5, Eqs. (4)-(5)). The prefiltered value of pixel
+ * (x', y') of view i of the real-time model T is the ratio estimate
+ *
+ *     sum_j rho_i(u_j, v_j) sigma(s_j, t_j) Lbar(o_j, e_j) / sum_j rho_i(u_j, v_j) sigma(s_j, t_j)
+ *
+ * over J sample pairs: (u_j, v_j) a point of view i's disk (the synthetic
+ * aperture; disk_pts are points of the unit disk scaled by the target disk
+ * radius), (s_j, t_j) a point of the pixel basis' support around the pixel
+ * centre (pix_offs, in pixels). The ray origin o_j is the disk point in 3-D
+ * (c_i + u_j r_i + v_j u_i); the ray passes through the 3-D point of view i's
+ * mesh that projects to image position (s_j, t_j) (the nearest hit of the ray
+ * from c_i through that image point). Lbar is Eq. (2) over the offline model
+ * (its own views, meshes and disks).
+ *
+ * Readings: rho is the linear falloff of Sec. 4.1 (1 - |(du, dv)| for a unit
+ * disk point); sigma is separable, box (1 on |d| <= 1/2) or Lanczos-2
+ * (sinc(d) sinc(d/2) on |d| < 2); a sample whose image point has no mesh
+ * point (outside the mesh domain), or whose ray no disk of the offline model
+ * covers (Lbar undefined), is left out of both sums; a pixel whose
+ * denominator is 0 is (0, 0, 0).
+ */
+static double lanczos2(double x) {
+    x = fabs(x);
+    if (x >= 2.0) return 0.0;
+    if (x == 0.0) return 1.0;
+    const double px = M_PI * x;
+    return 2.0 * sin(px) * sin(0.5 * px) / (px * px);
+}
+
+double orc_basis(int32_t basis, double d) {
+    if (basis == 1) return lanczos2(d);
+    return fabs(d) <= 0.5 ? 1.0 : 0.0;
+}
+
+void orc_prefilter(const orc_views *Lbar, const orc_views *T, int32_t i, double radius, int32_t J,
+                   const double *disk_pts, const double *pix_offs, int32_t basis, int64_t n_pix,
+                   const int64_t *pix, double *rgb, double *wsum) {
+#ifdef _OPENMP
+    if (Lbar->threads > 0) omp_set_num_threads(Lbar->threads);
+#endif
+    const double *c = T->centres + 3 * i, *R = T->rot + 9 * i;
+    const double ts = tan(0.5 * T->src_fov_deg * M_PI / 180.0);
+    const int32_t W = T->img_w, H = T->img_h;
+    double r[3], u[3];
+    col3(R, 0, r);
+    col3(R, 1, u);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_pix; ++q) {
+        const double xc = (double)(pix[q] % W) + 0.5, yc = (double)(pix[q] / W) + 0.5;
+        double num[3] = {0, 0, 0}, den = 0.0;
+        for (int32_t j = 0; j < J; ++j) {
+            const double du = disk_pts[2 * j], dv = disk_pts[2 * j + 1];
+            const double rho = 1.0 - sqrt(du * du + dv * dv);
+            const double sigma = orc_basis(basis, pix_offs[2 * j]) * orc_basis(basis, pix_offs[2 * j + 1]);
+            const double wgt = rho * sigma;
+            if (!(rho > 0.0) || wgt == 0.0) continue;
+            /* the 3-D point of view i's mesh seen at image position (s, t) */
+            const double s = xc + pix_offs[2 * j], t = yc + pix_offs[2 * j + 1];
+            const double X = (2.0 * s / W - 1.0) * ts, Y = (1.0 - 2.0 * t / H) * ts;
+            double dir[3];
+            for (int a = 0; a < 3; ++a) dir[a] = R[3 * a + 0] * X + R[3 * a + 1] * Y + R[3 * a + 2];
+            const double th = orc_mesh_hit(T, i, c, dir);
+            if (!isfinite(th)) continue;
+            double o[3], e[3];
+            for (int a = 0; a < 3; ++a) {
+                o[a] = c[a] + radius * (du * r[a] + dv * u[a]);
+                e[a] = c[a] + th * dir[a] - o[a];
+            }
+            double L[3], ws;
+            int32_t cnt;
+            orc_render_rays(Lbar, 1, o, e, L, &ws, &cnt, NULL);
+            if (!(ws > 0.0)) continue;
+            for (int a = 0; a < 3; ++a) num[a] += wgt * L[a];
+            den += wgt;
+        }
+        for (int a = 0; a < 3; ++a) rgb[3 * q + a] = den != 0.0 ? num[a] / den : 0.0;
+        if (wsum) wsum[q] = den;
     }
 }
 
