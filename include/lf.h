@@ -147,6 +147,44 @@ int lf_set_tune(lf_ctx *c, const lf_tune *t);
 int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
               float *out_rgb, float *out_wsum, uint8_t *out_count, void *hip_stream);
 
+/* Pixel reconstruction basis of the prefilter (one axis; the 2-D basis is the
+ * product of two): box, 1 on |d| <= 1/2; Lanczos-2, sinc(d) sinc(d/2) on
+ * |d| < 2 with sinc(x) = sin(pi x) / (pi x). */
+enum { LF_BASIS_BOX = 0, LF_BASIS_LANCZOS2 = 1 };
+
+/*
+ * Light field prefilter (Sec. 5, Eqs. (4)-(5)). For every pixel (x, y) of each
+ * listed view i the result is the Monte Carlo ratio estimate
+ *
+ *   sum_j rho(du_j, dv_j) sigma(ds_j) sigma(dt_j) Lbar(o_j, e_j) / sum_j (same weights)
+ *
+ * with rho = 1 - |(du, dv)| the linear disk falloff and sigma the basis. The
+ * ray of sample j starts at the point o_j = c_i + radius (du_j r_i + dv_j u_i)
+ * of view i's disk (the synthetic aperture of the real-time model, radius in
+ * metres) and passes through the point of view i's mesh that view i sees at
+ * image position (x + 1/2 + ds_j, y + 1/2 + dt_j) (pixel units). Lbar is the
+ * query of Eq. (2) over the context's views, meshes and disks (the offline
+ * model). A sample whose image position has no mesh point (outside the mesh
+ * domain) or whose ray no disk of the context covers is left out of both
+ * sums; a pixel with an empty denominator is (0, 0, 0). The same J samples
+ * serve every pixel.
+ *
+ *   views      host int32 [n_views], indices of the views to prefilter (any order,
+ *              repeats allowed); each is rendered at the context's image size
+ *   disk_pts   host float64 [J][2], points of the unit disk (|p| <= 1)
+ *   pix_offs   host float64 [J][2], offsets from the pixel centre in pixels (|.| <= 64)
+ *   basis      LF_BASIS_BOX or LF_BASIS_LANCZOS2
+ *   out_rgb    DEVICE float [n_views][img_h][img_w][3], overwritten
+ *   out_wsum   DEVICE float [n_views][img_h][img_w], receives the denominator
+ *
+ * Source images must be square. Asynchronous on hip_stream; LF_EINVAL for a
+ * NULL pointer, an empty list, a view index out of range, a non-positive
+ * radius, a disk point outside the unit disk or an unknown basis.
+ */
+int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *disk_pts,
+                 const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb, float *out_wsum,
+                 void *hip_stream);
+
 /*
  * Offline reference render (the analogue of the high-quality offline query of
  * Sec. 5.1): ss x ss regular sub-pixel rays per pixel, disks of radius

@@ -173,6 +173,10 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
     ch.n_eyes = n;
     ch.tile_w = tw;
     ch.tile_h = th;
+    ch.M = c->M;
+    ch.NB = num_blocks(c->M);
+    ch.sM = (float)(c->M / (2.0 * c->tan_s));
+    ch.cM = (float)(0.5 * (c->M - 1));
     const double tx = std::tan(0.5 * hfov_deg * M_PI / 180.0);
     int32_t tiles = 0, supers = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -183,6 +187,8 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
         E.H = res[2 * k + 1];
         E.tx = (float)tx;
         E.ty = (float)(tx * E.H / E.W);
+        E.sx = (float)(2.0 * tx / E.W);
+        E.sy = (float)(2.0 * tx / E.W);  // square pixels: 2 ty / H = 2 tx / W
         E.tiles_x = (E.W + tw - 1) / tw;
         E.tiles_y = (E.H + th - 1) / th;
         E.tile_off = tiles;
@@ -190,6 +196,7 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
         E.supers_y = (E.tiles_y + kSuper - 1) / kSuper;
         E.super_off = supers;
         E.pix_off = pix_off;
+        E.src_view = -1;
         tiles += E.tiles_x * E.tiles_y;
         supers += E.supers_x * E.supers_y;
         pix_off += (int64_t)E.W * E.H;
@@ -202,9 +209,6 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     RenderArgs a;
     std::memset(&a, 0, sizeof a);
     a.n_views = c->n;
-    a.img = c->img;
-    a.geo = c->geo;
-    a.blk = c->blk;
     a.NB = num_blocks(c->M);
     a.M = c->M;
     a.img_w = c->img_w;
@@ -220,10 +224,20 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     // R is the context's radius times the call's disk scale; oval extents scale alike
     a.ext_inv = c->ext_inv;
     a.ext_inv_scale = (float)(c->R / R);
-    a.texels_per_view = (int64_t)c->img_w * c->img_h;
-    a.cells_per_view = (int64_t)(c->M - 1) * (c->M - 1);
     a.scale = 1.0f;
     return a;
+}
+
+// Where each view's mesh cells, image and inverse-depth blocks start.
+ViewBases view_bases(const lf_ctx *c) {
+    ViewBases vb;
+    vb.geo = static_cast<const char *>(c->geo);
+    vb.img = static_cast<const char *>(c->img);
+    vb.blk = c->blk;
+    vb.geo_bytes = (int64_t)(c->M - 1) * (c->M - 1) * (c->geo_fmt == LF_GEO_F32 ? 16 : 8);
+    vb.img_bytes = (int64_t)c->img_w * c->img_h * (c->img_fmt == LF_IMG_RGBA8 ? 4 : (c->img_fmt == LF_IMG_RGBA16F ? 8 : 16));
+    vb.blk_per_view = (int64_t)num_blocks(c->M) * num_blocks(c->M);
+    return vb;
 }
 
 // Prep + cull for one chunk of eyes; fills the table/list pointers of `a`.
@@ -240,7 +254,7 @@ int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t 
     int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
     // conservative disk bounds for the tile test; the exact per-ray test decides in k_render
     const DiskBound db{c->vrad, R, R / c->R};
-    LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, ev, s); }), "k_prep launch");
+    LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, view_bases(c), ev, s); }), "k_prep launch");
     LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, tl, tc, s); }), "k_cull launch");
     a.ev = ev;
     a.tile_list = tl;
@@ -482,6 +496,82 @@ int lf_render_reference(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hf
     return LF_OK;
 }
 
+// One axis of the prefilter's pixel reconstruction basis (Sec. 5.1): box or
+// Lanczos-2, sinc(x) sinc(x / 2) on |x| < 2.
+static double basis_weight(int32_t basis, double x) {
+    x = std::fabs(x);
+    if (basis == LF_BASIS_BOX) return x <= 0.5 ? 1.0 : 0.0;
+    if (x >= 2.0) return 0.0;
+    if (x == 0.0) return 1.0;
+    const double px = M_PI * x;
+    return std::sin(px) / px * (std::sin(0.5 * px) / (0.5 * px));
+}
+
+int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *disk_pts,
+                 const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb, float *out_wsum,
+                 void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!views || !disk_pts || !pix_offs) return fail(LF_EINVAL, "views, disk_pts and pix_offs must not be NULL");
+    if (!out_rgb || !out_wsum) return fail(LF_EINVAL, "out_rgb and out_wsum must not be NULL");
+    if (n_views <= 0) return fail(LF_EINVAL, "n_views must be positive (got %d)", n_views);
+    if (n_samples <= 0 || n_samples > (1 << 20)) return fail(LF_EINVAL, "n_samples must be in [1, 2^20] (got %d)", n_samples);
+    if (basis != LF_BASIS_BOX && basis != LF_BASIS_LANCZOS2) return fail(LF_EINVAL, "unknown basis %d", basis);
+    if (!(radius > 0.0) || !std::isfinite(radius)) return fail(LF_EINVAL, "radius must be finite and > 0");
+    if (c->img_w != c->img_h) return fail(LF_EINVAL, "the prefilter needs square source images");
+    for (int32_t k = 0; k < n_views; ++k)
+        if (views[k] < 0 || views[k] >= c->n) return fail(LF_EINVAL, "views[%d] = %d out of range", k, views[k]);
+    for (int32_t j = 0; j < n_samples; ++j) {
+        const double du = disk_pts[2 * j], dv = disk_pts[2 * j + 1], ds = pix_offs[2 * j], dt = pix_offs[2 * j + 1];
+        if (!(du * du + dv * dv <= 1.0)) return fail(LF_EINVAL, "disk_pts[%d] is not in the unit disk", j);
+        if (!(std::fabs(ds) <= 64.0 && std::fabs(dt) <= 64.0))
+            return fail(LF_EINVAL, "pix_offs[%d] must be finite and within 64 pixels", j);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t npx = (int64_t)c->img_w * c->img_h;
+    LF_HIP(hipMemsetAsync(out_rgb, 0, sizeof(float) * 3 * npx * n_views, s), "hipMemsetAsync(out_rgb)");
+    LF_HIP(hipMemsetAsync(out_wsum, 0, sizeof(float) * npx * n_views, s), "hipMemsetAsync(out_wsum)");
+    const double hfov = 2.0 * std::atan(c->tan_s) * 180.0 / M_PI;
+    std::vector<lf_eye> eyes(kMaxEyesPerLaunch);
+    std::vector<int32_t> res(2 * kMaxEyesPerLaunch);
+    for (int32_t j = 0; j < n_samples; ++j) {
+        const double du = disk_pts[2 * j], dv = disk_pts[2 * j + 1], ds = pix_offs[2 * j], dt = pix_offs[2 * j + 1];
+        const double rho = 1.0 - std::sqrt(du * du + dv * dv);
+        const double wgt = rho * basis_weight(basis, ds) * basis_weight(basis, dt);
+        if (!(rho > 0.0) || wgt == 0.0) continue;
+        for (int32_t k0 = 0; k0 < n_views; k0 += kMaxEyesPerLaunch) {
+            const int32_t nk = std::min(kMaxEyesPerLaunch, n_views - k0);
+            // one eye per target view: at the sample's point of the view's disk, with the view's frame
+            for (int32_t k = 0; k < nk; ++k) {
+                const double *vc = &c->h_vt[12 * (size_t)views[k0 + k]];
+                const double *R = vc + 3;
+                for (int a = 0; a < 3; ++a) eyes[k].pos[a] = vc[a] + radius * (du * R[3 * a] + dv * R[3 * a + 1]);
+                std::memcpy(eyes[k].rot, R, sizeof(double) * 9);
+                res[2 * k] = c->img_w;
+                res[2 * k + 1] = c->img_h;
+            }
+            EyeChunk ch;
+            fill_chunk(c, ch, eyes.data(), nk, hfov, res.data(), (int64_t)k0 * npx, c->tune.tile_w, c->tune.tile_h);
+            for (int32_t k = 0; k < nk; ++k) {
+                EyeParam &E = ch.e[k];
+                E.src_view = views[k0 + k];
+                E.off_x = (float)ds;
+                E.off_y = (float)dt;
+                E.par_u = (float)(radius * du);
+                E.par_v = (float)(radius * dv);
+            }
+            RenderArgs a = base_args(c, c->R);
+            int rc = prep_and_cull(c, ch, a, c->R, s);
+            if (rc) return rc;
+            a.out_rgb = out_rgb;
+            a.out_wsum = out_wsum;
+            a.scale = (float)wgt;
+            LF_HIP(launch_render(ch, a, c->img_fmt, c->geo_fmt, MODE_PREFILTER, s), "k_render launch");
+        }
+    }
+    LF_HIP(launch_prefilter_finish(out_rgb, out_wsum, npx * n_views, s), "k_prefilter_finish launch");
+    return LF_OK;
+}
+
 int lf_debug_candidates(lf_ctx *c, const lf_eye *eye, double hfov_deg, int32_t W, int32_t H, int32_t cap,
                         int32_t *out_cand, int32_t *out_contrib, int32_t *out_ncand, void *hip_stream) {
     if (!c) return fail(LF_EINVAL, "NULL context");
@@ -605,7 +695,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
         batch_release_graph(c);
         if (!B.cap_stream) LF_HIP(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
         int per_cu = 0, n_cu = 0;
-        LF_HIP(persistent_occupancy(c->img_fmt, c->geo_fmt, t.tile_w * t.tile_h, &per_cu), "occupancy");
+        LF_HIP(persistent_occupancy(c->img_fmt, c->geo_fmt, c->ext_inv != nullptr, t.tile_w * t.tile_h, &per_cu),
+               "occupancy");
         LF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
         const int grid = std::max(1, std::min(per_cu * n_cu, tiles));
         const DiskBound db{c->vrad, c->R, 1.0};
@@ -614,7 +705,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
             LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
         }
         LF_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, c->img_fmt, c->geo_fmt, grid, B.cap_stream,
+        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, view_bases(c), c->img_fmt, c->geo_fmt, grid, B.cap_stream,
                                     nullptr, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(B.cap_stream, &g);

@@ -22,12 +22,20 @@ struct EyeParam {
     double pos[3];
     double rot[9];   // row-major, columns (r, u, f)
     float tx, ty;    // half-FOV tangents
+    float sx, sy;    // image-plane pitch of one pixel: 2 tx / W, 2 ty / H
     int32_t W, H;
     int32_t tiles_x, tiles_y;
     int32_t tile_off;  // first tile of this eye within the launch
     int32_t supers_x, supers_y;
     int32_t super_off; // first culling super-tile of this eye within the launch
     int64_t pix_off;   // first output pixel of this eye
+    // prefilter eyes (MODE_PREFILTER; src_view = -1 otherwise): the eye sits at a
+    // point of view src_view's disk, displaced by (par_u, par_v) metres along the
+    // view's r and u axes, with the view's frame and camera; the ray of pixel
+    // (x, y) passes through the view's mesh point seen at (x + off_x, y + off_y)
+    int32_t src_view;
+    float off_x, off_y;
+    float par_u, par_v;
 };
 
 struct EyeChunk {
@@ -36,17 +44,39 @@ struct EyeChunk {
     int32_t total_supers;
     int32_t pad;
     int32_t tile_w, tile_h;
+    // mesh grid of the light field (for the culling of prefilter eyes)
+    int32_t M, NB;
+    float sM, cM;
     EyeParam e[kMaxEyesPerLaunch];
 };
 
-// Per (eye, view) transform, 64 bytes: e' = M (X, Y, 1) is the eye ray in the
-// view's frame, o' the eye centre in the view's frame.
+// Per (eye, view) record, 96 bytes: e' = M (X, Y, 1) is the eye ray in the
+// view's frame, o' the eye centre in the view's frame; the view's mesh cells,
+// image and inverse-depth blocks are addressed through the pointers here, so
+// the render loop needs no per-view address arithmetic of its own.
 struct alignas(16) EyeView {
     float m[9];
     float o[3];
     float wmin, wmax;  // inverse-depth range of the view's mesh
     int32_t view;
     float rk;          // radius bounding the view's disk, padded for the conservative tile test
+    const void *cells;  // this view's mesh cells
+    const void *img;    // this view's image
+    const float2 *blk;  // this view's inverse-depth blocks
+    int64_t pad;
+};
+
+// Where each view's data starts: base + view * stride (bytes; blocks in elements).
+struct ViewBases {
+    const char *geo, *img;
+    const float2 *blk;
+    int64_t geo_bytes, img_bytes, blk_per_view;
+};
+
+// Mesh grid of the light field as the culling of prefilter eyes needs it.
+struct CullGeo {
+    int32_t M, NB;
+    float sM, cM;
 };
 
 // Bound of every disk for culling: the radius of view v's disk is
@@ -68,28 +98,26 @@ struct BatchArgs {
     unsigned long long *frame_t;  // [n_eyes][2]: earliest tile start, latest tile end
 };
 
-enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3 };
+enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3, MODE_PREFILTER = 4 };
+enum { DISK_CIRCLE = 0, DISK_OVAL = 1 };
 
 struct RenderArgs {
     const EyeView *ev;          // [n_eyes][n_views]
     int32_t n_views;
     const uint16_t *tile_list;  // [tiles][kListCap]
     const int32_t *tile_count;  // [tiles]
-    const void *img;
-    const void *geo;
-    const float2 *blk;          // [n_views][NB][NB] inverse-depth bounds per cell block
-    int32_t NB;
+    int32_t NB;                 // inverse-depth blocks per side of a view's mesh
     int32_t M, img_w, img_h;
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
     float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
     float R, invR;              // circular disks
     const float4 *ext_inv;      // oval disks (null: circles): [n] 1/e+u, 1/e-u, 1/e+v, 1/e-v
     float ext_inv_scale;        // multiplies ext_inv (1 / disk scale)
-    int64_t texels_per_view, cells_per_view;
     float *out_rgb;
     float *out_wsum;
     uint8_t *out_count;
     // sub-pixel (reference) passes: ray through (x + sub_x, y + sub_y); out += scale * L
+    // prefilter passes: out += scale * L and out_wsum += scale where L is defined
     float sub_x, sub_y, scale;
     int32_t accumulate;
     // debug lists
@@ -109,7 +137,7 @@ hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n,
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
-                       EyeView *ev, hipStream_t s);
+                       const ViewBases &vb, EyeView *ev, hipStream_t s);
 hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_t *tile_list, int32_t *tile_count,
                        hipStream_t s);
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
@@ -117,8 +145,11 @@ hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, i
 // reset + prep + cull + persistent render of a batch (a.ev / tile lists are the batch's buffers)
 // ev_a / ev_b (may be null) are recorded just before / after the persistent render kernel
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
-                        hipEvent_t ev_b);
-hipError_t persistent_occupancy(int img_fmt, int geo_fmt, int block, int *per_cu);
+                        const DiskBound &db, const ViewBases &vb, int img_fmt, int geo_fmt, int grid, hipStream_t s,
+                        hipEvent_t ev_a, hipEvent_t ev_b);
+// occupancy of the persistent render kernel (oval: the oval-disk form)
+hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu);
+// out[p] /= wsum[p] (0 where wsum[p] == 0), p < n pixels of RGB
+hipError_t launch_prefilter_finish(float *out_rgb, const float *wsum, int64_t n, hipStream_t s);
 
 }  // namespace lf

@@ -38,6 +38,9 @@
 
 namespace lf {
 
+// kernel arguments travel in a 4 KiB segment
+static_assert(sizeof(EyeChunk) + sizeof(RenderArgs) <= 4096, "k_render arguments exceed 4 KiB");
+
 __device__ __forceinline__ int find_eye(const EyeChunk &ch, int tile) {
     int e = 0;
     while (e + 1 < ch.n_eyes && tile >= ch.e[e + 1].tile_off) ++e;
@@ -142,10 +145,12 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
 
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
 __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__restrict__ vt,
-                                            const float2 *__restrict__ wr, int v, const DiskBound &db) {
+                                            const float2 *__restrict__ wr, int v, const DiskBound &db,
+                                            const ViewBases &vb) {
     const double *c = vt + 12 * (int64_t)v;
     const double *R = c + 3;
     EyeView out;
+    double oz = 0.0;
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b) {
             double s = 0.0;
@@ -155,24 +160,32 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
         double s = 0.0;
         for (int r = 0; r < 3; ++r) s += R[3 * r + a] * (E.pos[r] - c[r]);
         out.o[a] = (float)s;
+        oz = s;
     }
     const float2 w = wr[v];
     out.wmin = w.x;
     out.wmax = w.y;
+    // an eye in front of the view's disk plane (z' = oz > 0 in the view's frame)
+    // sees only mesh points beyond its own depth: inverse depth below 1 / oz
+    if (oz > 0.0) out.wmax = fminf(out.wmax, (float)(1.0 / oz));
     out.view = v;
     // padded by 1e-4 relative and 1e-7 m: the FP32 tile test may not drop a
     // disk that the exact per-ray test keeps
     out.rk = (float)((db.vrad ? (double)db.vrad[v] * db.vscale : db.R) * (1.0 + 1e-4) + 1e-7);
+    out.cells = vb.geo + v * vb.geo_bytes;
+    out.img = vb.img + v * vb.img_bytes;
+    out.blk = vb.blk + v * vb.blk_per_view;
+    out.pad = 0;
     return out;
 }
 
 __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
                                               const float2 *__restrict__ wr, int32_t n, const DiskBound db,
-                                              EyeView *__restrict__ ev) {
+                                              const ViewBases vb, EyeView *__restrict__ ev) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = blockIdx.y;
     if (v >= n || e >= ch.n_eyes) return;
-    ev[(int64_t)e * n + v] = eye_view(ch.e[e], vt, wr, v, db);
+    ev[(int64_t)e * n + v] = eye_view(ch.e[e], vt, wr, v, db, vb);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -242,6 +255,46 @@ __device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, f
     return allp || alln || best <= R * R;
 }
 
+// Image-plane rectangle [X0,X1] x [Y1,Y0] holding the rays of a prefilter eye
+// through the pixels whose plain rectangle is given: pixel (x, y) sends its ray
+// to (X - par_u w, Y - par_v w), where (X, Y) is its position shifted by the
+// sample offset and w the source mesh's inverse depth there, which the
+// inverse-depth blocks of the source view under the shifted rectangle bound.
+// False when the shifted rectangle misses the mesh domain (no ray at all).
+__device__ __forceinline__ bool prefilter_rect(const EyeParam &E, const CullGeo &g, const float2 *__restrict__ blk,
+                                               float &X0, float &X1, float &Y0, float &Y1) {
+    X0 = fmaf(E.off_x, E.sx, X0);
+    X1 = fmaf(E.off_x, E.sx, X1);
+    Y0 = fmaf(-E.off_y, E.sy, Y0);
+    Y1 = fmaf(-E.off_y, E.sy, Y1);
+    const float lim = (float)(g.M - 1);
+    const float gx0 = fmaf(X0, g.sM, g.cM), gx1 = fmaf(X1, g.sM, g.cM);
+    const float gy0 = fmaf(-Y0, g.sM, g.cM), gy1 = fmaf(-Y1, g.sM, g.cM);
+    if (gx1 < 0.0f || gx0 > lim || gy1 < 0.0f || gy0 > lim) return false;
+    const int Mc = g.M - 1;
+    const int j0 = min(max((int)floorf(gx0), 0), Mc - 1) / kBlk, j1 = min(max((int)floorf(gx1), 0), Mc - 1) / kBlk;
+    const int k0 = min(max((int)floorf(gy0), 0), Mc - 1) / kBlk, k1 = min(max((int)floorf(gy1), 0), Mc - 1) / kBlk;
+    float wlo = INFINITY, whi = -INFINITY;
+    for (int bk = k0; bk <= k1; ++bk)
+        for (int bi = j0; bi <= j1; ++bi) {
+            const float2 b = blk[bk * g.NB + bi];
+            wlo = fminf(wlo, b.x);
+            whi = fmaxf(whi, b.y);
+        }
+    const float ua = E.par_u * wlo, ub = E.par_u * whi, va = E.par_v * wlo, vb = E.par_v * whi;
+    X0 -= fmaxf(ua, ub);
+    X1 -= fminf(ua, ub);
+    Y0 -= fminf(va, vb);
+    Y1 -= fmaxf(va, vb);
+    // one part in 1e5 of slack for the FP32 evaluation of the above
+    const float sx = 1e-5f * (fabsf(X0) + fabsf(X1)) + 1e-7f, sy = 1e-5f * (fabsf(Y0) + fabsf(Y1)) + 1e-7f;
+    X0 -= sx;
+    X1 += sx;
+    Y0 += sy;
+    Y1 -= sy;
+    return true;
+}
+
 __device__ __forceinline__ int find_eye_super(const EyeChunk &ch, int super) {
     int e = 0;
     while (e + 1 < ch.n_eyes && super >= ch.e[e + 1].super_off) ++e;
@@ -263,25 +316,27 @@ struct CullSmem {
 };
 
 __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int tile_w, int tile_h,
-                                           const EyeView *__restrict__ eve, int32_t n,
+                                           const EyeView *__restrict__ eve, int32_t n, const CullGeo &g,
                                            uint16_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
                                            CullSmem &sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int tx0 = (local % E.supers_x) * kSuper, ty0 = (local / E.supers_x) * kSuper;
     const int tx1 = min(tx0 + kSuper, E.tiles_x), ty1 = min(ty0 + kSuper, E.tiles_y);
-    const float sxp = 2.0f * E.tx / E.W, syp = 2.0f * E.ty / E.H;
+    const float sxp = E.sx, syp = E.sy;
 
+    const float2 *pblk = E.src_view >= 0 ? eve[E.src_view].blk : nullptr;
     // phase 1: all views against the super-tile
     {
         const int x0 = tx0 * tile_w, x1 = min(tx1 * tile_w, E.W);
         const int y0 = ty0 * tile_h, y1 = min(ty1 * tile_h, E.H);
-        const float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
-        const float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
+        float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
+        float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
+        const bool any = E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1);
         int scount = 0;
         for (int base = 0; base < n; base += 256) {
             const int v = base + (int)threadIdx.x;
-            const bool keep = v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
+            const bool keep = any && v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
             const uint64_t mask = __ballot(keep);
             if (lane == 0) sm.wcnt[wave] = __popcll(mask);
             __syncthreads();
@@ -310,9 +365,10 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
         if (active) {
             const int x0 = tx * tile_w, x1 = min(x0 + tile_w, E.W);
             const int y0 = ty * tile_h, y1 = min(y0 + tile_h, E.H);
-            const float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
-            const float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
-            for (int b = 0; b < ns; b += 64) {
+            float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
+            float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
+            const bool any = E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1);
+            for (int b = 0; any && b < ns; b += 64) {
                 const int s = b + lane;
                 const int v = s < ns ? (sover ? s : (int)sm.slist[s]) : -1;
                 const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
@@ -341,7 +397,8 @@ __global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const EyeView *
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_super(ch, super);
-    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, tile_list,
+    const CullGeo g{ch.M, ch.NB, ch.sM, ch.cM};
+    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, g, tile_list,
                tile_count, sm);
 }
 
@@ -365,7 +422,8 @@ __global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const Eye
     const int super = blockIdx.x;
     const int e = find_eye_sorted(b.eyes, b.n_eyes, super, true);
     const EyeParam E = b.eyes[e];
-    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, tile_list, tile_count,
+    const CullGeo g{0, 0, 0.0f, 0.0f};  // batch eyes are plain eyes (src_view = -1)
+    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, g, tile_list, tile_count,
                sm);
 }
 
@@ -395,9 +453,10 @@ __device__ __forceinline__ T uniform_load(const T *p) {
 }
 
 // One screen tile of eye E (index e) by one workgroup of tile_w x tile_h
-// threads. Each candidate view's record and the per-view base addresses are
-// wave-uniform and live in SGPRs; a lane holds only its own ray's state.
-template <int IMG, int GEO, int MODE>
+// threads. Each candidate view's record (with the view's data addresses) is
+// wave-uniform and lives in SGPRs; a lane holds only its own ray's state.
+// DISK: DISK_CIRCLE or DISK_OVAL (the asymmetric disks of Sec. 4.4).
+template <int IMG, int GEO, int MODE, int DISK>
 __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, int tile_w, int tile_h,
                                             const RenderArgs &a) {
     tile = __builtin_amdgcn_readfirstlane(tile);
@@ -409,21 +468,30 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     const int bpr = tile_w >> 3;
     const int px = tx0 + (wave % bpr) * 8 + (lane & 7);
     const int py = ty0 + (wave / bpr) * 8 + (lane >> 3);
-    const bool inside = px < E.W && py < E.H;
+    const bool inside_img = px < E.W && py < E.H;
 
-    const float sub_x = MODE == MODE_SUBPIXEL ? a.sub_x : 0.5f, sub_y = MODE == MODE_SUBPIXEL ? a.sub_y : 0.5f;
-    const float X = (2.0f * ((float)px + sub_x) / (float)E.W - 1.0f) * E.tx;
-    const float Y = (1.0f - 2.0f * ((float)py + sub_y) / (float)E.H) * E.ty;
+    const float sub_x = MODE == MODE_SUBPIXEL ? a.sub_x : (MODE == MODE_PREFILTER ? 0.5f + E.off_x : 0.5f);
+    const float sub_y = MODE == MODE_SUBPIXEL ? a.sub_y : (MODE == MODE_PREFILTER ? 0.5f + E.off_y : 0.5f);
+    float X = fmaf((float)px + sub_x, E.sx, -E.tx);
+    float Y = fmaf(-((float)py + sub_y), E.sy, E.ty);
     const int64_t pix = E.pix_off + (int64_t)py * E.W + px;
 
     const int cnt = uniform_load(a.tile_count + tile);
     const bool overflow = cnt > kListCap;
     const int total = overflow ? a.n_views : cnt;
     const EyeView *eve = a.ev + (int64_t)e * a.n_views;
+    bool inside = inside_img;
+    if (MODE == MODE_PREFILTER && inside) {
+        // the ray leaves the eye (a point of the source view's disk) towards the
+        // source mesh point seen at (X, Y): in the eye's image plane that is
+        // (X - par_u w, Y - par_v w) with w the mesh's inverse depth there
+        float w = 0.0f;
+        inside = mesh_point<GEO>(uniform_load(eve + E.src_view).cells, a.M, a.sM, a.cM, X, Y, w);
+        X = fmaf(-E.par_u, w, X);
+        Y = fmaf(-E.par_v, w, Y);
+    }
     // the list's 16-bit entries, read in pairs (the list of a tile starts 4-byte aligned)
     const uint32_t *tl = reinterpret_cast<const uint32_t *>(a.tile_list + (int64_t)tile * kListCap);
-    const int64_t geo_bytes = a.cells_per_view * (GEO == 0 ? 16 : 8);
-    const int64_t img_bytes = a.texels_per_view * (IMG == 0 ? 4 : (IMG == 1 ? 8 : 16));
 
     float accr = 0.0f, accg = 0.0f, accb = 0.0f, ws = 0.0f;
     int nc = 0, nh = 0, n_tests = 0, n_cells = 0;
@@ -437,8 +505,9 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             const EyeView v = uniform_load(eve + vid);
             RayView rv;
             ++n_tests;
-            const bool cand = a.ext_inv ? disk_test_oval(v, X, Y, uniform_load(a.ext_inv + v.view), a.ext_inv_scale, rv)
-                                        : disk_test(v, X, Y, a.R, a.invR, rv);
+            const bool cand = DISK == DISK_OVAL
+                                  ? disk_test_oval(v, X, Y, uniform_load(a.ext_inv + v.view), a.ext_inv_scale, rv)
+                                  : disk_test(v, X, Y, a.R, a.invR, rv);
             if (!cand) continue;
             if (MODE == MODE_STATS) ++nc;
             if (MODE == MODE_DEBUG) {
@@ -446,9 +515,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
                 ++nc;
             }
             float wh;
-            const void *cells = reinterpret_cast<const char *>(a.geo) + (int64_t)v.view * geo_bytes;
-            const float2 *blk = a.blk + (int64_t)v.view * a.NB * a.NB;
-            if (!march<GEO>(cells, blk, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh,
+            if (!march<GEO>(v.cells, v.blk, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh,
                             n_cells))
                 continue;
             if (MODE == MODE_DEBUG) {
@@ -458,14 +525,25 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             }
             const float Xs = fmaf(wh, rv.Dx, rv.Vx), Ys = fmaf(wh, rv.Dy, rv.Vy);
             const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
-            const void *img = reinterpret_cast<const char *>(a.img) + (int64_t)v.view * img_bytes;
-            const Rgb col = bilinear<IMG>(img, a.img_w, a.img_h, tpx, tpy);
+            const Rgb col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
             accr = fmaf(rv.rho, col.r, accr);
             accg = fmaf(rv.rho, col.g, accg);
             accb = fmaf(rv.rho, col.b, accb);
             ws += rv.rho;
             ++nh;
         }
+    }
+    if (MODE == MODE_PREFILTER) {
+        // one sample of Eq. (5): out += scale * L, wsum += scale where L is defined
+        if (inside && ws > 0.0f) {
+            const float k = texel_scale<IMG>() * fast_rcp(ws);
+            float *o = a.out_rgb + pix * 3;
+            o[0] = fmaf(a.scale, accr * k, o[0]);
+            o[1] = fmaf(a.scale, accg * k, o[1]);
+            o[2] = fmaf(a.scale, accb * k, o[2]);
+            a.out_wsum[pix] += a.scale;
+        }
+        return;
     }
     if (MODE == MODE_STATS) {
         // block-wide sums, one atomic per counter per block
@@ -514,11 +592,11 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     }
 }
 
-template <int IMG, int GEO, int MODE>
+template <int IMG, int GEO, int MODE, int DISK>
 __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderArgs a) {
     const int tile = blockIdx.x;
     const int e = find_eye(ch, tile);
-    render_tile<IMG, GEO, MODE>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a);
+    render_tile<IMG, GEO, MODE, DISK>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a);
 }
 
 // Next tile of a persistent workgroup. The launch's tiles are cut into kXcds
@@ -549,7 +627,7 @@ __device__ __forceinline__ int next_tile(const BatchArgs &b, int home, int &prob
 // wall-clock stamps of its tiles are kept (per-frame latency).
 // Seven waves per SIMD: the register budget that leaves room for a small
 // spill but hides more of the mesh walk's load latency than the default five.
-template <int IMG, int GEO>
+template <int IMG, int GEO, int DISK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void
 k_render_persistent(const BatchArgs b, const RenderArgs a) {
     __shared__ int s_tile;
@@ -579,7 +657,7 @@ k_render_persistent(const BatchArgs b, const RenderArgs a) {
             lo = E.tile_off;
             hi = lo + E.tiles_x * E.tiles_y;
         }
-        render_tile<IMG, GEO, MODE_RENDER>(E, cur_e, tile, b.tile_w, b.tile_h, a);
+        render_tile<IMG, GEO, MODE_RENDER, DISK>(E, cur_e, tile, b.tile_w, b.tile_h, a);
         if (threadIdx.x == 0) t1 = wall_clock64();
         __syncthreads();  // the prefetched index is visible
         tile = s_tile;
@@ -604,12 +682,23 @@ __global__ void k_batch_reset(unsigned int *queue, unsigned long long *frame_t, 
 // Per (eye, view) set-up for a batch whose eye table lives in device memory.
 __global__ __launch_bounds__(256) void k_prep_batch(const BatchArgs b, const double *__restrict__ vt,
                                                     const float2 *__restrict__ wr, int32_t n, const DiskBound db,
-                                                    EyeView *__restrict__ ev) {
+                                                    const ViewBases vb, EyeView *__restrict__ ev) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = blockIdx.y;
     if (v >= n || e >= b.n_eyes) return;
     const EyeParam E = b.eyes[e];
-    ev[(int64_t)e * n + v] = eye_view(E, vt, wr, v, db);
+    ev[(int64_t)e * n + v] = eye_view(E, vt, wr, v, db, vb);
+}
+
+// Prefilter finish (Eq. (5)): divide the weighted colour sums by the weight sums.
+__global__ void k_prefilter_finish(float *__restrict__ out, const float *__restrict__ wsum, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const float w = wsum[p];
+        const float k = w != 0.0f ? 1.0f / w : 0.0f;
+        out[3 * p] *= k;
+        out[3 * p + 1] *= k;
+        out[3 * p + 2] *= k;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -657,8 +746,8 @@ hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t 
 }
 
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
-                       EyeView *ev, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep, dim3((n + 255) / 256, ch.n_eyes), dim3(256), 0, s, ch, vt, wr, n, db, ev);
+                       const ViewBases &vb, EyeView *ev, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3((n + 255) / 256, ch.n_eyes), dim3(256), 0, s, ch, vt, wr, n, db, vb, ev);
     return hipGetLastError();
 }
 
@@ -668,10 +757,10 @@ hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, int DISK>
 static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, hipStream_t s) {
     const dim3 grid(ch.total_tiles), block(ch.tile_w * ch.tile_h);
-#define LF_R(I, G) hipLaunchKernelGGL((k_render<I, G, MODE>), grid, block, 0, s, ch, a)
+#define LF_R(I, G) hipLaunchKernelGGL((k_render<I, G, MODE, DISK>), grid, block, 0, s, ch, a)
     if (geo_fmt == 0) {
         if (img_fmt == 0) LF_R(0, 0);
         else if (img_fmt == 1) LF_R(1, 0);
@@ -684,20 +773,17 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
 #undef LF_R
 }
 
-hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a,
-                        hipEvent_t ev_b) {
-    hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
-    hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n, db,
-                       const_cast<EyeView *>(a.ev));
-    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n,
-                       const_cast<uint16_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
+template <int MODE>
+static void launch_render_disk(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, hipStream_t s) {
+    if (a.ext_inv) launch_render_mode<MODE, DISK_OVAL>(ch, a, img_fmt, geo_fmt, s);
+    else launch_render_mode<MODE, DISK_CIRCLE>(ch, a, img_fmt, geo_fmt, s);
+}
+
+template <int DISK>
+static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_fmt, int geo_fmt, int grid,
+                              hipStream_t s) {
     const dim3 block(b.tile_w * b.tile_h);
-    if (ev_a) {
-        hipError_t e = hipEventRecordWithFlags(ev_a, s, hipEventRecordExternal);
-        if (e != hipSuccess) return e;
-    }
-#define LF_P(I, G) hipLaunchKernelGGL((k_render_persistent<I, G>), dim3(grid), block, 0, s, b, a)
+#define LF_P(I, G) hipLaunchKernelGGL((k_render_persistent<I, G, DISK>), dim3(grid), block, 0, s, b, a)
     if (geo_fmt == 0) {
         if (img_fmt == 0) LF_P(0, 0);
         else if (img_fmt == 1) LF_P(1, 0);
@@ -708,28 +794,55 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
         else LF_P(2, 1);
     }
 #undef LF_P
+}
+
+hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
+                        const DiskBound &db, const ViewBases &vb, int img_fmt, int geo_fmt, int grid, hipStream_t s,
+                        hipEvent_t ev_a, hipEvent_t ev_b) {
+    hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
+    hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n, db, vb,
+                       const_cast<EyeView *>(a.ev));
+    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n,
+                       const_cast<uint16_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
+    if (ev_a) {
+        hipError_t e = hipEventRecordWithFlags(ev_a, s, hipEventRecordExternal);
+        if (e != hipSuccess) return e;
+    }
+    if (a.ext_inv) launch_persistent<DISK_OVAL>(b, a, img_fmt, geo_fmt, grid, s);
+    else launch_persistent<DISK_CIRCLE>(b, a, img_fmt, geo_fmt, grid, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && ev_b) e = hipEventRecordWithFlags(ev_b, s, hipEventRecordExternal);
     return e;
 }
 
-hipError_t persistent_occupancy(int img_fmt, int geo_fmt, int block, int *per_cu) {
-    const void *f;
+template <int DISK>
+static const void *persistent_fn(int img_fmt, int geo_fmt) {
     if (geo_fmt == 0)
-        f = img_fmt == 0 ? (const void *)k_render_persistent<0, 0>
-                         : (img_fmt == 1 ? (const void *)k_render_persistent<1, 0> : (const void *)k_render_persistent<2, 0>);
-    else
-        f = img_fmt == 0 ? (const void *)k_render_persistent<0, 1>
-                         : (img_fmt == 1 ? (const void *)k_render_persistent<1, 1> : (const void *)k_render_persistent<2, 1>);
+        return img_fmt == 0 ? (const void *)k_render_persistent<0, 0, DISK>
+                            : (img_fmt == 1 ? (const void *)k_render_persistent<1, 0, DISK>
+                                            : (const void *)k_render_persistent<2, 0, DISK>);
+    return img_fmt == 0 ? (const void *)k_render_persistent<0, 1, DISK>
+                        : (img_fmt == 1 ? (const void *)k_render_persistent<1, 1, DISK>
+                                        : (const void *)k_render_persistent<2, 1, DISK>);
+}
+
+hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu) {
+    const void *f = oval ? persistent_fn<DISK_OVAL>(img_fmt, geo_fmt) : persistent_fn<DISK_CIRCLE>(img_fmt, geo_fmt);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, block, 0);
+}
+
+hipError_t launch_prefilter_finish(float *out_rgb, const float *wsum, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prefilter_finish, dim3(grid_for(n, 256)), dim3(256), 0, s, out_rgb, wsum, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
                          hipStream_t s) {
-    if (mode == MODE_RENDER) launch_render_mode<MODE_RENDER>(ch, a, img_fmt, geo_fmt, s);
-    else if (mode == MODE_SUBPIXEL) launch_render_mode<MODE_SUBPIXEL>(ch, a, img_fmt, geo_fmt, s);
-    else if (mode == MODE_STATS) launch_render_mode<MODE_STATS>(ch, a, img_fmt, geo_fmt, s);
-    else launch_render_mode<MODE_DEBUG>(ch, a, img_fmt, geo_fmt, s);
+    if (mode == MODE_RENDER) launch_render_disk<MODE_RENDER>(ch, a, img_fmt, geo_fmt, s);
+    else if (mode == MODE_SUBPIXEL) launch_render_disk<MODE_SUBPIXEL>(ch, a, img_fmt, geo_fmt, s);
+    else if (mode == MODE_STATS) launch_render_disk<MODE_STATS>(ch, a, img_fmt, geo_fmt, s);
+    else if (mode == MODE_PREFILTER) launch_render_disk<MODE_PREFILTER>(ch, a, img_fmt, geo_fmt, s);
+    else launch_render_disk<MODE_DEBUG>(ch, a, img_fmt, geo_fmt, s);
     return hipGetLastError();
 }
 

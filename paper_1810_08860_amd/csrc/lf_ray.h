@@ -23,6 +23,14 @@ LF_HD float fast_rcp(float x) {
     return 1.0f / x;
 #endif
 }
+// Product of two operands below 2^24 (a full-rate multiply on the device).
+LF_HD uint32_t mul24(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return a * b;
+#endif
+}
 LF_HD float fast_sqrt(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __builtin_amdgcn_sqrtf(x);
@@ -41,9 +49,18 @@ struct Rgb {
 // Element idx of an array that starts at base, with the byte offset formed in
 // 32 bits: every array indexed this way is one view's share (well under
 // 4 GiB), so a wave-uniform base plus a 32-bit per-lane offset addresses it.
+// On the device the base is a global-memory pointer (address space 1): the
+// per-view bases come from the view records in memory, and a generic pointer
+// would make every access a flat load.
 template <typename T>
-LF_HD const T &at(const void *__restrict__ base, uint32_t idx) {
+LF_HD T at(const void *__restrict__ base, uint32_t idx) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) T gT;
+    return *(gT *)((gchar *)base + idx * (uint32_t)sizeof(T));
+#else
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (uint32_t)sizeof(T));
+#endif
 }
 
 // Texel idx (row-major) of one view's image.
@@ -190,7 +207,7 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
         const float wn = xs ? wxe : wye;
         const bool last = !(wn > we);
         const float w1 = last ? we : (wn < w0 ? wn : w0);
-        const float4 c = load_cell<GEO>(cells, (uint32_t)(k * Mc + j));
+        const float4 c = load_cell<GEO>(cells, mul24(k, Mc) + j);
         ++n_cells;
         float t;
         found = cell_root(c, fx0, fy0, w0, w1 - w0, bx, by, dbb, tol, t);
@@ -253,7 +270,7 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
         const float wn = fmaxf(wxe, wye);
         const bool last = !(wn > wlo);
         const float wb1 = last ? wlo : fminf(wn, w0);
-        const float2 bb = at<float2>(blk, (uint32_t)(bk * NB + bi));
+        const float2 bb = at<float2>(blk, mul24(bk, NB) + bi);
         const float ws = fminf(w0, bb.y), we = fmaxf(wb1, bb.x);
         if (ws >= we)
             found = walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, dwx, dwy, tol, j0, j1, k0, k1, ws, we, w_hit,
@@ -266,6 +283,23 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
     return found;
 }
 
+// Inverse depth w of a view's mesh at its image-plane point (X, Y): the
+// plane of the cell triangle holding the point (triangle A for fx >= fy,
+// B otherwise, as in cell_root). False outside the mesh domain (the square
+// spanned by the depth-pixel centres).
+template <int GEO>
+LF_HD bool mesh_point(const void *__restrict__ cells, int M, float sM, float cM, float X, float Y, float &w) {
+    const float gx = fmaf(X, sM, cM), gy = fmaf(-Y, sM, cM);
+    const float lim = (float)(M - 1);
+    if (!(gx >= 0.0f && gx <= lim && gy >= 0.0f && gy <= lim)) return false;
+    const int Mc = M - 1;
+    const int j = min((int)gx, Mc - 1), k = min((int)gy, Mc - 1);
+    const float fx = gx - (float)j, fy = gy - (float)k;
+    const float4 c = load_cell<GEO>(cells, mul24(k, Mc) + j);
+    w = fx >= fy ? fmaf(fy, c.w - c.y, fmaf(fx, c.y - c.x, c.x)) : fmaf(fy, c.z - c.x, fmaf(fx, c.w - c.z, c.x));
+    return true;
+}
+
 // Bilinear sample at normalised image-plane point (Xs, Ys): texel centres at
 // half-integers, clamp-to-edge (result in texel units; see texel_scale).
 template <int IMG>
@@ -276,7 +310,7 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float p
     int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
     x0 = min(max(x0, 0), W - 1);
     y0 = min(max(y0, 0), H - 1);
-    const uint32_t r0 = (uint32_t)(y0 * W), r1 = (uint32_t)(y1 * W);
+    const uint32_t r0 = mul24(y0, W), r1 = mul24(y1, W);
     const Rgb a = texel<IMG>(img, r0 + x0), b = texel<IMG>(img, r0 + x1);
     const Rgb c = texel<IMG>(img, r1 + x0), d = texel<IMG>(img, r1 + x1);
     // the four tap weights; FP16 taps then feed mixed-precision FMAs directly

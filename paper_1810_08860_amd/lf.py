@@ -65,6 +65,7 @@ def lib():
         L.lf_set_tune.argtypes = [vp, ctypes.POINTER(lf_tune)]
         L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
         L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
+        L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
         L.lf_debug_candidates.argtypes = [vp, ctypes.POINTER(lf_eye), f64, i32, i32, i32, vp, vp, vp, vp]
         L.lf_query.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
@@ -228,6 +229,22 @@ def lf_render_reference(ctx: Context, eyes, hfov_deg, res, ss, disk_scale, out_r
                                      float(disk_scale), _ptr(out_rgb), _stream(stream)))
 
 
+BASIS = {"box": 0, "lanczos2": 1}
+
+
+def lf_prefilter(ctx: Context, views, radius, disk_pts, pix_offs, basis, out_rgb, out_wsum, stream=None):
+    """Prefilter (Sec. 5, Eq. (5)) of the listed views; outputs are device
+    buffers of n_views x img_h x img_w RGB floats and weight sums."""
+    v = np.ascontiguousarray(views, np.int32).reshape(-1)
+    dp = np.ascontiguousarray(disk_pts, np.float64).reshape(-1, 2)
+    po = np.ascontiguousarray(pix_offs, np.float64).reshape(-1, 2)
+    if dp.shape != po.shape:
+        raise ValueError("disk_pts and pix_offs must both be (J, 2)")
+    _check(lib().lf_prefilter(ctx.handle, v.ctypes.data, len(v), float(radius), dp.ctypes.data, po.ctypes.data,
+                              dp.shape[0], BASIS[basis] if isinstance(basis, str) else int(basis), _ptr(out_rgb),
+                              _ptr(out_wsum), _stream(stream)))
+
+
 def lf_debug_candidates(ctx: Context, eye, hfov_deg, W, H, cap, out_cand, out_contrib, out_ncand=None,
                         stream=None):
     e = make_eyes([eye]) if not isinstance(eye, ctypes.Array) else eye
@@ -361,6 +378,7 @@ def lf_last_error() -> str:
 
 # names of every symbol include/lf.h declares (checked by the ABI test)
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_reference",
+           "lf_prefilter",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
            "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",
