@@ -632,6 +632,19 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
             supers += ch.total_supers;
         }
     }
+    // XCD queues: queue x holds band (x + k / 2) mod kXcds (a range of tile rows)
+    // of every eye k in turn
+    int32_t q_len[kXcds];
+    for (int x = 0; x < kXcds; ++x) {
+        int32_t off = 0;
+        for (int32_t k = 0; k < n_eyes; ++k) {
+            EyeParam &E = ep[k];
+            const int band = (x + k / 2) % kXcds;
+            E.band_off[x] = off;
+            off += ((band + 1) * E.tiles_y / kXcds - band * E.tiles_y / kXcds) * E.tiles_x;
+        }
+        q_len[x] = off;
+    }
     // device buffers: eye table, eye-view records, tile lists, counts, queue, stamps
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t ev_b = al(sizeof(EyeView) * (size_t)n_eyes * c->n);
@@ -678,6 +691,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     b.tile_w = t.tile_w;
     b.tile_h = t.tile_h;
     b.queue = (unsigned int *)(p + ev_b + tl_b + tc_b);
+    for (int x = 0; x < kXcds; ++x) b.q_len[x] = q_len[x];
     b.frame_t = (unsigned long long *)(p + ev_b + tl_b + tc_b + q_b);
     B.frame_t = b.frame_t;
     B.n_eyes = n_eyes;

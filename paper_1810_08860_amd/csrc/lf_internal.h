@@ -36,6 +36,10 @@ struct EyeParam {
     int32_t src_view;
     float off_x, off_y;
     float par_u, par_v;
+    // batches: first slot of this eye's band in each XCD's tile queue (band k
+    // = tile rows [k tiles_y / kXcds, (k + 1) tiles_y / kXcds); queue x holds
+    // band (x + e / 2) mod kXcds of eye e)
+    int32_t band_off[kXcds];
 };
 
 struct EyeChunk {
@@ -96,6 +100,7 @@ struct BatchArgs {
     int32_t tile_w, tile_h;
     unsigned int *queue;
     unsigned long long *frame_t;  // [n_eyes][2]: earliest tile start, latest tile end
+    int32_t q_len[kXcds];         // slots of each XCD's queue (one band of every eye)
 };
 
 enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3, MODE_PREFILTER = 4 };

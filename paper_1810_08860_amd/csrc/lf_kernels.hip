@@ -599,22 +599,34 @@ __global__ __launch_bounds__(256) void k_render(const EyeChunk ch, const RenderA
     render_tile<IMG, GEO, MODE, DISK>(ch.e[e], e, tile, ch.tile_w, ch.tile_h, a);
 }
 
-// Next tile of a persistent workgroup. The launch's tiles are cut into kXcds
-// contiguous ranges, each with its own queue counter (on its own 128-byte
-// line). Work-group ids are dispatched round-robin over the XCDs, so
-// workgroup b runs on XCD b % kXcds and drains that range first: the XCD's
-// CUs then work on neighbouring tiles of the same eyes, whose source texels
-// their shared L2 already holds, instead of every XCD fetching every eye's
-// texels from HBM into its own L2. A workgroup whose range is empty takes
-// tiles from the other ranges in turn (load balance). `probe` counts the
-// ranges found empty; once all are, the result is total_tiles (the exit).
+// Next tile of a persistent workgroup. Each eye's tile rows are cut into
+// kXcds bands; the queue of XCD x (its own counter, on its own 128-byte line)
+// holds one band of every eye in turn: band (x + e / 2) mod kXcds of eye e,
+// so both eyes of a stereo pair give XCD x the same band and over every
+// kXcds poses each XCD takes every band once (the queues cost the same and
+// move through the eyes together: short frame spans). Work-group ids are
+// dispatched round-robin over the XCDs, so workgroup b runs on XCD b % kXcds
+// and drains that queue: each XCD works on neighbouring tiles of its current
+// band, whose source texels its L2 then holds, instead of every XCD fetching
+// every part of every eye into its own L2. A workgroup whose queue is empty
+// takes slots from the other queues in turn (load balance). `probe` counts
+// the queues found empty; once all are, the result is total_tiles (the exit).
 __device__ __forceinline__ int next_tile(const BatchArgs &b, int home, int &probe) {
     while (probe < kXcds) {
         const int q = (home + probe) % kXcds;
-        const int lo = (int)((int64_t)b.total_tiles * q / kXcds);
-        const int hi = (int)((int64_t)b.total_tiles * (q + 1) / kXcds);
-        const int t = lo + (int)atomicAdd(b.queue + q * kQueueStride, 1u);
-        if (t < hi) return t;
+        const int t = (int)atomicAdd(b.queue + q * kQueueStride, 1u);
+        if (t < b.q_len[q]) {
+            // the last eye whose band in queue q starts at or before slot t
+            int lo = 0, hi = b.n_eyes - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (b.eyes[mid].band_off[q] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const EyeParam *E = b.eyes + lo;
+            const int band = (q + lo / 2) % kXcds;
+            return E->tile_off + (band * E->tiles_y) / kXcds * E->tiles_x + (t - E->band_off[q]);
+        }
         ++probe;
     }
     return b.total_tiles;
