@@ -39,6 +39,7 @@ class _Views(ctypes.Structure):
         ("zdepth", ctypes.c_void_p), ("zrange", ctypes.c_void_p),
         ("disk_radius", ctypes.c_double), ("disk_ext", ctypes.c_void_p),
         ("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
+        ("yuv_y", ctypes.c_void_p), ("yuv_uv", ctypes.c_void_p),
     ]
 
 
@@ -84,6 +85,7 @@ def lib():
         L.orc_prefilter.argtypes = [ctypes.POINTER(_Views), ctypes.POINTER(_Views), i32, f64, i32, vp, vp, i32,
                                     i64, vp, vp, vp]
         L.orc_basis.argtypes = [i32, f64]
+        L.orc_yuv420_encode.argtypes = [i32, i32, i32, vp, vp, vp]
         L.orc_basis.restype = f64
         L.orc_views_size.restype = i32
         L.orc_rec_size.restype = i32
@@ -131,7 +133,7 @@ class OracleViews:
         self.s = _Views(n, w, h, m, float(src_fov_deg), _p(self.centres), _p(self.rot), _p(self.rgba8),
                         _p(self.zdepth), _p(self.zrange), float(disk_radius),
                         None if self.disk_ext is None else _p(self.disk_ext),
-                        1 if mode == "brute" else 0, int(threads))
+                        1 if mode == "brute" else 0, int(threads), None, None)
 
     @classmethod
     def from_views(cls, v, mode="traversal", threads=0, disk_radius=None, disk_ext=None):
@@ -155,6 +157,16 @@ class OracleViews:
         o = self.with_disk_radius(self.s.disk_radius)
         o.disk_ext = None if ext is None else np.ascontiguousarray(ext, np.float64).reshape(self.n, 4)
         o.s.disk_ext = None if o.disk_ext is None else _p(o.disk_ext)
+        return o
+
+    def with_yuv420(self):
+        """The same light field with its images in the YUV420 form of the
+        paper's tile cache (Sec. 7.2), encoded by the oracle's own fixed-point
+        BT.601 (see yuv420_encode); sampling then recombines luma and
+        half-resolution chroma."""
+        o = self.with_disk_radius(self.s.disk_radius)
+        o.yuv_y, o.yuv_uv = yuv420_encode(self.rgba8)
+        o.s.yuv_y, o.s.yuv_uv = _p(o.yuv_y), _p(o.yuv_uv)
         return o
 
     def with_mode(self, mode):
@@ -261,6 +273,19 @@ def disk_extents(centres, rot):
     if not (ext > 0).all():
         raise ValueError("a disk has no 1-ring neighbour on one side of an axis")
     return ext, ring
+
+
+def yuv420_encode(rgba8):
+    """YUV420 planes (luma (n,H,W), chroma (n,H/2,W/2,2) = Cb, Cr) of RGBA8
+    images by the oracle's fixed-point full-range BT.601 (oracle.c)."""
+    rgba8 = np.ascontiguousarray(rgba8, np.uint8)
+    n, H, W, _ = rgba8.shape
+    if H % 2 or W % 2:
+        raise ValueError("YUV420 needs even image sizes")
+    y = np.zeros((n, H, W), np.uint8)
+    uv = np.zeros((n, H // 2, W // 2, 2), np.uint8)
+    lib().orc_yuv420_encode(n, W, H, _p(rgba8), _p(y), _p(uv))
+    return y, uv
 
 
 BASIS = {"box": 0, "lanczos2": 1}

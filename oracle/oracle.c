@@ -69,6 +69,8 @@ typedef struct {
     const double *disk_ext;  /* [n][4] oval extents e+u, e-u, e+v, e-v (metres), or NULL: circles of disk_radius */
     int32_t mode;            /* 0 = traversal, 1 = brute force over all triangles */
     int32_t threads;
+    const uint8_t *yuv_y;    /* [n][img_h][img_w] luma, or NULL: sample rgba8 */
+    const uint8_t *yuv_uv;   /* [n][img_h/2][img_w/2][2] chroma (Cb, Cr) at half resolution */
 } orc_views;
 
 /* Per-ray outputs. Lists are ascending view ids padded with -1. */
@@ -294,13 +296,80 @@ double orc_mesh_hit(const orc_views *V, int32_t i, const double o[3], const doub
     return best;
 }
 
+/*
+ * YUV420 form of the images (the paper's tile cache stores its tiles as
+ * YUV420: a full-resolution luma plane and a half-resolution two-channel
+ * chroma plane, sampled separately and recombined to RGB; Sec. 7.2). Full
+ * range BT.601 in 8-bit fixed point: Y = (77 R + 150 G + 29 B + 128) >> 8,
+ * Cb = ((-43 R - 85 G + 128 B + 128) >> 8) + 128,
+ * Cr = ((128 R - 107 G - 21 B + 128) >> 8) + 128 (clamped to 255; the shifts
+ * floor), each chroma sample the rounded mean (sum + 2) >> 2 of the 2x2
+ * block it covers. Integer arithmetic only, so any exact implementation gives
+ * the same bytes. Image sizes must be even.
+ */
+static inline int32_t yuv_floor_div256(int32_t v) { return (v + 256 * 256) / 256 - 256; }
+
+void orc_yuv420_encode(int32_t n, int32_t W, int32_t H, const uint8_t *rgba8, uint8_t *y, uint8_t *uv) {
+    for (int32_t i = 0; i < n; ++i) {
+        const uint8_t *img = rgba8 + (int64_t)i * W * H * 4;
+        uint8_t *yi = y + (int64_t)i * W * H;
+        uint8_t *ci = uv + (int64_t)i * (W / 2) * (H / 2) * 2;
+        for (int32_t by = 0; by < H / 2; ++by)
+            for (int32_t bx = 0; bx < W / 2; ++bx) {
+                int32_t sb = 0, sr = 0;
+                for (int32_t dy = 0; dy < 2; ++dy)
+                    for (int32_t dx = 0; dx < 2; ++dx) {
+                        const int64_t p = (int64_t)(2 * by + dy) * W + 2 * bx + dx;
+                        const int32_t R = img[4 * p], G = img[4 * p + 1], B = img[4 * p + 2];
+                        yi[p] = (uint8_t)((77 * R + 150 * G + 29 * B + 128) >> 8);
+                        int32_t cb = yuv_floor_div256(-43 * R - 85 * G + 128 * B + 128) + 128;
+                        int32_t cr = yuv_floor_div256(128 * R - 107 * G - 21 * B + 128) + 128;
+                        sb += cb > 255 ? 255 : cb;
+                        sr += cr > 255 ? 255 : cr;
+                    }
+                ci[2 * ((int64_t)by * (W / 2) + bx)] = (uint8_t)((sb + 2) >> 2);
+                ci[2 * ((int64_t)by * (W / 2) + bx) + 1] = (uint8_t)((sr + 2) >> 2);
+            }
+    }
+}
+
+/* Bilinear sample of a one- or two-channel 8-bit plane at texel-centre
+ * coordinate (px, py), clamp-to-edge; channel c of nc. */
+static double plane_bilinear(const uint8_t *pl, int32_t W, int32_t H, int32_t nc, int32_t c, double px, double py) {
+    double fx0 = floor(px), fy0 = floor(py);
+    double fx = px - fx0, fy = py - fy0;
+    int64_t x0 = (int64_t)fx0, y0 = (int64_t)fy0, x1 = x0 + 1, y1 = y0 + 1;
+    if (x0 < 0) x0 = 0; if (x0 > W - 1) x0 = W - 1;
+    if (x1 < 0) x1 = 0; if (x1 > W - 1) x1 = W - 1;
+    if (y0 < 0) y0 = 0; if (y0 > H - 1) y0 = H - 1;
+    if (y1 < 0) y1 = 0; if (y1 > H - 1) y1 = H - 1;
+    const double a = pl[(y0 * W + x0) * nc + c], b = pl[(y0 * W + x1) * nc + c];
+    const double d = pl[(y1 * W + x0) * nc + c], e = pl[(y1 * W + x1) * nc + c];
+    const double top = a + fx * (b - a), bot = d + fx * (e - d);
+    return top + fy * (bot - top);
+}
+
 /* Continuous sample of view i's image at normalised image-plane point (Xs, Ys):
- * bilinear over texel centres, clamp-to-edge, RGB/255. */
+ * bilinear over texel centres, clamp-to-edge, RGB/255. With YUV420 planes the
+ * luma is sampled at full resolution and the chroma at half resolution (a
+ * chroma sample sits at the centre of its 2x2 luma block), then recombined
+ * with the full-range BT.601 inverse; no clamping of the result. */
 void orc_sample(const orc_views *V, int32_t i, double Xs, double Ys, double rgb[3]) {
     const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
     const int32_t W = V->img_w, H = V->img_h;
     double px = (Xs / ts + 1.0) * 0.5 * W - 0.5;
     double py = (1.0 - Ys / ts) * 0.5 * H - 0.5;
+    if (V->yuv_y) {
+        const double Y = plane_bilinear(V->yuv_y + (int64_t)i * W * H, W, H, 1, 0, px, py);
+        const uint8_t *uv = V->yuv_uv + (int64_t)i * (W / 2) * (H / 2) * 2;
+        const double cx = 0.5 * (px - 0.5), cy = 0.5 * (py - 0.5);
+        const double cb = plane_bilinear(uv, W / 2, H / 2, 2, 0, cx, cy) - 128.0;
+        const double cr = plane_bilinear(uv, W / 2, H / 2, 2, 1, cx, cy) - 128.0;
+        rgb[0] = (Y + 1.402 * cr) / 255.0;
+        rgb[1] = (Y - 0.344136 * cb - 0.714136 * cr) / 255.0;
+        rgb[2] = (Y + 1.772 * cb) / 255.0;
+        return;
+    }
     double fx0 = floor(px), fy0 = floor(py);
     double fx = px - fx0, fy = py - fy0;
     int64_t x0 = (int64_t)fx0, y0 = (int64_t)fy0, x1 = x0 + 1, y1 = y0 + 1;
