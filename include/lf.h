@@ -57,9 +57,17 @@ enum {
 };
 
 /* Storage format of the source images on the device. RGBA32F is the plain
- * FP32 form; RGBA16F and RGBA8 (UNORM) are the compact forms. All sampling
- * and blending arithmetic is FP32 in every format. */
-enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2 };
+ * FP32 form; RGBA16F and RGBA8 (UNORM) are the compact forms. YUV420 is the
+ * form of the paper's tile cache (Sec. 7.2): a full-resolution 8-bit luma
+ * plane and a half-resolution two-channel 8-bit chroma plane (1.5 bytes per
+ * texel), converted on load with full-range BT.601 in 8-bit fixed point
+ * (Y = (77 R + 150 G + 29 B + 128) >> 8, Cb = ((-43 R - 85 G + 128 B + 128)
+ * >> 8) + 128, Cr = ((128 R - 107 G - 21 B + 128) >> 8) + 128, clamped to 255,
+ * each chroma sample the rounded mean of its 2x2 block), sampled bilinearly
+ * per plane (a chroma sample sits at the centre of its block) and recombined
+ * with the BT.601 inverse; it needs even image sizes. All sampling and
+ * blending arithmetic is FP32 in every format. */
+enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2, LF_IMG_YUV420 = 3 };
 
 /* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex, in
  * FP32 or FP16, packed per mesh cell. Intersection arithmetic is FP32. */

@@ -56,7 +56,10 @@ bool frame_ok(const double *R) {
     return true;
 }
 
-size_t img_bytes_per_texel(int fmt) { return fmt == LF_IMG_RGBA8 ? 4 : (fmt == LF_IMG_RGBA16F ? 8 : 16); }
+// bytes per texel of the (first) image plane
+size_t img_bytes_per_texel(int fmt) {
+    return fmt == LF_IMG_RGBA8 ? 4 : (fmt == LF_IMG_RGBA16F ? 8 : (fmt == LF_IMG_RGBA32F ? 16 : 1));
+}
 size_t geo_bytes_per_cell(int fmt) { return fmt == LF_GEO_F32 ? 16 : 8; }
 
 }  // namespace
@@ -66,7 +69,8 @@ struct lf_ctx {
     int32_t n = 0, img_w = 0, img_h = 0, M = 0;
     double src_fov_deg = 0.0, tan_s = 0.0, R = 0.0;
     int32_t img_fmt = 0, geo_fmt = 0;
-    void *img = nullptr;     // device images in img_fmt
+    void *img = nullptr;     // device images in img_fmt (YUV420: the luma planes)
+    void *img2 = nullptr;    // YUV420: the chroma planes
     void *geo = nullptr;     // device mesh cells in geo_fmt
     double *vt = nullptr;    // device [n][12]: centre, frame
     float2 *wr = nullptr;    // device [n]: inverse-depth range
@@ -233,9 +237,11 @@ ViewBases view_bases(const lf_ctx *c) {
     ViewBases vb;
     vb.geo = static_cast<const char *>(c->geo);
     vb.img = static_cast<const char *>(c->img);
+    vb.img2 = static_cast<const char *>(c->img2);
     vb.blk = c->blk;
     vb.geo_bytes = (int64_t)(c->M - 1) * (c->M - 1) * (c->geo_fmt == LF_GEO_F32 ? 16 : 8);
-    vb.img_bytes = (int64_t)c->img_w * c->img_h * (c->img_fmt == LF_IMG_RGBA8 ? 4 : (c->img_fmt == LF_IMG_RGBA16F ? 8 : 16));
+    vb.img_bytes = (int64_t)c->img_w * c->img_h * (int64_t)img_bytes_per_texel(c->img_fmt);
+    vb.img2_bytes = (int64_t)(c->img_w / 2) * (c->img_h / 2) * 2;
     vb.blk_per_view = (int64_t)num_blocks(c->M) * num_blocks(c->M);
     return vb;
 }
@@ -290,7 +296,9 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (!(d->src_fov_deg > 0.0 && d->src_fov_deg < 180.0)) return fail(LF_EINVAL, "src_fov_deg must be in (0,180)");
     if (!(d->disk_radius > 0.0) || !std::isfinite(d->disk_radius)) return fail(LF_EINVAL, "disk_radius must be > 0");
     if (!d->centres || !d->rot || !d->rgba8 || !d->zdepth) return fail(LF_EINVAL, "NULL data pointer");
-    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_RGBA32F) return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
+    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_YUV420) return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
+    if (d->img_fmt == LF_IMG_YUV420 && (d->img_w % 2 || d->img_h % 2))
+        return fail(LF_EINVAL, "YUV420 needs even image sizes (got %dx%d)", d->img_w, d->img_h);
     if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
     if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
     const int32_t n = d->n_views, M = d->mesh_m;
@@ -374,6 +382,16 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
             if ((e = hipMemcpy(c->img, rgba_dev, n_tex * 4, hipMemcpyDeviceToDevice)) != hipSuccess)
                 return bail(hip_fail(e, "copy images"));
         }
+    } else if (d->img_fmt == LF_IMG_YUV420) {
+        if ((e = hipMalloc(&c->img, n_tex)) != hipSuccess || (e = hipMalloc(&c->img2, n_tex / 2)) != hipSuccess) {
+            if (rgba_owned) (void)hipFree(rgba_dev);
+            return bail(hip_fail(e, "hipMalloc(YUV420 planes)"));
+        }
+        e = launch_convert_yuv420((const uint8_t *)rgba_dev, (uint8_t *)c->img, (uint8_t *)c->img2, n, d->img_w,
+                                  d->img_h, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (rgba_owned) (void)hipFree(rgba_dev);
+        if (e != hipSuccess) return bail(hip_fail(e, "YUV420 conversion"));
     } else {
         if ((e = hipMalloc(&c->img, n_tex * img_bytes_per_texel(d->img_fmt))) != hipSuccess) {
             if (rgba_owned) (void)hipFree(rgba_dev);
@@ -915,6 +933,7 @@ void lf_free(lf_ctx *c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
     if (c->img) (void)hipFree(c->img);
+    if (c->img2) (void)hipFree(c->img2);
     if (c->geo) (void)hipFree(c->geo);
     if (c->vt) (void)hipFree(c->vt);
     if (c->wr) (void)hipFree(c->wr);

@@ -65,16 +65,16 @@ struct alignas(16) EyeView {
     int32_t view;
     float rk;          // radius bounding the view's disk, padded for the conservative tile test
     const void *cells;  // this view's mesh cells
-    const void *img;    // this view's image
+    const void *img;    // this view's image (YUV420: its luma plane)
     const float2 *blk;  // this view's inverse-depth blocks
-    int64_t pad;
+    const void *img2;   // YUV420: this view's chroma plane (else unused)
 };
 
 // Where each view's data starts: base + view * stride (bytes; blocks in elements).
 struct ViewBases {
-    const char *geo, *img;
+    const char *geo, *img, *img2;
     const float2 *blk;
-    int64_t geo_bytes, img_bytes, blk_per_view;
+    int64_t geo_bytes, img_bytes, img2_bytes, blk_per_view;
 };
 
 // Mesh grid of the light field as the culling of prefilter eyes needs it.
@@ -138,6 +138,9 @@ int fail_msg(int code, const char *msg);
 // Launchers (lf_kernels.hip). All are asynchronous on `s` and return the
 // launch status.
 hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int64_t n_texels, hipStream_t s);
+// RGBA8 [n][H][W] -> luma [n][H][W] and chroma [n][H/2][W/2][2] (H, W even)
+hipError_t launch_convert_yuv420(const uint8_t *src, uint8_t *y, uint8_t *uv, int32_t n, int32_t W, int32_t H,
+                                 hipStream_t s);
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);

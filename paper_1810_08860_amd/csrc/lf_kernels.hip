@@ -68,6 +68,33 @@ __global__ void k_convert_images(const uint32_t *__restrict__ src, void *__restr
     }
 }
 
+// YUV420 planes of RGBA8 images (full-range BT.601 in 8-bit fixed point,
+// integer arithmetic; arithmetic right shifts floor), one thread per 2x2
+// luma block and its chroma sample, the rounded mean of the block's four.
+__global__ void k_convert_yuv420(const uint32_t *__restrict__ src, uint8_t *__restrict__ y,
+                                 uint8_t *__restrict__ uv, int32_t n, int32_t W, int32_t H) {
+    const int Wc = W / 2, Hc = H / 2;
+    const int64_t total = (int64_t)n * Wc * Hc;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = q / ((int64_t)Wc * Hc);
+        const int r = (int)(q % ((int64_t)Wc * Hc));
+        const int by = r / Wc, bx = r % Wc;
+        int sb = 0, sr = 0;
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int64_t p = v * W * H + (int64_t)(2 * by + dy) * W + 2 * bx + dx;
+                const uint32_t t = src[p];
+                const int R = (int)(t & 255u), G = (int)((t >> 8) & 255u), B = (int)((t >> 16) & 255u);
+                y[p] = (uint8_t)((77 * R + 150 * G + 29 * B + 128) >> 8);
+                sb += min(((-43 * R - 85 * G + 128 * B + 128) >> 8) + 128, 255);
+                sr += min(((128 * R - 107 * G - 21 * B + 128) >> 8) + 128, 255);
+            }
+        uint8_t *c = uv + 2 * (v * Wc * Hc + (int64_t)by * Wc + bx);
+        c[0] = (uint8_t)((sb + 2) >> 2);
+        c[1] = (uint8_t)((sr + 2) >> 2);
+    }
+}
+
 // Mesh cells of every view: corner inverse depths (w00, w10, w01, w11).
 template <int GEO>
 __global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cells, int32_t n, int32_t M) {
@@ -175,7 +202,7 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     out.cells = vb.geo + v * vb.geo_bytes;
     out.img = vb.img + v * vb.img_bytes;
     out.blk = vb.blk + v * vb.blk_per_view;
-    out.pad = 0;
+    out.img2 = vb.img2 ? vb.img2 + v * vb.img2_bytes : nullptr;
     return out;
 }
 
@@ -525,7 +552,9 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             }
             const float Xs = fmaf(wh, rv.Dx, rv.Vx), Ys = fmaf(wh, rv.Dy, rv.Vy);
             const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
-            const Rgb col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
+            Rgb col;
+            if constexpr (IMG == 3) col = bilinear_yuv(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
+            else col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
             accr = fmaf(rv.rho, col.r, accr);
             accg = fmaf(rv.rho, col.g, accg);
             accb = fmaf(rv.rho, col.b, accb);
@@ -730,6 +759,13 @@ hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int
     return hipGetLastError();
 }
 
+hipError_t launch_convert_yuv420(const uint8_t *src, uint8_t *y, uint8_t *uv, int32_t n, int32_t W, int32_t H,
+                                 hipStream_t s) {
+    const int g = grid_for((int64_t)n * (W / 2) * (H / 2), 256);
+    hipLaunchKernelGGL(k_convert_yuv420, dim3(g), dim3(256), 0, s, (const uint32_t *)src, y, uv, n, W, H);
+    return hipGetLastError();
+}
+
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s) {
     const int g = grid_for((int64_t)(M - 1) * (M - 1) * n, 256);
     if (geo_fmt == 0)
@@ -776,11 +812,13 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
     if (geo_fmt == 0) {
         if (img_fmt == 0) LF_R(0, 0);
         else if (img_fmt == 1) LF_R(1, 0);
-        else LF_R(2, 0);
+        else if (img_fmt == 2) LF_R(2, 0);
+        else LF_R(3, 0);
     } else {
         if (img_fmt == 0) LF_R(0, 1);
         else if (img_fmt == 1) LF_R(1, 1);
-        else LF_R(2, 1);
+        else if (img_fmt == 2) LF_R(2, 1);
+        else LF_R(3, 1);
     }
 #undef LF_R
 }
@@ -799,11 +837,13 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
     if (geo_fmt == 0) {
         if (img_fmt == 0) LF_P(0, 0);
         else if (img_fmt == 1) LF_P(1, 0);
-        else LF_P(2, 0);
+        else if (img_fmt == 2) LF_P(2, 0);
+        else LF_P(3, 0);
     } else {
         if (img_fmt == 0) LF_P(0, 1);
         else if (img_fmt == 1) LF_P(1, 1);
-        else LF_P(2, 1);
+        else if (img_fmt == 2) LF_P(2, 1);
+        else LF_P(3, 1);
     }
 #undef LF_P
 }
@@ -829,13 +869,11 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
 
 template <int DISK>
 static const void *persistent_fn(int img_fmt, int geo_fmt) {
-    if (geo_fmt == 0)
-        return img_fmt == 0 ? (const void *)k_render_persistent<0, 0, DISK>
-                            : (img_fmt == 1 ? (const void *)k_render_persistent<1, 0, DISK>
-                                            : (const void *)k_render_persistent<2, 0, DISK>);
-    return img_fmt == 0 ? (const void *)k_render_persistent<0, 1, DISK>
-                        : (img_fmt == 1 ? (const void *)k_render_persistent<1, 1, DISK>
-                                        : (const void *)k_render_persistent<2, 1, DISK>);
+    const void *f0[4] = {(const void *)k_render_persistent<0, 0, DISK>, (const void *)k_render_persistent<1, 0, DISK>,
+                         (const void *)k_render_persistent<2, 0, DISK>, (const void *)k_render_persistent<3, 0, DISK>};
+    const void *f1[4] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
+                         (const void *)k_render_persistent<2, 1, DISK>, (const void *)k_render_persistent<3, 1, DISK>};
+    return geo_fmt == 0 ? f0[img_fmt] : f1[img_fmt];
 }
 
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu) {

@@ -87,7 +87,7 @@ LF_HD Rgb texel<2>(const void *__restrict__ img, uint32_t idx) {  // RGBA32F
 
 // scale from stored texel units to [0,1]
 template <int IMG>
-LF_HD float texel_scale() { return IMG == 0 ? (1.0f / 255.0f) : 1.0f; }
+LF_HD float texel_scale() { return (IMG == 0 || IMG == 3) ? (1.0f / 255.0f) : 1.0f; }
 
 // Corner inverse depths of one mesh cell: (w00, w10, w01, w11) with j to the
 // right and k downwards.
@@ -318,6 +318,46 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float p
     return {fmaf(w11, d.r, fmaf(w01, c.r, fmaf(w10, b.r, fmaf(w00, a.r, 0.0f)))),
             fmaf(w11, d.g, fmaf(w01, c.g, fmaf(w10, b.g, fmaf(w00, a.g, 0.0f)))),
             fmaf(w11, d.b, fmaf(w01, c.b, fmaf(w10, b.b, fmaf(w00, a.b, 0.0f))))};
+}
+
+// YUV420 sample (result in 0..255 units): luma bilinear at full resolution,
+// chroma bilinear at half resolution with chroma sample (i, j) at the centre
+// of luma block (2i..2i+1, 2j..2j+1), i.e. at chroma coordinate
+// ((px - 1/2) / 2, (py - 1/2) / 2); clamp-to-edge on both planes; recombined
+// with the full-range BT.601 inverse.
+LF_HD Rgb bilinear_yuv(const void *__restrict__ yp, const void *__restrict__ uvp, int W, int H, float px, float py) {
+    float lum;
+    {
+        const float x0f = floorf(px), y0f = floorf(py);
+        const float fx = px - x0f, fy = py - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
+        x0 = min(max(x0, 0), W - 1);
+        y0 = min(max(y0, 0), H - 1);
+        const uint32_t r0 = mul24(y0, W), r1 = mul24(y1, W);
+        const float a = at<uint8_t>(yp, r0 + x0), b = at<uint8_t>(yp, r0 + x1);
+        const float c = at<uint8_t>(yp, r1 + x0), d = at<uint8_t>(yp, r1 + x1);
+        const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+        lum = fmaf(w11, d, fmaf(w01, c, fmaf(w10, b, w00 * a)));
+    }
+    float cb, cr;
+    {
+        const int Wc = W >> 1, Hc = H >> 1;
+        const float cx = 0.5f * (px - 0.5f), cy = 0.5f * (py - 0.5f);
+        const float x0f = floorf(cx), y0f = floorf(cy);
+        const float fx = cx - x0f, fy = cy - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        const int x1 = min(max(x0 + 1, 0), Wc - 1), y1 = min(max(y0 + 1, 0), Hc - 1);
+        x0 = min(max(x0, 0), Wc - 1);
+        y0 = min(max(y0, 0), Hc - 1);
+        const uint32_t r0 = mul24(y0, Wc), r1 = mul24(y1, Wc);
+        const uint32_t a = at<uint16_t>(uvp, r0 + x0), b = at<uint16_t>(uvp, r0 + x1);
+        const uint32_t c = at<uint16_t>(uvp, r1 + x0), d = at<uint16_t>(uvp, r1 + x1);
+        const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+        cb = fmaf(w11, (float)(d & 255u), fmaf(w01, (float)(c & 255u), fmaf(w10, (float)(b & 255u), w00 * (float)(a & 255u)))) - 128.0f;
+        cr = fmaf(w11, (float)(d >> 8), fmaf(w01, (float)(c >> 8), fmaf(w10, (float)(b >> 8), w00 * (float)(a >> 8)))) - 128.0f;
+    }
+    return {fmaf(1.402f, cr, lum), fmaf(-0.714136f, cr, fmaf(-0.344136f, cb, lum)), fmaf(1.772f, cb, lum)};
 }
 
 }  // namespace lf
