@@ -155,6 +155,29 @@ int lf_set_tune(lf_ctx *c, const lf_tune *t);
 int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
               float *out_rgb, float *out_wsum, uint8_t *out_count, void *hip_stream);
 
+/*
+ * Views taking part in renders. enabled: host uint8 [n_views], non-zero =
+ * enabled, or NULL to enable every view (the state after lf_load_views). A
+ * disabled view is left out of every later query (render, batch, reference,
+ * prefilter, candidate lists): Eq. (2) sums over the enabled views only.
+ * Synchronous: waits for the device to be idle, then applies to later calls.
+ */
+int lf_set_view_mask(lf_ctx *c, const uint8_t *enabled);
+
+/*
+ * Two-level progressive rendering (Sec. 7.2): the context holds a fine level
+ * (views [0, n_fine)) and a coarse level (views [n_fine, n_views), typically
+ * a subset of the same captures with larger disks given through per-view
+ * extents); each level alone is a complete light field. Given which fine
+ * views are available this frame (fine_available, host uint8 [n_fine], e.g.
+ * the ones a decode budget allowed), writes the view mask for
+ * lf_set_view_mask: every available fine view, plus every coarse view whose
+ * disk reaches the centre of an unavailable fine view (the coarse disk is
+ * drawn in the region the missing fine disks leave); both levels then blend
+ * in Eq. (2). mask_out: host uint8 [n_views].
+ */
+int lf_two_level_mask(const lf_ctx *c, int32_t n_fine, const uint8_t *fine_available, uint8_t *mask_out);
+
 /* Pixel reconstruction basis of the prefilter (one axis; the 2-D basis is the
  * product of two): box, 1 on |d| <= 1/2; Lanczos-2, sinc(d) sinc(d/2) on
  * |d| < 2 with sinc(x) = sin(pi x) / (pi x). */

@@ -77,6 +77,8 @@ struct lf_ctx {
     float2 *blk = nullptr;   // device [n][NB][NB]: inverse-depth range per block of cells
     float4 *ext_inv = nullptr;  // device [n]: oval disks' inverse extents (null: circles of radius R)
     float *vrad = nullptr;      // device [n]: oval disks' largest extent (culling bound)
+    uint8_t *vmask = nullptr;   // device [n]: views taking part in renders (lf_set_view_mask)
+    std::vector<double> h_rad;  // host [n]: each disk's largest extent (R for circles)
     std::vector<double> h_vt;  // host copy of the view table (eye validation)
     // per-render scratch: eye-view table and tile lists, grown on demand
     void *scratch = nullptr;
@@ -259,7 +261,7 @@ int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t 
     uint16_t *tl = (uint16_t *)(p + al(ev_bytes));
     int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
     // conservative disk bounds for the tile test; the exact per-ray test decides in k_render
-    const DiskBound db{c->vrad, R, R / c->R};
+    const DiskBound db{c->vrad, R, R / c->R, c->vmask};
     LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, view_bases(c), ev, s); }), "k_prep launch");
     LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, tl, tc, s); }), "k_cull launch");
     a.ev = ev;
@@ -346,6 +348,9 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if ((e = hipMalloc(&c->wr, sizeof(float2) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(w range)"));
     if ((e = hipMemcpy(c->vt, c->h_vt.data(), c->h_vt.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(hip_fail(e, "copy view table"));
+    c->h_rad.assign(n, d->disk_radius);
+    if ((e = hipMalloc(&c->vmask, n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(view mask)"));
+    if ((e = hipMemset(c->vmask, 1, n)) != hipSuccess) return bail(hip_fail(e, "hipMemset(view mask)"));
     if (d->disk_ext) {
         std::vector<float4> inv(n);
         std::vector<float> big(n);
@@ -353,6 +358,7 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
             const double *x = d->disk_ext + 4 * (size_t)v;
             inv[v] = make_float4((float)(1.0 / x[0]), (float)(1.0 / x[1]), (float)(1.0 / x[2]), (float)(1.0 / x[3]));
             big[v] = (float)std::max(std::max(x[0], x[1]), std::max(x[2], x[3]));
+            c->h_rad[v] = std::max(std::max(x[0], x[1]), std::max(x[2], x[3]));
         }
         if ((e = hipMalloc(&c->ext_inv, sizeof(float4) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(disks)"));
         if ((e = hipMalloc(&c->vrad, sizeof(float) * n)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(disks)"));
@@ -523,6 +529,36 @@ static double basis_weight(int32_t basis, double x) {
     if (x == 0.0) return 1.0;
     const double px = M_PI * x;
     return std::sin(px) / px * (std::sin(0.5 * px) / (0.5 * px));
+}
+
+int lf_set_view_mask(lf_ctx *c, const uint8_t *enabled) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    std::vector<uint8_t> m(c->n, 1);
+    if (enabled)
+        for (int32_t v = 0; v < c->n; ++v) m[v] = enabled[v] ? 1 : 0;
+    // renders already queued on other streams may still read the mask
+    LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    LF_HIP(hipMemcpy(c->vmask, m.data(), c->n, hipMemcpyHostToDevice), "copy view mask");
+    return LF_OK;
+}
+
+int lf_two_level_mask(const lf_ctx *c, int32_t n_fine, const uint8_t *fine_available, uint8_t *mask_out) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!fine_available || !mask_out) return fail(LF_EINVAL, "fine_available and mask_out must not be NULL");
+    if (n_fine <= 0 || n_fine > c->n) return fail(LF_EINVAL, "n_fine must be in [1, n_views] (got %d)", n_fine);
+    for (int32_t v = 0; v < n_fine; ++v) mask_out[v] = fine_available[v] ? 1 : 0;
+    for (int32_t j = n_fine; j < c->n; ++j) {
+        const double *cj = &c->h_vt[12 * (size_t)j];
+        uint8_t need = 0;
+        for (int32_t i = 0; i < n_fine && !need; ++i) {
+            if (fine_available[i]) continue;
+            const double *ci = &c->h_vt[12 * (size_t)i];
+            const double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
+            need = dx * dx + dy * dy + dz * dz < c->h_rad[j] * c->h_rad[j];
+        }
+        mask_out[j] = need;
+    }
+    return LF_OK;
 }
 
 int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *disk_pts,
@@ -731,7 +767,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
                "occupancy");
         LF_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
         const int grid = std::max(1, std::min(per_cu * n_cu, tiles));
-        const DiskBound db{c->vrad, c->R, 1.0};
+        const DiskBound db{c->vrad, c->R, 1.0, c->vmask};
         if (c->profiling && !B.ph_a) {
             LF_HIP(hipEventCreate(&B.ph_a), "hipEventCreate");
             LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
@@ -940,6 +976,7 @@ void lf_free(lf_ctx *c) {
     if (c->blk) (void)hipFree(c->blk);
     if (c->ext_inv) (void)hipFree(c->ext_inv);
     if (c->vrad) (void)hipFree(c->vrad);
+    if (c->vmask) (void)hipFree(c->vmask);
     if (c->scratch) (void)hipFree(c->scratch);
     for (auto &t : c->timed) {
         (void)hipEventDestroy(t.a);

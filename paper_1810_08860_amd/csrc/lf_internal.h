@@ -63,7 +63,7 @@ struct alignas(16) EyeView {
     float o[3];
     float wmin, wmax;  // inverse-depth range of the view's mesh
     int32_t view;
-    float rk;          // radius bounding the view's disk, padded for the conservative tile test
+    float rk;          // radius bounding the view's disk, padded for the conservative tile test; < 0: view disabled
     const void *cells;  // this view's mesh cells
     const void *img;    // this view's image (YUV420: its luma plane)
     const float2 *blk;  // this view's inverse-depth blocks
@@ -89,6 +89,7 @@ struct CullGeo {
 struct DiskBound {
     const float *vrad;  // [n] or null
     double R, vscale;
+    const uint8_t *vmask;  // [n]: 0 = the view takes no part in renders (its record gets rk = -1); or null
 };
 
 // A batch: eye table in device memory (sorted by tile_off / super_off), the

@@ -199,6 +199,7 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     // padded by 1e-4 relative and 1e-7 m: the FP32 tile test may not drop a
     // disk that the exact per-ray test keeps
     out.rk = (float)((db.vrad ? (double)db.vrad[v] * db.vscale : db.R) * (1.0 + 1e-4) + 1e-7);
+    if (db.vmask && !db.vmask[v]) out.rk = -1.0f;  // disabled: culled everywhere
     out.cells = vb.geo + v * vb.geo_bytes;
     out.img = vb.img + v * vb.img_bytes;
     out.blk = vb.blk + v * vb.blk_per_view;
@@ -225,6 +226,7 @@ __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *_
 // that straddles the plane's horizon is kept.
 __device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, float X1, float Y0, float Y1) {
     const float R = v.rk;
+    if (!(R > 0.0f)) return false;  // a disabled view
     const float cx[4] = {X0, X1, X1, X0}, cy[4] = {Y0, Y0, Y1, Y1};
     float dx[4], dy[4];
     int npos = 0;
@@ -530,6 +532,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
                 vid = (c & 1) ? (int)(pair >> 16) : (int)(pair & 0xffffu);
             }
             const EyeView v = uniform_load(eve + vid);
+            if (overflow && !(v.rk > 0.0f)) continue;  // a disabled view (listed tiles never hold one)
             RayView rv;
             ++n_tests;
             const bool cand = DISK == DISK_OVAL

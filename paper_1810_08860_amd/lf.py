@@ -66,6 +66,8 @@ def lib():
         L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
         L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
         L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
+        L.lf_set_view_mask.argtypes = [vp, vp]
+        L.lf_two_level_mask.argtypes = [vp, i32, vp, vp]
         L.lf_debug_candidates.argtypes = [vp, ctypes.POINTER(lf_eye), f64, i32, i32, i32, vp, vp, vp, vp]
         L.lf_query.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
@@ -229,6 +231,24 @@ def lf_render_reference(ctx: Context, eyes, hfov_deg, res, ss, disk_scale, out_r
                                      float(disk_scale), _ptr(out_rgb), _stream(stream)))
 
 
+def lf_set_view_mask(ctx: Context, enabled=None):
+    """Views taking part in later renders (None: all)."""
+    m = None if enabled is None else np.ascontiguousarray(enabled, np.uint8).reshape(-1)
+    if m is not None and len(m) != ctx.n_views:
+        raise ValueError("enabled must hold one entry per view")
+    _check(lib().lf_set_view_mask(ctx.handle, None if m is None else m.ctypes.data))
+
+
+def lf_two_level_mask(ctx: Context, n_fine, fine_available):
+    """View mask of two-level progressive rendering (fine views first)."""
+    a = np.ascontiguousarray(fine_available, np.uint8).reshape(-1)
+    if len(a) != n_fine:
+        raise ValueError("fine_available must hold n_fine entries")
+    out = np.zeros(ctx.n_views, np.uint8)
+    _check(lib().lf_two_level_mask(ctx.handle, int(n_fine), a.ctypes.data, out.ctypes.data))
+    return out
+
+
 BASIS = {"box": 0, "lanczos2": 1}
 
 
@@ -378,7 +398,7 @@ def lf_last_error() -> str:
 
 # names of every symbol include/lf.h declares (checked by the ABI test)
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_reference",
-           "lf_prefilter",
+           "lf_prefilter", "lf_set_view_mask", "lf_two_level_mask",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
            "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",
