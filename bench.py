@@ -23,6 +23,8 @@ different blending field, reported beside the headline, never as it. A last
 leg times the light field prefilter of Sec. 5 (Eq. (5)): 16 views of a
 real-time model (every 4th view) prefiltered at full resolution with 16
 Lanczos-2 samples per pixel against the whole view set as the offline model.
+The two-level leg renders with half the fine views available and the coarse
+level (every 4th capture, larger disks) filling in (Sec. 7.2).
 """
 from __future__ import annotations
 
@@ -362,6 +364,29 @@ def prefilter_leg(lf, torch, ctx, V, n_targets=16, n_samples=16, reps=3):
     }
 
 
+def two_level_leg(lf, torch, V, eyes_all, steps=200, avail_frac=0.5):
+    """Two-level progressive rendering (Sec. 7.2): fine level = every view,
+    coarse level = every 4th capture again with disks for its own spacing;
+    a seeded half of the fine views is available per frame, and the coarse
+    disks that reach a missing fine centre are drawn with them (FP16 images
+    and geometry, per-frame path)."""
+    import lfsynth
+    coarse = np.arange(0, V.n, 4)
+    idx = np.concatenate([np.arange(V.n), coarse])
+    ext = np.concatenate([np.full((V.n, 4), V.disk_radius),
+                          np.full((len(coarse), 4), 1.5 * lfsynth.mean_nn(V.centres[coarse]))])
+    ctx = lf.lf_load_views(V.centres[idx], V.rot[idx], V.rgba8[idx], V.zdepth[idx], V.src_fov_deg, V.disk_radius,
+                           img_fmt="rgba16f", geo_fmt="f16", disk_ext=ext)
+    avail = (np.random.default_rng(5).uniform(size=V.n) < avail_frac).astype(np.uint8)
+    mask = lf.lf_two_level_mask(ctx, V.n, avail)
+    lf.lf_set_view_mask(ctx, mask)
+    r = time_variant(lf, torch, ctx, eyes_all, steps, 16)
+    ctx.close()
+    return {"fine_available": int(mask[:V.n].sum()), "coarse_drawn": int(mask[V.n:].sum()),
+            "mpix_s": r["mpix_s"], "ms_per_stereo_frame": r["ms_per_stereo_frame"],
+            "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"]}
+
+
 def mixed_batch(lf, torch, ctx, seed, n_poses=64, reps=10):
     """64 stereo poses of uneven per-eye sizes in one persistent launch."""
     import lfsynth
@@ -421,6 +446,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector leg")
     ap.add_argument("--no-prefilter", action="store_true", help="skip the prefilter leg")
+    ap.add_argument("--no-two-level", action="store_true", help="skip the two-level progressive leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
     ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,fp16_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
@@ -507,6 +533,13 @@ def main():
         log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']}, "
             f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
+    two = None
+    if not args.no_two_level:
+        log("[bench] two-level ...")
+        two = two_level_leg(lf, torch, V, eyes_all)
+        log(f"[bench] two-level: {two['fine_available']} fine + {two['coarse_drawn']} coarse views, "
+            f"{two['mpix_s']:.0f} Mpix/s, {two['ms_per_stereo_frame']:.4f} ms/stereo frame")
+
     pref = None
     if not args.no_prefilter and ("rgba32f", "f32", "circle") in ctxs:
         log("[bench] prefilter ...")
@@ -581,6 +614,7 @@ def main():
         "mixed_batch": mixed,
         "corrector": corr,
         "prefilter": pref,
+        "two_level": two,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
