@@ -475,7 +475,7 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the renderer has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
