@@ -448,14 +448,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int l = tid >> 5, c = tid & 31;
         s_bias[l][c] = (l < 3 || c < 16) ? bbuf[L.layer[l].b_off + c] : 0.0f;
     }
-    // this lane's weight fragments (row 16 nb + i, columns 32 s + 8 g ..)
-    bf16x8 w1[3][2], w2[9][2], w3[9][2], w4[9][1];
+    // this lane's weight fragments of layers 2-4 (row 16 nb + i, columns
+    // 32 s + 8 g ..), held for the life of the workgroup; layer 1's are
+    // fetched per tile (cached), which leaves registers for the prefetch below
+    bf16x8 w2[9][2], w3[9][2], w4[9][1];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
         const int co = 16 * nb + i;
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-            w1[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[0].wf_off + co * L.layer[0].kf + 32 * s + 8 * g]);
 #pragma unroll
         for (int s = 0; s < 9; ++s) {
             w2[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[1].wf_off + co * L.layer[1].kf + 32 * s + 8 * g]);
@@ -468,22 +467,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     const int tx = (W + FT - 1) / FT, ty = (H + FT - 1) / FT;
     const int total = N * tx * ty;
+    // The layer-1 inputs of a tile (its region grown by 4 pixels per side) are
+    // read from the render into registers one tile ahead: thread t holds
+    // region pixels t, t + 256 and t + 512, and the next tile's loads are in
+    // flight while this tile's layers run.
+    constexpr int QN = (FR0 * FR0 + 255) / 256;
+    float pr[QN], pg[QN], pb[QN], pw[QN];
+    uint32_t pn[QN];
+    auto fetch = [&](int t) {
+        const int n = t / (tx * ty), r = t % (tx * ty);
+        const int x0 = (r % tx) * FT, y0 = (r / tx) * FT;
+        const int64_t img = (int64_t)n * H * W;
+#pragma unroll
+        for (int k = 0; k < QN; ++k) {
+            const int q = tid + 256 * k;
+            const int xx = x0 - 4 + q % FR0, yy = y0 - 4 + q / FR0;
+            pr[k] = pg[k] = pb[k] = pw[k] = 0.0f;
+            pn[k] = 0u;
+            if (q < FR0 * FR0 && xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                const int64_t p = img + (int64_t)yy * W + xx;
+                pr[k] = rgb[3 * p];
+                pg[k] = rgb[3 * p + 1];
+                pb[k] = rgb[3 * p + 2];
+                pw[k] = wsum[p];
+                pn[k] = count[p];
+            }
+        }
+    };
+    if (blockIdx.x < total) fetch(blockIdx.x);
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int n = tile / (tx * ty), r = tile % (tx * ty);
         const int x0 = (r % tx) * FT, y0 = (r / tx) * FT;
         const int64_t img = (int64_t)n * H * W;
-        // layer-1 input over the tile grown by 4 pixels per side
-        for (int q = tid; q < FR0 * FR0; q += 256) {
-            const int xx = x0 - 4 + q % FR0, yy = y0 - 4 + q / FR0;
-            uint4 o = make_uint4(0, 0, 0, 0);
-            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
-                const int64_t p = img + (int64_t)yy * W + xx;
-                o.x = f2bf(rgb[3 * p]) | ((uint32_t)f2bf(rgb[3 * p + 1]) << 16);
-                o.y = f2bf(rgb[3 * p + 2]) | ((uint32_t)f2bf(wsum[p] * (1.0f / kCorrWScale)) << 16);
-                o.z = f2bf((float)count[p] * (1.0f / kCorrNScale));
+        // layer-1 input (R, G, B, W / 4, n / 8; zero outside the image) from the staged values
+#pragma unroll
+        for (int k = 0; k < QN; ++k) {
+            const int q = tid + 256 * k;
+            if (q < FR0 * FR0) {
+                uint4 o;
+                o.x = f2bf(pr[k]) | ((uint32_t)f2bf(pg[k]) << 16);
+                o.y = f2bf(pb[k]) | ((uint32_t)f2bf(pw[k] * (1.0f / kCorrWScale)) << 16);
+                o.z = f2bf((float)pn[k] * (1.0f / kCorrNScale));
+                o.w = 0u;
+                *reinterpret_cast<uint4 *>(&s_in[q * 8]) = o;
             }
-            *reinterpret_cast<uint4 *>(&s_in[q * 8]) = o;
         }
+        // (an opaque zero offset keeps the compiler from hoisting these loads
+        // out of the tile loop, which would keep them live across it)
+        int wz = 0;
+        asm volatile("" : "+s"(wz));
+        bf16x8 w1[3][2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                w1[s][nb] = *reinterpret_cast<const bf16x8 *>(
+                    &wbuf[wz + L.layer[0].wf_off + (16 * nb + i) * L.layer[0].kf + 32 * s + 8 * g]);
+        if (tile + (int)gridDim.x < total) fetch(tile + gridDim.x);
         __syncthreads();
         fused_layer<FR1, true, 3, 2, false>(s_in, s_a, nullptr, w1, s_bias[0], x0 - 3, y0 - 3, H, W);
         __syncthreads();

@@ -100,6 +100,42 @@ def test_fused_inference_matches_training_forward(shape):
     c.close()
 
 
+def test_fused_inference_many_tiles_per_workgroup():
+    """An image with several times more 16 x 16 tiles than the fused kernel
+    has resident workgroups, so every workgroup runs several tiles and reads
+    each next tile's input while the current one computes. Windows at the
+    corners and inside are checked against the FP64 oracle on crops grown by
+    the network's 4-pixel reach (cut at the image edge, where the oracle's
+    zero padding is the image's)."""
+    import torch
+    from paper_1810_08860_amd import lf
+    n, h, w = 2, 392, 584  # 25 x 37 tiles per image, ragged in both directions
+    prm = _params(21)
+    rng = np.random.default_rng(22)
+    rgb = rng.uniform(0, 1, (n, h, w, 3)).astype(np.float32)
+    ws = rng.uniform(0, 3, (n, h, w)).astype(np.float32)
+    cnt = rng.integers(0, 10, (n, h, w)).astype(np.uint8)
+    c = lf.lf_corrector_create(prm)
+    d_rgb, d_ws, d_cnt = _dev(rgb, ws, cnt)
+    resid = torch.zeros_like(d_rgb)
+    out = torch.zeros_like(d_rgb)
+    lf.lf_corrector_apply(c, d_rgb, d_ws, d_cnt, n, w, h, float("inf"), out, None, resid)
+    torch.cuda.synchronize()
+    got = resid.cpu().numpy().astype(np.float64)
+    c.close()
+    p64 = bf16_round(prm).astype(np.float64)
+    wins = [(0, 0, 0), (1, h - 20, w - 20), (0, 0, w - 20), (1, h - 20, 0)]
+    wins += [(int(rng.integers(n)), int(rng.integers(h - 20)), int(rng.integers(w - 20))) for _ in range(6)]
+    for k, y0, x0 in wins:
+        ya, yb, xa, xb = max(0, y0 - 4), min(h, y0 + 24), max(0, x0 - 4), min(w, x0 + 24)
+        x = _oracle_inputs(rgb[k:k + 1, ya:yb, xa:xb], ws[k:k + 1, ya:yb, xa:xb], cnt[k:k + 1, ya:yb, xa:xb])
+        want = oracle.corrector_forward(p64, x)[0][0, y0 - ya:y0 - ya + 20, x0 - xa:x0 - xa + 20]
+        g = got[k, y0:y0 + 20, x0:x0 + 20]
+        rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+        print(f"window image {k} at ({y0}, {x0}): relative L2 {rel:.3g}")
+        assert rel < 1e-2
+
+
 def test_fallback_threshold_rule():
     import torch
     from paper_1810_08860_amd import lf
