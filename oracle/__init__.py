@@ -40,6 +40,7 @@ class _Views(ctypes.Structure):
         ("disk_radius", ctypes.c_double), ("disk_ext", ctypes.c_void_p),
         ("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
         ("yuv_y", ctypes.c_void_p), ("yuv_uv", ctypes.c_void_p),
+        ("rgtc_y", ctypes.c_void_p), ("rgtc_uv", ctypes.c_void_p),
     ]
 
 
@@ -86,6 +87,8 @@ def lib():
                                     i64, vp, vp, vp]
         L.orc_basis.argtypes = [i32, f64]
         L.orc_yuv420_encode.argtypes = [i32, i32, i32, vp, vp, vp]
+        L.orc_rgtc_encode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
+        L.orc_rgtc_decode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
         L.orc_basis.restype = f64
         L.orc_views_size.restype = i32
         L.orc_rec_size.restype = i32
@@ -133,7 +136,7 @@ class OracleViews:
         self.s = _Views(n, w, h, m, float(src_fov_deg), _p(self.centres), _p(self.rot), _p(self.rgba8),
                         _p(self.zdepth), _p(self.zrange), float(disk_radius),
                         None if self.disk_ext is None else _p(self.disk_ext),
-                        1 if mode == "brute" else 0, int(threads), None, None)
+                        1 if mode == "brute" else 0, int(threads), None, None, None, None)
 
     @classmethod
     def from_views(cls, v, mode="traversal", threads=0, disk_radius=None, disk_ext=None):
@@ -167,6 +170,15 @@ class OracleViews:
         o = self.with_disk_radius(self.s.disk_radius)
         o.yuv_y, o.yuv_uv = yuv420_encode(self.rgba8)
         o.s.yuv_y, o.s.yuv_uv = _p(o.yuv_y), _p(o.yuv_uv)
+        return o
+
+    def with_yuv420_rgtc(self):
+        """The YUV420 form transcoded to RGTC blocks (luma RGTC1, chroma RGTC2),
+        the 4x smaller tile-cache form of Sec. 7.2, by the oracle's own encoder
+        (see rgtc_encode); sampling reads the decoded block texels."""
+        o = self.with_yuv420()
+        o.rgtc_y, o.rgtc_uv = rgtc_encode(o.yuv_y, o.yuv_uv)
+        o.s.rgtc_y, o.s.rgtc_uv = _p(o.rgtc_y), _p(o.rgtc_uv)
         return o
 
     def with_mode(self, mode):
@@ -285,6 +297,35 @@ def yuv420_encode(rgba8):
     y = np.zeros((n, H, W), np.uint8)
     uv = np.zeros((n, H // 2, W // 2, 2), np.uint8)
     lib().orc_yuv420_encode(n, W, H, _p(rgba8), _p(y), _p(uv))
+    return y, uv
+
+
+def rgtc_encode(y, uv):
+    """RGTC blocks of YUV420 planes (oracle.c, orc_rgtc_encode): luma (n,H,W)
+    as RGTC1 blocks (n,H/4,W/4,8) and chroma (n,H/2,W/2,2) as RGTC2 blocks
+    (n,H/8,W/8,16), row-major over blocks. Sizes must be multiples of 8."""
+    y = np.ascontiguousarray(y, np.uint8)
+    uv = np.ascontiguousarray(uv, np.uint8)
+    n, H, W = y.shape
+    if H % 8 or W % 8:
+        raise ValueError("RGTC needs image sizes that are multiples of 8")
+    assert uv.shape == (n, H // 2, W // 2, 2)
+    yb = np.zeros((n, H // 4, W // 4, 8), np.uint8)
+    uvb = np.zeros((n, H // 8, W // 8, 16), np.uint8)
+    lib().orc_rgtc_encode(n, W, H, _p(y), _p(uv), _p(yb), _p(uvb))
+    return yb, uvb
+
+
+def rgtc_decode(yb, uvb):
+    """Decoded planes of RGTC blocks, real values in 0..255: luma (n,H,W) and
+    chroma (n,H/2,W/2,2)."""
+    yb = np.ascontiguousarray(yb, np.uint8)
+    uvb = np.ascontiguousarray(uvb, np.uint8)
+    n, H, W = yb.shape[0], 4 * yb.shape[1], 4 * yb.shape[2]
+    assert uvb.shape == (n, H // 8, W // 8, 16)
+    y = np.zeros((n, H, W), np.float64)
+    uv = np.zeros((n, H // 2, W // 2, 2), np.float64)
+    lib().orc_rgtc_decode(n, W, H, _p(yb), _p(uvb), _p(y), _p(uv))
     return y, uv
 
 

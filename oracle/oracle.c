@@ -71,6 +71,8 @@ typedef struct {
     int32_t threads;
     const uint8_t *yuv_y;    /* [n][img_h][img_w] luma, or NULL: sample rgba8 */
     const uint8_t *yuv_uv;   /* [n][img_h/2][img_w/2][2] chroma (Cb, Cr) at half resolution */
+    const uint8_t *rgtc_y;   /* [n][img_h/4][img_w/4][8] luma as RGTC1 blocks, or NULL: sample yuv_y / rgba8 */
+    const uint8_t *rgtc_uv;  /* [n][img_h/8][img_w/8][16] chroma as RGTC2 blocks (Cb block, then Cr block) */
 } orc_views;
 
 /* Per-ray outputs. Lists are ascending view ids padded with -1. */
@@ -333,6 +335,121 @@ void orc_yuv420_encode(int32_t n, int32_t W, int32_t H, const uint8_t *rgba8, ui
     }
 }
 
+/*
+ * RGTC form of the YUV420 planes (the paper's renderer can transcode its
+ * cached YUV420 tiles to RGTC for a 4x smaller tile cache, Sec. 7.2). The
+ * block format is the published RGTC1 (BC4, unsigned) one: a 4x4 block of one
+ * 8-bit channel is 8 bytes, two endpoints e0 = byte 0 and e1 = byte 1, then a
+ * 48-bit little-endian field holding a 3-bit code per texel, texel (x, y) of
+ * the block at bits 3 (4 y + x). Code 0 stands for e0 and code 1 for e1; if
+ * e0 > e1, codes 2..7 stand for the six points that split [e1, e0] into
+ * sevenths, code c at ((8 - c) e0 + (c - 1) e1) / 7; otherwise codes 2..5
+ * split it into fifths, ((6 - c) e0 + (c - 1) e1) / 5, code 6 is 0 and code 7
+ * is 255. RGTC2 (BC5) is two such blocks, one per channel, first channel
+ * first. Luma is coded in RGTC1 blocks of the full-resolution plane and the
+ * chroma pair in RGTC2 blocks of the half-resolution plane, both row-major
+ * over blocks, so the image sizes must be multiples of 8.
+ *
+ * The encoder (any encoder yields a valid block; this one is fixed so that
+ * every implementation writes the same bytes, with integer arithmetic only):
+ * e0 = the block maximum, e1 = the block minimum; a constant block takes code
+ * 0 everywhere; otherwise each texel takes the nearest of the eight points,
+ * the one at p = round(7 (e0 - x) / (e0 - e1)) sevenths from e0, halves
+ * rounded up, coded 0 for p = 0, 1 for p = 7 and p + 1 in between.
+ */
+static void rgtc1_block(const uint8_t *src, int64_t stride, int32_t step, uint8_t out[8]) {
+    int32_t v[16], hi = 0, lo = 255;
+    for (int32_t t = 0; t < 16; ++t) {
+        v[t] = src[(t / 4) * stride + (t % 4) * step];
+        if (v[t] > hi) hi = v[t];
+        if (v[t] < lo) lo = v[t];
+    }
+    uint64_t bits = 0;
+    if (hi > lo) {
+        const int32_t d = hi - lo;
+        for (int32_t t = 0; t < 16; ++t) {
+            const int32_t p = (14 * (hi - v[t]) + d) / (2 * d);
+            const uint64_t code = p == 0 ? 0 : (p == 7 ? 1 : (uint64_t)(p + 1));
+            bits |= code << (3 * t);
+        }
+    }
+    out[0] = (uint8_t)hi;
+    out[1] = (uint8_t)lo;
+    for (int32_t b = 0; b < 6; ++b) out[2 + b] = (uint8_t)(bits >> (8 * b));
+}
+
+void orc_rgtc_encode(int32_t n, int32_t W, int32_t H, const uint8_t *y, const uint8_t *uv, uint8_t *yb,
+                     uint8_t *uvb) {
+    const int32_t Wc = W / 2, Hc = H / 2;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint8_t *yi = y + (int64_t)i * W * H;
+        const uint8_t *ci = uv + (int64_t)i * Wc * Hc * 2;
+        uint8_t *ybi = yb + (int64_t)i * (W / 4) * (H / 4) * 8;
+        uint8_t *cbi = uvb + (int64_t)i * (Wc / 4) * (Hc / 4) * 16;
+        for (int32_t by = 0; by < H / 4; ++by)
+            for (int32_t bx = 0; bx < W / 4; ++bx)
+                rgtc1_block(yi + (int64_t)4 * by * W + 4 * bx, W, 1, ybi + 8 * ((int64_t)by * (W / 4) + bx));
+        for (int32_t by = 0; by < Hc / 4; ++by)
+            for (int32_t bx = 0; bx < Wc / 4; ++bx) {
+                uint8_t *o = cbi + 16 * ((int64_t)by * (Wc / 4) + bx);
+                const uint8_t *s0 = ci + 2 * ((int64_t)4 * by * Wc + 4 * bx);
+                rgtc1_block(s0, 2 * (int64_t)Wc, 2, o);
+                rgtc1_block(s0 + 1, 2 * (int64_t)Wc, 2, o + 8);
+            }
+    }
+}
+
+/* Texel t (= 4 y + x) of an RGTC1 block, decoded to a real value in 0..255. */
+static double rgtc1_texel(const uint8_t *blk, int32_t t) {
+    uint64_t bits = 0;
+    for (int32_t b = 0; b < 6; ++b) bits |= (uint64_t)blk[2 + b] << (8 * b);
+    const int32_t c = (int32_t)((bits >> (3 * t)) & 7u);
+    const double e0 = blk[0], e1 = blk[1];
+    if (c == 0) return e0;
+    if (c == 1) return e1;
+    if (blk[0] > blk[1]) return ((8 - c) * e0 + (c - 1) * e1) / 7.0;
+    if (c == 6) return 0.0;
+    if (c == 7) return 255.0;
+    return ((6 - c) * e0 + (c - 1) * e1) / 5.0;
+}
+
+/* Texel (x, y) of channel ch of a plane of W x H texels stored as RGTC blocks
+ * of bpb bytes (8: RGTC1; 16: RGTC2, channel ch's block at byte 8 ch). */
+static double rgtc_plane_texel(const uint8_t *blocks, int32_t W, int32_t bpb, int32_t ch, int64_t x, int64_t y) {
+    const uint8_t *blk = blocks + bpb * ((y / 4) * (W / 4) + x / 4) + 8 * ch;
+    return rgtc1_texel(blk, (int32_t)(4 * (y % 4) + x % 4));
+}
+
+/* Decoded planes (luma [n][H][W], chroma [n][H/2][W/2][2]) in 0..255 units. */
+void orc_rgtc_decode(int32_t n, int32_t W, int32_t H, const uint8_t *yb, const uint8_t *uvb, double *y, double *uv) {
+    const int32_t Wc = W / 2, Hc = H / 2;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint8_t *ybi = yb + (int64_t)i * (W / 4) * (H / 4) * 8;
+        const uint8_t *cbi = uvb + (int64_t)i * (Wc / 4) * (Hc / 4) * 16;
+        for (int64_t r = 0; r < H; ++r)
+            for (int64_t c = 0; c < W; ++c) y[((int64_t)i * H + r) * W + c] = rgtc_plane_texel(ybi, W, 8, 0, c, r);
+        for (int64_t r = 0; r < Hc; ++r)
+            for (int64_t c = 0; c < Wc; ++c)
+                for (int32_t ch = 0; ch < 2; ++ch)
+                    uv[(((int64_t)i * Hc + r) * Wc + c) * 2 + ch] = rgtc_plane_texel(cbi, Wc, 16, ch, c, r);
+    }
+}
+
+/* Bilinear sample of channel ch of an RGTC-coded plane, as plane_bilinear. */
+static double rgtc_bilinear(const uint8_t *blocks, int32_t W, int32_t H, int32_t bpb, int32_t ch, double px, double py) {
+    double fx0 = floor(px), fy0 = floor(py);
+    double fx = px - fx0, fy = py - fy0;
+    int64_t x0 = (int64_t)fx0, y0 = (int64_t)fy0, x1 = x0 + 1, y1 = y0 + 1;
+    if (x0 < 0) x0 = 0; if (x0 > W - 1) x0 = W - 1;
+    if (x1 < 0) x1 = 0; if (x1 > W - 1) x1 = W - 1;
+    if (y0 < 0) y0 = 0; if (y0 > H - 1) y0 = H - 1;
+    if (y1 < 0) y1 = 0; if (y1 > H - 1) y1 = H - 1;
+    const double a = rgtc_plane_texel(blocks, W, bpb, ch, x0, y0), b = rgtc_plane_texel(blocks, W, bpb, ch, x1, y0);
+    const double d = rgtc_plane_texel(blocks, W, bpb, ch, x0, y1), e = rgtc_plane_texel(blocks, W, bpb, ch, x1, y1);
+    const double top = a + fx * (b - a), bot = d + fx * (e - d);
+    return top + fy * (bot - top);
+}
+
 /* Bilinear sample of a one- or two-channel 8-bit plane at texel-centre
  * coordinate (px, py), clamp-to-edge; channel c of nc. */
 static double plane_bilinear(const uint8_t *pl, int32_t W, int32_t H, int32_t nc, int32_t c, double px, double py) {
@@ -353,12 +470,26 @@ static double plane_bilinear(const uint8_t *pl, int32_t W, int32_t H, int32_t nc
  * bilinear over texel centres, clamp-to-edge, RGB/255. With YUV420 planes the
  * luma is sampled at full resolution and the chroma at half resolution (a
  * chroma sample sits at the centre of its 2x2 luma block), then recombined
- * with the full-range BT.601 inverse; no clamping of the result. */
+ * with the full-range BT.601 inverse; no clamping of the result. With RGTC
+ * blocks the planes' texels are the decoded block values, sampled the same
+ * way. */
 void orc_sample(const orc_views *V, int32_t i, double Xs, double Ys, double rgb[3]) {
     const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
     const int32_t W = V->img_w, H = V->img_h;
     double px = (Xs / ts + 1.0) * 0.5 * W - 0.5;
     double py = (1.0 - Ys / ts) * 0.5 * H - 0.5;
+    if (V->rgtc_y) {
+        const uint8_t *yb = V->rgtc_y + (int64_t)i * (W / 4) * (H / 4) * 8;
+        const uint8_t *cb_blocks = V->rgtc_uv + (int64_t)i * (W / 8) * (H / 8) * 16;
+        const double Y = rgtc_bilinear(yb, W, H, 8, 0, px, py);
+        const double cx = 0.5 * (px - 0.5), cy = 0.5 * (py - 0.5);
+        const double cb = rgtc_bilinear(cb_blocks, W / 2, H / 2, 16, 0, cx, cy) - 128.0;
+        const double cr = rgtc_bilinear(cb_blocks, W / 2, H / 2, 16, 1, cx, cy) - 128.0;
+        rgb[0] = (Y + 1.402 * cr) / 255.0;
+        rgb[1] = (Y - 0.344136 * cb - 0.714136 * cr) / 255.0;
+        rgb[2] = (Y + 1.772 * cb) / 255.0;
+        return;
+    }
     if (V->yuv_y) {
         const double Y = plane_bilinear(V->yuv_y + (int64_t)i * W * H, W, H, 1, 0, px, py);
         const uint8_t *uv = V->yuv_uv + (int64_t)i * (W / 2) * (H / 2) * 2;
