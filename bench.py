@@ -448,7 +448,7 @@ def main():
     ap.add_argument("--no-prefilter", action="store_true", help="skip the prefilter leg")
     ap.add_argument("--no-two-level", action="store_true", help="skip the two-level progressive leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
-    ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,fp16_batched,fp16_batched_oval")
+    ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,yuv420_rgtc,fp16_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
@@ -495,6 +495,7 @@ def main():
     # definition; "oval" = the asymmetric Delaunay 1-ring ovals of Sec. 4.4 (a different blending field)
     storage = {"plain": ("rgba32f", "f32", "circle"), "fp16": ("rgba16f", "f16", "circle"),
                "rgba8": ("rgba8", "f16", "circle"), "yuv420": ("yuv420", "f16", "circle"),
+               "yuv420_rgtc": ("yuv420_rgtc", "f16", "circle"),
                "fp16_batched": ("rgba16f", "f16", "circle"),
                "fp16_batched_oval": ("rgba16f", "f16", "oval")}
     chosen = [v for v in args.variants.split(",") if v]

@@ -65,9 +65,17 @@ enum {
  * >> 8) + 128, Cr = ((128 R - 107 G - 21 B + 128) >> 8) + 128, clamped to 255,
  * each chroma sample the rounded mean of its 2x2 block), sampled bilinearly
  * per plane (a chroma sample sits at the centre of its block) and recombined
- * with the BT.601 inverse; it needs even image sizes. All sampling and
- * blending arithmetic is FP32 in every format. */
-enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2, LF_IMG_YUV420 = 3 };
+ * with the BT.601 inverse; it needs even image sizes. YUV420_RGTC is the
+ * same two planes transcoded to RGTC blocks, the paper's 4x smaller tile
+ * cache (Sec. 7.2): luma as RGTC1 (BC4) blocks of 4 x 4 texels, 8 bytes
+ * each, chroma as RGTC2 (BC5) blocks of 4 x 4 chroma samples, 16 bytes each
+ * (the Cb block, then the Cr block), 0.75 bytes per texel in all. Each block
+ * takes e0 = its maximum and e1 = its minimum and every value the nearest of
+ * the eight points that split [e1, e0] into sevenths (halves rounded towards
+ * e1); the render decodes the texels it reads from their blocks and samples
+ * as for YUV420. It needs image sizes that are multiples of 8. All sampling
+ * and blending arithmetic is FP32 in every format. */
+enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2, LF_IMG_YUV420 = 3, LF_IMG_YUV420_RGTC = 4 };
 
 /* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex, in
  * FP32 or FP16, packed per mesh cell. Intersection arithmetic is FP32. */

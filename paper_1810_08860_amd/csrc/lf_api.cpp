@@ -56,9 +56,21 @@ bool frame_ok(const double *R) {
     return true;
 }
 
-// bytes per texel of the (first) image plane
-size_t img_bytes_per_texel(int fmt) {
-    return fmt == LF_IMG_RGBA8 ? 4 : (fmt == LF_IMG_RGBA16F ? 8 : (fmt == LF_IMG_RGBA32F ? 16 : 1));
+// bytes of one view's first image plane (YUV420: luma; RGTC: luma blocks)
+// and of its second (the chroma plane or its blocks; none for RGBA)
+int64_t img_view_bytes(int fmt, int64_t W, int64_t H) {
+    switch (fmt) {
+    case LF_IMG_RGBA8: return 4 * W * H;
+    case LF_IMG_RGBA16F: return 8 * W * H;
+    case LF_IMG_RGBA32F: return 16 * W * H;
+    case LF_IMG_YUV420: return W * H;
+    default: return (W / 4) * (H / 4) * 8;
+    }
+}
+int64_t img2_view_bytes(int fmt, int64_t W, int64_t H) {
+    if (fmt == LF_IMG_YUV420) return (W / 2) * (H / 2) * 2;
+    if (fmt == LF_IMG_YUV420_RGTC) return (W / 8) * (H / 8) * 16;
+    return 0;
 }
 size_t geo_bytes_per_cell(int fmt) { return fmt == LF_GEO_F32 ? 16 : 8; }
 
@@ -242,8 +254,8 @@ ViewBases view_bases(const lf_ctx *c) {
     vb.img2 = static_cast<const char *>(c->img2);
     vb.blk = c->blk;
     vb.geo_bytes = (int64_t)(c->M - 1) * (c->M - 1) * (c->geo_fmt == LF_GEO_F32 ? 16 : 8);
-    vb.img_bytes = (int64_t)c->img_w * c->img_h * (int64_t)img_bytes_per_texel(c->img_fmt);
-    vb.img2_bytes = (int64_t)(c->img_w / 2) * (c->img_h / 2) * 2;
+    vb.img_bytes = img_view_bytes(c->img_fmt, c->img_w, c->img_h);
+    vb.img2_bytes = img2_view_bytes(c->img_fmt, c->img_w, c->img_h);
     vb.blk_per_view = (int64_t)num_blocks(c->M) * num_blocks(c->M);
     return vb;
 }
@@ -298,9 +310,12 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (!(d->src_fov_deg > 0.0 && d->src_fov_deg < 180.0)) return fail(LF_EINVAL, "src_fov_deg must be in (0,180)");
     if (!(d->disk_radius > 0.0) || !std::isfinite(d->disk_radius)) return fail(LF_EINVAL, "disk_radius must be > 0");
     if (!d->centres || !d->rot || !d->rgba8 || !d->zdepth) return fail(LF_EINVAL, "NULL data pointer");
-    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_YUV420) return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
+    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_YUV420_RGTC)
+        return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
     if (d->img_fmt == LF_IMG_YUV420 && (d->img_w % 2 || d->img_h % 2))
         return fail(LF_EINVAL, "YUV420 needs even image sizes (got %dx%d)", d->img_w, d->img_h);
+    if (d->img_fmt == LF_IMG_YUV420_RGTC && (d->img_w % 8 || d->img_h % 8))
+        return fail(LF_EINVAL, "RGTC needs image sizes that are multiples of 8 (got %dx%d)", d->img_w, d->img_h);
     if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
     if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
     const int32_t n = d->n_views, M = d->mesh_m;
@@ -398,8 +413,25 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (rgba_owned) (void)hipFree(rgba_dev);
         if (e != hipSuccess) return bail(hip_fail(e, "YUV420 conversion"));
+    } else if (d->img_fmt == LF_IMG_YUV420_RGTC) {
+        // RGBA8 -> YUV420 planes (scratch) -> RGTC blocks
+        uint8_t *yp = nullptr, *uvp = nullptr;
+        if ((e = hipMalloc(&c->img, (size_t)n * img_view_bytes(d->img_fmt, d->img_w, d->img_h))) != hipSuccess ||
+            (e = hipMalloc(&c->img2, (size_t)n * img2_view_bytes(d->img_fmt, d->img_w, d->img_h))) != hipSuccess ||
+            (e = hipMalloc(&yp, n_tex)) != hipSuccess || (e = hipMalloc(&uvp, n_tex / 2)) != hipSuccess) {
+            if (yp) (void)hipFree(yp);
+            if (rgba_owned) (void)hipFree(rgba_dev);
+            return bail(hip_fail(e, "hipMalloc(RGTC planes)"));
+        }
+        e = launch_convert_yuv420((const uint8_t *)rgba_dev, yp, uvp, n, d->img_w, d->img_h, 0);
+        if (e == hipSuccess) e = launch_convert_rgtc(yp, uvp, c->img, c->img2, n, d->img_w, d->img_h, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        (void)hipFree(yp);
+        (void)hipFree(uvp);
+        if (rgba_owned) (void)hipFree(rgba_dev);
+        if (e != hipSuccess) return bail(hip_fail(e, "RGTC conversion"));
     } else {
-        if ((e = hipMalloc(&c->img, n_tex * img_bytes_per_texel(d->img_fmt))) != hipSuccess) {
+        if ((e = hipMalloc(&c->img, n_tex * (size_t)img_view_bytes(d->img_fmt, 1, 1))) != hipSuccess) {
             if (rgba_owned) (void)hipFree(rgba_dev);
             return bail(hip_fail(e, "hipMalloc(converted images)"));
         }

@@ -142,6 +142,8 @@ hipError_t launch_convert_images(const uint8_t *src, void *dst, int img_fmt, int
 // RGBA8 [n][H][W] -> luma [n][H][W] and chroma [n][H/2][W/2][2] (H, W even)
 hipError_t launch_convert_yuv420(const uint8_t *src, uint8_t *y, uint8_t *uv, int32_t n, int32_t W, int32_t H,
                                  hipStream_t s);
+hipError_t launch_convert_rgtc(const uint8_t *y, const uint8_t *uv, void *yb, void *uvb, int32_t n, int32_t W,
+                               int32_t H, hipStream_t s);
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);

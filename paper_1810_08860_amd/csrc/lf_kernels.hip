@@ -95,6 +95,57 @@ __global__ void k_convert_yuv420(const uint32_t *__restrict__ src, uint8_t *__re
     }
 }
 
+// RGTC1 block of 16 8-bit values (texel t = 4 y + x at src[y * stride +
+// x * step]): e0 = maximum, e1 = minimum, a constant block all code 0,
+// otherwise each texel the nearest of the eight points, p = round(7 (e0 - x) /
+// (e0 - e1)) sevenths from e0 with halves rounded up, coded 0 for p = 0, 1 for
+// p = 7 and p + 1 in between (integer arithmetic: any exact implementation
+// writes the same bytes).
+__device__ uint2 rgtc1_encode(const uint8_t *__restrict__ src, int64_t stride, int step) {
+    int v[16], hi = 0, lo = 255;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        v[t] = src[(t >> 2) * stride + (t & 3) * step];
+        hi = max(hi, v[t]);
+        lo = min(lo, v[t]);
+    }
+    uint64_t bits = 0;
+    if (hi > lo) {
+        const int d = hi - lo;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int p = (14 * (hi - v[t]) + d) / (2 * d);
+            const uint64_t code = p == 0 ? 0u : (p == 7 ? 1u : (uint64_t)(p + 1));
+            bits |= code << (3 * t);
+        }
+    }
+    const uint64_t word = (uint64_t)hi | ((uint64_t)lo << 8) | (bits << 16);
+    return make_uint2((uint32_t)word, (uint32_t)(word >> 32));
+}
+
+// RGTC blocks of YUV420 planes: thread q < n (W/4) (H/4) codes one luma
+// block, the rest one chroma block each (its Cb block, then its Cr block).
+__global__ void k_convert_rgtc(const uint8_t *__restrict__ y, const uint8_t *__restrict__ uv,
+                               uint2 *__restrict__ yb, uint4 *__restrict__ uvb, int32_t n, int32_t W, int32_t H) {
+    const int Wc = W / 2, Hc = H / 2;
+    const int64_t nl = (int64_t)(W / 4) * (H / 4), nc = (int64_t)(Wc / 4) * (Hc / 4);
+    const int64_t total = n * (nl + nc);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        if (q < n * nl) {
+            const int64_t v = q / nl, r = q % nl;
+            const int by = (int)(r / (W / 4)), bx = (int)(r % (W / 4));
+            yb[q] = rgtc1_encode(y + v * W * H + (int64_t)4 * by * W + 4 * bx, W, 1);
+        } else {
+            const int64_t qc = q - n * nl;
+            const int64_t v = qc / nc, r = qc % nc;
+            const int by = (int)(r / (Wc / 4)), bx = (int)(r % (Wc / 4));
+            const uint8_t *s0 = uv + 2 * (v * Wc * Hc + (int64_t)4 * by * Wc + 4 * bx);
+            const uint2 b0 = rgtc1_encode(s0, 2 * (int64_t)Wc, 2), b1 = rgtc1_encode(s0 + 1, 2 * (int64_t)Wc, 2);
+            uvb[qc] = make_uint4(b0.x, b0.y, b1.x, b1.y);
+        }
+    }
+}
+
 // Mesh cells of every view: corner inverse depths (w00, w10, w01, w11).
 template <int GEO>
 __global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cells, int32_t n, int32_t M) {
@@ -557,6 +608,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
             Rgb col;
             if constexpr (IMG == 3) col = bilinear_yuv(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
+            else if constexpr (IMG == 4) col = bilinear_rgtc(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
             else col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
             accr = fmaf(rv.rho, col.r, accr);
             accg = fmaf(rv.rho, col.g, accg);
@@ -769,6 +821,14 @@ hipError_t launch_convert_yuv420(const uint8_t *src, uint8_t *y, uint8_t *uv, in
     return hipGetLastError();
 }
 
+hipError_t launch_convert_rgtc(const uint8_t *y, const uint8_t *uv, void *yb, void *uvb, int32_t n, int32_t W,
+                               int32_t H, hipStream_t s) {
+    const int64_t blocks = (int64_t)n * ((int64_t)(W / 4) * (H / 4) + (int64_t)(W / 8) * (H / 8));
+    const int g = grid_for(blocks, 256);
+    hipLaunchKernelGGL(k_convert_rgtc, dim3(g), dim3(256), 0, s, y, uv, (uint2 *)yb, (uint4 *)uvb, n, W, H);
+    return hipGetLastError();
+}
+
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s) {
     const int g = grid_for((int64_t)(M - 1) * (M - 1) * n, 256);
     if (geo_fmt == 0)
@@ -816,12 +876,14 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
         if (img_fmt == 0) LF_R(0, 0);
         else if (img_fmt == 1) LF_R(1, 0);
         else if (img_fmt == 2) LF_R(2, 0);
-        else LF_R(3, 0);
+        else if (img_fmt == 3) LF_R(3, 0);
+        else LF_R(4, 0);
     } else {
         if (img_fmt == 0) LF_R(0, 1);
         else if (img_fmt == 1) LF_R(1, 1);
         else if (img_fmt == 2) LF_R(2, 1);
-        else LF_R(3, 1);
+        else if (img_fmt == 3) LF_R(3, 1);
+        else LF_R(4, 1);
     }
 #undef LF_R
 }
@@ -841,12 +903,14 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
         if (img_fmt == 0) LF_P(0, 0);
         else if (img_fmt == 1) LF_P(1, 0);
         else if (img_fmt == 2) LF_P(2, 0);
-        else LF_P(3, 0);
+        else if (img_fmt == 3) LF_P(3, 0);
+        else LF_P(4, 0);
     } else {
         if (img_fmt == 0) LF_P(0, 1);
         else if (img_fmt == 1) LF_P(1, 1);
         else if (img_fmt == 2) LF_P(2, 1);
-        else LF_P(3, 1);
+        else if (img_fmt == 3) LF_P(3, 1);
+        else LF_P(4, 1);
     }
 #undef LF_P
 }
@@ -872,10 +936,12 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
 
 template <int DISK>
 static const void *persistent_fn(int img_fmt, int geo_fmt) {
-    const void *f0[4] = {(const void *)k_render_persistent<0, 0, DISK>, (const void *)k_render_persistent<1, 0, DISK>,
-                         (const void *)k_render_persistent<2, 0, DISK>, (const void *)k_render_persistent<3, 0, DISK>};
-    const void *f1[4] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
-                         (const void *)k_render_persistent<2, 1, DISK>, (const void *)k_render_persistent<3, 1, DISK>};
+    const void *f0[5] = {(const void *)k_render_persistent<0, 0, DISK>, (const void *)k_render_persistent<1, 0, DISK>,
+                         (const void *)k_render_persistent<2, 0, DISK>, (const void *)k_render_persistent<3, 0, DISK>,
+                         (const void *)k_render_persistent<4, 0, DISK>};
+    const void *f1[5] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
+                         (const void *)k_render_persistent<2, 1, DISK>, (const void *)k_render_persistent<3, 1, DISK>,
+                         (const void *)k_render_persistent<4, 1, DISK>};
     return geo_fmt == 0 ? f0[img_fmt] : f1[img_fmt];
 }
 

@@ -87,7 +87,7 @@ LF_HD Rgb texel<2>(const void *__restrict__ img, uint32_t idx) {  // RGBA32F
 
 // scale from stored texel units to [0,1]
 template <int IMG>
-LF_HD float texel_scale() { return (IMG == 0 || IMG == 3) ? (1.0f / 255.0f) : 1.0f; }
+LF_HD float texel_scale() { return (IMG == 0 || IMG >= 3) ? (1.0f / 255.0f) : 1.0f; }
 
 // Corner inverse depths of one mesh cell: (w00, w10, w01, w11) with j to the
 // right and k downwards.
@@ -356,6 +356,76 @@ LF_HD Rgb bilinear_yuv(const void *__restrict__ yp, const void *__restrict__ uvp
         const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
         cb = fmaf(w11, (float)(d & 255u), fmaf(w01, (float)(c & 255u), fmaf(w10, (float)(b & 255u), w00 * (float)(a & 255u)))) - 128.0f;
         cr = fmaf(w11, (float)(d >> 8), fmaf(w01, (float)(c >> 8), fmaf(w10, (float)(b >> 8), w00 * (float)(a >> 8)))) - 128.0f;
+    }
+    return {fmaf(1.402f, cr, lum), fmaf(-0.714136f, cr, fmaf(-0.344136f, cb, lum)), fmaf(1.772f, cb, lum)};
+}
+
+// One texel of an RGTC1 (BC4 unsigned) block held as two little-endian words:
+// endpoints e0 = byte 0, e1 = byte 1, then the 3-bit code of texel t = 4 y + x
+// at bit 16 + 3 t. Code 0 is e0 and code 1 is e1; with e0 > e1 codes 2..7 are
+// the sevenths from e0 towards e1 (code c at c - 1 sevenths), otherwise codes
+// 2..5 are the fifths, code 6 is 0 and code 7 is 255 (result in 0..255 units).
+LF_HD float rgtc1_texel(uint32_t lo, uint32_t hi, uint32_t t) {
+    const uint64_t bits = ((uint64_t)hi << 32) | lo;
+    const uint32_t c = (uint32_t)(bits >> (16u + 3u * t)) & 7u;
+    const uint32_t e0 = lo & 255u, e1 = (lo >> 8) & 255u;
+    const bool eight = e0 > e1;
+    const uint32_t steps = eight ? 7u : 5u;
+    const uint32_t p = c == 0u ? 0u : (c == 1u ? steps : c - 1u);
+    const float f0 = (float)e0;
+    float v = fmaf((float)p * (eight ? (1.0f / 7.0f) : 0.2f), (float)e1 - f0, f0);
+    if (!eight && c >= 6u) v = c == 6u ? 0.0f : 255.0f;
+    return v;
+}
+
+// RGTC form of the YUV420 planes (result in 0..255 units): the luma plane as
+// RGTC1 blocks (8 bytes per 4 x 4 texels) and the chroma plane as RGTC2 blocks
+// (16 bytes: the Cb block, then the Cr block), both row-major over blocks;
+// texels decoded from their blocks, then sampled and recombined as in
+// bilinear_yuv. W and H are multiples of 8.
+LF_HD float rgtc_luma(const void *__restrict__ yp, int Wb, int x, int y) {
+    const uint2 b = at<uint2>(yp, mul24(y >> 2, Wb) + (x >> 2));
+    return rgtc1_texel(b.x, b.y, (uint32_t)(((y & 3) << 2) | (x & 3)));
+}
+LF_HD void rgtc_chroma(const void *__restrict__ uvp, int Wb, int x, int y, float &cb, float &cr) {
+    const uint4 b = at<uint4>(uvp, mul24(y >> 2, Wb) + (x >> 2));
+    const uint32_t t = (uint32_t)(((y & 3) << 2) | (x & 3));
+    cb = rgtc1_texel(b.x, b.y, t);
+    cr = rgtc1_texel(b.z, b.w, t);
+}
+LF_HD Rgb bilinear_rgtc(const void *__restrict__ yp, const void *__restrict__ uvp, int W, int H, float px, float py) {
+    float lum;
+    {
+        const float x0f = floorf(px), y0f = floorf(py);
+        const float fx = px - x0f, fy = py - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
+        x0 = min(max(x0, 0), W - 1);
+        y0 = min(max(y0, 0), H - 1);
+        const int Wb = W >> 2;
+        const float a = rgtc_luma(yp, Wb, x0, y0), b = rgtc_luma(yp, Wb, x1, y0);
+        const float c = rgtc_luma(yp, Wb, x0, y1), d = rgtc_luma(yp, Wb, x1, y1);
+        const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+        lum = fmaf(w11, d, fmaf(w01, c, fmaf(w10, b, w00 * a)));
+    }
+    float cb, cr;
+    {
+        const int Wc = W >> 1, Hc = H >> 1, Wb = W >> 3;
+        const float cx = 0.5f * (px - 0.5f), cy = 0.5f * (py - 0.5f);
+        const float x0f = floorf(cx), y0f = floorf(cy);
+        const float fx = cx - x0f, fy = cy - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        const int x1 = min(max(x0 + 1, 0), Wc - 1), y1 = min(max(y0 + 1, 0), Hc - 1);
+        x0 = min(max(x0, 0), Wc - 1);
+        y0 = min(max(y0, 0), Hc - 1);
+        float ab, ar, bb, br, cb_, cr_, db, dr;
+        rgtc_chroma(uvp, Wb, x0, y0, ab, ar);
+        rgtc_chroma(uvp, Wb, x1, y0, bb, br);
+        rgtc_chroma(uvp, Wb, x0, y1, cb_, cr_);
+        rgtc_chroma(uvp, Wb, x1, y1, db, dr);
+        const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+        cb = fmaf(w11, db, fmaf(w01, cb_, fmaf(w10, bb, w00 * ab))) - 128.0f;
+        cr = fmaf(w11, dr, fmaf(w01, cr_, fmaf(w10, br, w00 * ar))) - 128.0f;
     }
     return {fmaf(1.402f, cr, lum), fmaf(-0.714136f, cr, fmaf(-0.344136f, cb, lum)), fmaf(1.772f, cb, lum)};
 }

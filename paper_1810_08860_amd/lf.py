@@ -12,11 +12,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblf.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
-LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420 = 0, 1, 2, 3
+LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420, LF_IMG_YUV420_RGTC = 0, 1, 2, 3, 4
 LF_GEO_F32, LF_GEO_F16 = 0, 1
 LF_SRC_DEVICE = 1
 
-IMG_FORMATS = {"rgba8": LF_IMG_RGBA8, "rgba16f": LF_IMG_RGBA16F, "rgba32f": LF_IMG_RGBA32F, "yuv420": LF_IMG_YUV420}
+IMG_FORMATS = {"rgba8": LF_IMG_RGBA8, "rgba16f": LF_IMG_RGBA16F, "rgba32f": LF_IMG_RGBA32F, "yuv420": LF_IMG_YUV420,
+               "yuv420_rgtc": LF_IMG_YUV420_RGTC}
 GEO_FORMATS = {"f32": LF_GEO_F32, "f16": LF_GEO_F16}
 
 

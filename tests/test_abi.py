@@ -50,6 +50,8 @@ def _desc(**kw):
     ("src_fov_deg", 180.0, "src_fov"),
     ("disk_radius", 0.0, "disk_radius"),
     ("img_fmt", 7, "img_fmt"),
+    ("img_fmt", 5, "img_fmt"),
+    ("img_fmt", 4, "multiples of 8"),  # RGTC blocks of 4 x 4 chroma samples
     ("geo_fmt", 5, "geo_fmt"),
     ("flags", 8, "flags"),
     ("rgba8", None, "NULL"),

@@ -1,0 +1,99 @@
+"""RGTC source images (the 4x smaller tile-cache form of Sec. 7.2: the YUV420
+planes transcoded to RGTC1 luma and RGTC2 chroma blocks) on the GPU: the render
+against the FP64 oracle sampling its own RGTC blocks of its own YUV420 planes,
+the persistent batch against the per-eye path, block-constant views that must
+render exactly as YUV420 does, and a full-size sampled check."""
+import numpy as np
+import pytest
+
+import lfsynth
+import oracle
+from lfcheck import check_eye, gpu_context, gpu_render, unstable_mask
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx_rgtc(tiny):
+    c = gpu_context(tiny.views, "yuv420_rgtc", "f32")
+    yield c
+    c.close()
+
+
+def test_tiny_full_frame_rgtc_matches_oracle(tiny, tiny_oracle, ctx_rgtc):
+    orc = tiny_oracle.with_yuv420_rgtc()
+    s = check_eye(orc, ctx_rgtc, tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg, 256, 256)
+    print("tiny 256^2 yuv420_rgtc:", s)
+
+
+def test_ragged_eye_rgtc_matches_oracle(tiny, tiny_oracle, ctx_rgtc):
+    orc = tiny_oracle.with_yuv420_rgtc()
+    p, R = lfsynth.poses(41, 1, 0.2)
+    s = check_eye(orc, ctx_rgtc, p[0], R[0], 75.0, 173, 91)
+    print("tiny 173x91 yuv420_rgtc:", s)
+
+
+def test_rgtc_batch_matches_per_eye(tiny, ctx_rgtc):
+    import torch
+    from paper_1810_08860_amd import lf
+    p, R = lfsynth.poses(37, 3, 0.2)
+    eyes, res = [], []
+    for k in range(3):
+        for e in lf.lf_stereo_eyes(p[k], R[k], 0.064):
+            eyes.append((np.array(e.pos), np.array(e.rot).reshape(3, 3)))
+            res.append((136, 120))
+    npx = sum(w * h for w, h in res)
+    ref = torch.zeros(npx * 3, dtype=torch.float32, device="cuda")
+    off = 0
+    for (pp, RR), (w, h) in zip(eyes, res):
+        lf.lf_render(ctx_rgtc, [(pp, RR)], 90.0, (w, h), ref[off:off + 3 * w * h])
+        off += 3 * w * h
+    got = torch.full((npx * 3,), -5.0, dtype=torch.float32, device="cuda")
+    lf.lf_render_batch(ctx_rgtc, eyes, 90.0, np.array(res, np.int32), got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+
+
+def test_block_constant_views_render_as_yuv420(tiny):
+    """Views constant over 8 x 8 texel blocks are coded exactly by RGTC, so
+    the GPU's RGTC render equals its YUV420 render up to FP32 rounding of the
+    decode (1e-5); a block read at a wrong address or a swapped chroma block
+    moves colours by far more."""
+    V = tiny.views
+    n, H, W = V.rgba8.shape[:3]
+    rng = np.random.default_rng(10)
+    cols = rng.integers(0, 256, (n, H // 8, W // 8, 3)).astype(np.uint8)
+    img = np.zeros_like(V.rgba8)
+    img[..., :3] = np.repeat(np.repeat(cols, 8, axis=1), 8, axis=2)
+    img[..., 3] = 255
+    from paper_1810_08860_amd import lf
+    ctxs = [lf.lf_load_views(V.centres, V.rot, img, V.zdepth, V.src_fov_deg, V.disk_radius, img_fmt=f, geo_fmt="f32")
+            for f in ("yuv420", "yuv420_rgtc")]
+    eye = [(tiny.head_pos[0], tiny.head_rot[0])]
+    a, b = [gpu_render(c, eye, tiny.hfov_deg, [(200, 184)])[0] for c in ctxs]
+    for c in ctxs:
+        c.close()
+    assert np.abs(a[0] - b[0]).max() <= 1e-5
+    assert np.array_equal(a[2], b[2])
+
+
+def test_full_size_rgtc_sampled_parity():
+    """Full light field in RGTC with FP32 geometry: sampled pixels of one
+    stereo frame against the oracle on the same blocks."""
+    w = lfsynth.make_workload("full", seed=0, n_poses=1)
+    V = w.views
+    orc = oracle.OracleViews.from_views(V).with_yuv420_rgtc()
+    ctx = gpu_context(V, "yuv420_rgtc", "f32")
+    from paper_1810_08860_amd import lf
+    eyes = [(np.array(e.pos), np.array(e.rot).reshape(3, 3))
+            for e in lf.lf_stereo_eyes(w.head_pos[0], w.head_rot[0], 0.064)]
+    outs = gpu_render(ctx, eyes, 100.0, [(1440, 1600)] * 2)
+    ctx.close()
+    rng = np.random.default_rng(11)
+    for (pos, rot), (rgb, _, _) in zip(eyes, outs):
+        idx = np.sort(rng.choice(1440 * 1600, 1500, replace=False))
+        ref = oracle.render(orc, pos, rot, 100.0, 1440, 1600, idx)["rgb"]
+        bad = unstable_mask(orc, pos, rot, 100.0, 1440, 1600, idx, ref)
+        err = np.abs(rgb[idx] - ref).max(1)
+        print(f"full rgtc: max err stable {err[~bad].max():.3g}, unstable {bad.mean() * 100:.2f}%")
+        assert bad.mean() < 0.005 and err[~bad].max() <= 1e-4
