@@ -41,6 +41,7 @@ class _Views(ctypes.Structure):
         ("mode", ctypes.c_int32), ("threads", ctypes.c_int32),
         ("yuv_y", ctypes.c_void_p), ("yuv_uv", ctypes.c_void_p),
         ("rgtc_y", ctypes.c_void_p), ("rgtc_uv", ctypes.c_void_p),
+        ("resident", ctypes.c_void_p), ("page", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ def lib():
         L.orc_yuv420_encode.argtypes = [i32, i32, i32, vp, vp, vp]
         L.orc_rgtc_encode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
         L.orc_rgtc_decode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
+        L.orc_visible_tiles.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, i32, vp]
         L.orc_basis.restype = f64
         L.orc_views_size.restype = i32
         L.orc_rec_size.restype = i32
@@ -136,7 +138,7 @@ class OracleViews:
         self.s = _Views(n, w, h, m, float(src_fov_deg), _p(self.centres), _p(self.rot), _p(self.rgba8),
                         _p(self.zdepth), _p(self.zrange), float(disk_radius),
                         None if self.disk_ext is None else _p(self.disk_ext),
-                        1 if mode == "brute" else 0, int(threads), None, None, None, None)
+                        1 if mode == "brute" else 0, int(threads), None, None, None, None, None, 0)
 
     @classmethod
     def from_views(cls, v, mode="traversal", threads=0, disk_radius=None, disk_ext=None):
@@ -179,6 +181,22 @@ class OracleViews:
         o = self.with_yuv420()
         o.rgtc_y, o.rgtc_uv = rgtc_encode(o.yuv_y, o.yuv_uv)
         o.s.rgtc_y, o.s.rgtc_uv = _p(o.rgtc_y), _p(o.rgtc_uv)
+        return o
+
+    def with_residency(self, resident, page=64):
+        """Tile streaming (Sec. 4.2, Sec. 7.2): only the image tiles marked in
+        resident [n][H/page][W/page] can be sampled; a view whose sample for a
+        ray needs another tile is left out for that ray. None: every tile."""
+        o = self.with_disk_radius(self.s.disk_radius)
+        if resident is None:
+            o.resident = None
+            o.s.resident, o.s.page = None, 0
+            return o
+        H, W = self.rgba8.shape[1:3]
+        if H % page or W % page:
+            raise ValueError("image sizes must be multiples of the tile size")
+        o.resident = np.ascontiguousarray(resident, np.uint8).reshape(self.n, H // page, W // page)
+        o.s.resident, o.s.page = _p(o.resident), int(page)
         return o
 
     def with_mode(self, mode):
@@ -239,6 +257,18 @@ def render(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, cap: int = 0, ji
         pxy = pxy + np.asarray(jitter, np.float64)
     o, e = eye_rays(pos, rot, hfov_deg, W, H, pxy)
     return render_rays(ov, o, e, cap)
+
+
+def visible_tiles(ov: OracleViews, pos, rot, hfov_deg, W, H, page=64, idx=None):
+    """The image tiles (n, H_src/page, W_src/page) that the eye's pixel-centre
+    rays sample (every tap of every contributing view's bilinear sample)."""
+    Hs, Ws = ov.rgba8.shape[1:3]
+    if Hs % page or Ws % page:
+        raise ValueError("image sizes must be multiples of the tile size")
+    o, e = eye_rays(pos, rot, hfov_deg, W, H, pixel_centres(W, H, idx))
+    vis = np.zeros((ov.n, Hs // page, Ws // page), np.uint8)
+    lib().orc_visible_tiles(ctypes.byref(ov.s), o.shape[0], _p(o), _p(e), int(page), _p(vis))
+    return vis
 
 
 def render_reference(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, ss: int = 4, disk_scale: float = 2.0):

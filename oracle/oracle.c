@@ -73,6 +73,8 @@ typedef struct {
     const uint8_t *yuv_uv;   /* [n][img_h/2][img_w/2][2] chroma (Cb, Cr) at half resolution */
     const uint8_t *rgtc_y;   /* [n][img_h/4][img_w/4][8] luma as RGTC1 blocks, or NULL: sample yuv_y / rgba8 */
     const uint8_t *rgtc_uv;  /* [n][img_h/8][img_w/8][16] chroma as RGTC2 blocks (Cb block, then Cr block) */
+    const uint8_t *resident; /* [n][img_h/page][img_w/page] 1 = image tile in the tile cache, or NULL: all */
+    int32_t page;            /* image tile size in texels (with resident) */
 } orc_views;
 
 /* Per-ray outputs. Lists are ascending view ids padded with -1. */
@@ -518,6 +520,31 @@ void orc_sample(const orc_views *V, int32_t i, double Xs, double Ys, double rgb[
     }
 }
 
+/*
+ * Tile streaming (Sec. 4.2, tile streaming and caching; Sec. 7.2): the images
+ * are cut into page x page tiles and only the tiles in the cache can be
+ * sampled. Reading: a view whose bilinear sample for a ray needs a tile that
+ * is not in the cache contributes nothing to that ray (left out of both sums
+ * of Eq. 2, like a missed mesh). The taps of a sample are the four texels
+ * orc_sample interpolates (clamped to the image), so a tile is needed iff one
+ * of them lies in it, whatever its weight.
+ */
+static void sample_tap_tiles(const orc_views *V, double Xs, double Ys, int64_t tiles[4]) {
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    const int32_t W = V->img_w, H = V->img_h, P = V->page;
+    const double px = (Xs / ts + 1.0) * 0.5 * W - 0.5, py = (1.0 - Ys / ts) * 0.5 * H - 0.5;
+    int64_t x0 = (int64_t)floor(px), y0 = (int64_t)floor(py), x1 = x0 + 1, y1 = y0 + 1;
+    if (x0 < 0) x0 = 0; if (x0 > W - 1) x0 = W - 1;
+    if (x1 < 0) x1 = 0; if (x1 > W - 1) x1 = W - 1;
+    if (y0 < 0) y0 = 0; if (y0 > H - 1) y0 = H - 1;
+    if (y1 < 0) y1 = 0; if (y1 > H - 1) y1 = H - 1;
+    const int64_t tw = W / P;
+    tiles[0] = (y0 / P) * tw + x0 / P;
+    tiles[1] = (y0 / P) * tw + x1 / P;
+    tiles[2] = (y1 / P) * tw + x0 / P;
+    tiles[3] = (y1 / P) * tw + x1 / P;
+}
+
 /* One view's full record for one ray (used by the per-ray loop and by tests). */
 typedef struct {
     double a, u, v, rho, t_hit, Xs, Ys, rgb[3];
@@ -542,7 +569,46 @@ void orc_view_ray(const orc_views *V, int32_t i, const double o[3], const double
     to_local(R, P, Pl);
     r->Xs = Pl[0] / Pl[2];
     r->Ys = Pl[1] / Pl[2];
+    if (V->resident) {
+        int64_t tl[4];
+        sample_tap_tiles(V, r->Xs, r->Ys, tl);
+        const int64_t tpv = (int64_t)(V->img_w / V->page) * (V->img_h / V->page);
+        for (int k = 0; k < 4; ++k)
+            if (!V->resident[(int64_t)i * tpv + tl[k]]) {
+                r->hit = 0; /* the view is left out for this ray */
+                return;
+            }
+    }
     orc_sample(V, i, r->Xs, r->Ys, r->rgb);
+}
+
+/*
+ * The image tiles a set of rays samples: vis[i][tile] = 1 for every tile
+ * holding a tap of a sample that view i contributes to one of the rays
+ * (ignoring any residency table), else left as it is.
+ */
+void orc_visible_tiles(const orc_views *V, int64_t n_rays, const double *o, const double *e, int32_t page,
+                       uint8_t *vis) {
+    orc_views A = *V;
+    A.resident = NULL;
+    A.page = page;
+    const int64_t tpv = (int64_t)(V->img_w / page) * (V->img_h / page);
+#ifdef _OPENMP
+    if (V->threads > 0) omp_set_num_threads(V->threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_rays; ++k)
+        for (int32_t i = 0; i < A.n; ++i) {
+            orc_rec r;
+            orc_view_ray(&A, i, o + 3 * k, e + 3 * k, &r);
+            if (!r.hit) continue;
+            int64_t tl[4];
+            sample_tap_tiles(&A, r.Xs, r.Ys, tl);
+            for (int q = 0; q < 4; ++q) {
+#pragma omp atomic write
+                vis[(int64_t)i * tpv + tl[q]] = 1;
+            }
+        }
 }
 
 static void list_put(int32_t *list, int32_t cap, int32_t *cnt, int32_t id) {
