@@ -75,7 +75,14 @@ enum {
  * e1); the render decodes the texels it reads from their blocks and samples
  * as for YUV420. It needs image sizes that are multiples of 8. All sampling
  * and blending arithmetic is FP32 in every format. */
-enum { LF_IMG_RGBA8 = 0, LF_IMG_RGBA16F = 1, LF_IMG_RGBA32F = 2, LF_IMG_YUV420 = 3, LF_IMG_YUV420_RGTC = 4 };
+enum {
+    LF_IMG_RGBA8 = 0,
+    LF_IMG_RGBA16F = 1,
+    LF_IMG_RGBA32F = 2,
+    LF_IMG_YUV420 = 3,
+    LF_IMG_YUV420_RGTC = 4,
+    LF_IMG_PAGED_RGBA8 = 5  /* RGBA8 tiles streamed into a device tile cache: see lf_cache_config */
+};
 
 /* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex, in
  * FP32 or FP16, packed per mesh cell. Intersection arithmetic is FP32. */
@@ -185,6 +192,57 @@ int lf_set_view_mask(lf_ctx *c, const uint8_t *enabled);
  * in Eq. (2). mask_out: host uint8 [n_views].
  */
 int lf_two_level_mask(const lf_ctx *c, int32_t n_fine, const uint8_t *fine_available, uint8_t *mask_out);
+
+/*
+ * Tile streaming and caching (Sec. 4.2, tile streaming and caching; Sec. 7.2).
+ * A context loaded with LF_IMG_PAGED_RGBA8 (image sizes multiples of 64) keeps
+ * every image cut into 64 x 64-texel tiles in pinned host memory (the store
+ * the paper decodes its tiles from) and samples them only from a device cache
+ * of pages, one tile per 16 KB page, found through a per-view page table. A
+ * view whose bilinear sample for a ray needs a tile that is not in the cache
+ * contributes nothing to that ray (left out of both sums of Eq. 2); such
+ * samples are counted (lf_cache_page_misses).
+ *
+ * lf_cache_config: (re)creates the cache with `pages` pages, emptying it.
+ * Views [first_resident, n_views) (the coarse level of lf_two_level_mask;
+ * n_views for none) are loaded into the first pages at once and never
+ * evicted, so pages must exceed their tile count. Synchronous.
+ * Errors: LF_ESTATE if the images are not paged; LF_EINVAL for sizes.
+ */
+int lf_cache_config(lf_ctx *c, int64_t pages, int32_t first_resident);
+
+/*
+ * One frame of tile streaming for the given eyes (arguments as lf_render):
+ *   1. a visibility pass (the render's own disk tests and mesh walks over the
+ *      fine views [0, first_resident), no sampling) marks every image tile
+ *      holding one of the four taps of a sample;
+ *   2. visible tiles not in the cache are copied in from host memory, view
+ *      by view in index order, at most `budget` tiles per call (the paper's
+ *      per-frame decode budget), each into the next page in FIFO order,
+ *      evicting that page's tile; a page filled by this call is not reused
+ *      by it;
+ *   3. a fine view is available iff every tile it showed is in the cache,
+ *      and the view mask (lf_set_view_mask) becomes the available fine views
+ *      plus, with a coarse level, lf_two_level_mask's coarse fill-in (without
+ *      one, the available views).
+ * A following render of the same eyes then samples only cached tiles.
+ * fine_available: host uint8 [first_resident] or NULL; visible_out: host uint8
+ * [n_views][tiles] (the visibility pass, 1 = shown) or NULL; stats: host
+ * int64 [5] or NULL = visible tiles, of them already cached, tiles copied in,
+ * tiles evicted, fine views unavailable. Synchronous on hip_stream (waits for
+ * the copies). Errors: LF_ESTATE without lf_cache_config or paged images;
+ * LF_EINVAL as lf_render or for budget < 0.
+ */
+int lf_cache_update(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    int32_t budget, uint8_t *fine_available, uint8_t *visible_out, int64_t *stats,
+                    void *hip_stream);
+
+/* Which image tiles are in the cache: host uint8 [n_views][tiles], 1 = cached. */
+int lf_cache_resident(const lf_ctx *c, uint8_t *resident_out);
+
+/* Samples left out since the last call because a tap's tile was not in the
+ * cache (then resets the count). Synchronous. */
+int lf_cache_page_misses(lf_ctx *c, uint64_t *misses);
 
 /* Pixel reconstruction basis of the prefilter (one axis; the 2-D basis is the
  * product of two): box, 1 on |d| <= 1/2; Lanczos-2, sinc(d) sinc(d/2) on

@@ -64,6 +64,7 @@ int64_t img_view_bytes(int fmt, int64_t W, int64_t H) {
     case LF_IMG_RGBA16F: return 8 * W * H;
     case LF_IMG_RGBA32F: return 16 * W * H;
     case LF_IMG_YUV420: return W * H;
+    case LF_IMG_PAGED_RGBA8: return (W / kPage) * (H / kPage) * 4;  // the view's page-table row
     default: return (W / 4) * (H / 4) * 8;
     }
 }
@@ -90,6 +91,26 @@ struct lf_ctx {
     float4 *ext_inv = nullptr;  // device [n]: oval disks' inverse extents (null: circles of radius R)
     float *vrad = nullptr;      // device [n]: oval disks' largest extent (culling bound)
     uint8_t *vmask = nullptr;   // device [n]: views taking part in renders (lf_set_view_mask)
+    // paged images (tile streaming): every image tile in pinned host memory,
+    // a cache of device pages filled on demand (lf_cache_config / lf_cache_update);
+    // img is then the device page table [n][tiles]
+    struct Cache {
+        uint32_t *host = nullptr;           // pinned [n][tiles][kPage * kPage] RGBA8
+        int32_t tiles_x = 0, tiles_y = 0, tpv = 0;
+        char *pool = nullptr;               // device pages, 16 KB each
+        int64_t pages = 0, fixed = 0;       // pages; the first `fixed` hold the resident views
+        int64_t next = 0;                   // FIFO position in [fixed, pages)
+        int32_t first_resident = 0;         // views [first_resident, n) stay in the cache
+        std::vector<int32_t> pt;            // host mirror of the page table
+        std::vector<int64_t> owner;         // page -> tile key (view * tpv + tile), -1 = free
+        std::vector<int64_t> stamp;         // page -> update call that filled it
+        int64_t calls = 0;
+        uint8_t *vis_dev = nullptr;         // visibility pass output [n][tiles]
+        std::vector<uint8_t> vis;
+        char *stage_host = nullptr, *stage_dev = nullptr;  // patches, pages, tiles of one update
+        size_t stage_bytes = 0;
+        unsigned int *miss_dev = nullptr;   // samples left out for a missing page
+    } cache;
     std::vector<double> h_rad;  // host [n]: each disk's largest extent (R for circles)
     std::vector<double> h_vt;  // host copy of the view table (eye validation)
     // per-render scratch: eye-view table and tile lists, grown on demand
@@ -241,6 +262,11 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.invR = (float)(1.0 / R);
     // R is the context's radius times the call's disk scale; oval extents scale alike
     a.ext_inv = c->ext_inv;
+    a.pool = c->cache.pool;
+    a.tiles_x = c->cache.tiles_x;
+    a.tiles_y = c->cache.tiles_y;
+    a.vis = c->cache.vis_dev;
+    a.page_miss = c->cache.miss_dev;
     a.ext_inv_scale = (float)(c->R / R);
     a.scale = 1.0f;
     return a;
@@ -310,8 +336,11 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (!(d->src_fov_deg > 0.0 && d->src_fov_deg < 180.0)) return fail(LF_EINVAL, "src_fov_deg must be in (0,180)");
     if (!(d->disk_radius > 0.0) || !std::isfinite(d->disk_radius)) return fail(LF_EINVAL, "disk_radius must be > 0");
     if (!d->centres || !d->rot || !d->rgba8 || !d->zdepth) return fail(LF_EINVAL, "NULL data pointer");
-    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_YUV420_RGTC)
+    if (d->img_fmt < LF_IMG_RGBA8 || d->img_fmt > LF_IMG_PAGED_RGBA8)
         return fail(LF_EINVAL, "unknown img_fmt %d", d->img_fmt);
+    if (d->img_fmt == LF_IMG_PAGED_RGBA8 && (d->img_w % kPage || d->img_h % kPage))
+        return fail(LF_EINVAL, "paged images need sizes that are multiples of %d (got %dx%d)", kPage, d->img_w,
+                    d->img_h);
     if (d->img_fmt == LF_IMG_YUV420 && (d->img_w % 2 || d->img_h % 2))
         return fail(LF_EINVAL, "YUV420 needs even image sizes (got %dx%d)", d->img_w, d->img_h);
     if (d->img_fmt == LF_IMG_YUV420_RGTC && (d->img_w % 8 || d->img_h % 8))
@@ -413,6 +442,32 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (rgba_owned) (void)hipFree(rgba_dev);
         if (e != hipSuccess) return bail(hip_fail(e, "YUV420 conversion"));
+    } else if (d->img_fmt == LF_IMG_PAGED_RGBA8) {
+        // tiles cut on the device, kept in pinned host memory; the device holds
+        // the page table (every tile absent until lf_cache_config / lf_cache_update)
+        if (((uintptr_t)rgba_dev & 15) != 0) {
+            if (rgba_owned) (void)hipFree(rgba_dev);
+            return bail(fail(LF_EINVAL, "paged images: the device RGBA8 source must be 16-byte aligned"));
+        }
+        lf_ctx::Cache &K = c->cache;
+        K.tiles_x = d->img_w / kPage;
+        K.tiles_y = d->img_h / kPage;
+        K.tpv = K.tiles_x * K.tiles_y;
+        void *tiled = nullptr;
+        if ((e = hipMalloc(&tiled, n_tex * 4)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&K.host, n_tex * 4, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&c->img, sizeof(int32_t) * (size_t)n * K.tpv)) != hipSuccess) {
+            if (tiled) (void)hipFree(tiled);
+            if (rgba_owned) (void)hipFree(rgba_dev);
+            return bail(hip_fail(e, "allocating paged images"));
+        }
+        e = launch_tile_images((const uint32_t *)rgba_dev, (uint32_t *)tiled, n, d->img_w, d->img_h, 0);
+        if (e == hipSuccess) e = hipMemcpy(K.host, tiled, n_tex * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemset(c->img, 0xff, sizeof(int32_t) * (size_t)n * K.tpv);
+        (void)hipFree(tiled);
+        if (rgba_owned) (void)hipFree(rgba_dev);
+        if (e != hipSuccess) return bail(hip_fail(e, "tiling paged images"));
+        K.pt.assign((size_t)n * K.tpv, -1);
     } else if (d->img_fmt == LF_IMG_YUV420_RGTC) {
         // RGBA8 -> YUV420 planes (scratch) -> RGTC blocks
         uint8_t *yp = nullptr, *uvp = nullptr;
@@ -590,6 +645,200 @@ int lf_two_level_mask(const lf_ctx *c, int32_t n_fine, const uint8_t *fine_avail
         }
         mask_out[j] = need;
     }
+    return LF_OK;
+}
+
+int lf_cache_config(lf_ctx *c, int64_t pages, int32_t first_resident) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (c->img_fmt != LF_IMG_PAGED_RGBA8) return fail(LF_ESTATE, "the context's images are not paged");
+    lf_ctx::Cache &K = c->cache;
+    if (first_resident < 0 || first_resident > c->n)
+        return fail(LF_EINVAL, "first_resident must be in [0, n_views] (got %d)", first_resident);
+    const int64_t fixed = (int64_t)(c->n - first_resident) * K.tpv;
+    if (pages <= fixed || pages > ((int64_t)1 << 26))
+        return fail(LF_EINVAL, "pages must exceed the %lld pages of the resident views and be at most 2^26 (got %lld)",
+                    (long long)fixed, (long long)pages);
+    LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (K.pool) {
+        LF_HIP(hipFree(K.pool), "hipFree");
+        K.pool = nullptr;
+    }
+    const size_t page_bytes = (size_t)kPage * kPage * 4;
+    LF_HIP(hipMalloc((void **)&K.pool, page_bytes * pages), "hipMalloc(tile cache)");
+    if (!K.vis_dev) LF_HIP(hipMalloc((void **)&K.vis_dev, (size_t)c->n * K.tpv), "hipMalloc(visibility)");
+    if (!K.miss_dev) {
+        LF_HIP(hipMalloc((void **)&K.miss_dev, sizeof(unsigned int)), "hipMalloc(page misses)");
+        LF_HIP(hipMemset(K.miss_dev, 0, sizeof(unsigned int)), "hipMemset");
+    }
+    K.pages = pages;
+    K.fixed = fixed;
+    K.next = fixed;
+    K.first_resident = first_resident;
+    K.owner.assign((size_t)pages, -1);
+    K.stamp.assign((size_t)pages, -1);
+    std::fill(K.pt.begin(), K.pt.end(), -1);
+    // the resident views' tiles take the first pages, in order (contiguous in the host store)
+    for (int64_t k = 0; k < fixed; ++k) {
+        const int64_t key = (int64_t)first_resident * K.tpv + k;
+        K.pt[(size_t)key] = (int32_t)k;
+        K.owner[(size_t)k] = key;
+    }
+    if (fixed > 0)
+        LF_HIP(hipMemcpy(K.pool, K.host + (size_t)first_resident * K.tpv * kPage * kPage, page_bytes * fixed,
+                         hipMemcpyHostToDevice),
+               "copy resident tiles");
+    LF_HIP(hipMemcpy(c->img, K.pt.data(), sizeof(int32_t) * K.pt.size(), hipMemcpyHostToDevice), "copy page table");
+    return LF_OK;
+}
+
+int lf_cache_update(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                    int32_t budget, uint8_t *fine_available, uint8_t *visible_out, int64_t *stats,
+                    void *hip_stream) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (c->img_fmt != LF_IMG_PAGED_RGBA8) return fail(LF_ESTATE, "the context's images are not paged");
+    lf_ctx::Cache &K = c->cache;
+    if (!K.pool) return fail(LF_ESTATE, "lf_cache_config has not been called");
+    if (budget < 0) return fail(LF_EINVAL, "budget must be >= 0 (got %d)", budget);
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int32_t n = c->n, nf = K.first_resident;
+    const size_t page_bytes = (size_t)kPage * kPage * 4;
+    ++K.calls;
+
+    // 1. visibility pass over the fine views (the resident ones need nothing)
+    std::vector<uint8_t> m((size_t)n, 0);
+    for (int32_t v = 0; v < nf; ++v) m[(size_t)v] = 1;
+    LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    LF_HIP(hipMemcpy(c->vmask, m.data(), (size_t)n, hipMemcpyHostToDevice), "copy view mask");
+    LF_HIP(hipMemsetAsync(K.vis_dev, 0, (size_t)n * K.tpv, s), "hipMemsetAsync");
+    rc = render_impl(c, eyes, n_eyes, hfov_deg, res, nullptr, nullptr, nullptr, MODE_VISIBILITY, c->R, 0.5f, 0.5f,
+                     1.0f, 0, s);
+    if (rc) return rc;
+    K.vis.resize((size_t)n * K.tpv);
+    LF_HIP(hipMemcpyAsync(K.vis.data(), K.vis_dev, K.vis.size(), hipMemcpyDeviceToHost, s), "copy visibility");
+    LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+
+    // 2. FIFO: fill pages with visible tiles not in the cache, view by view, up
+    // to the budget; a page filled by this call is never taken again by it
+    int64_t visible = 0, hits = 0, evicted = 0;
+    std::vector<int64_t> touched;  // page-table entries changed by this call
+    std::vector<int32_t> slots;
+    std::vector<int64_t> keys;
+    const int64_t ring = K.pages - K.fixed;
+    for (int32_t v = 0; v < nf; ++v)
+        for (int32_t t = 0; t < K.tpv; ++t) {
+            const int64_t key = (int64_t)v * K.tpv + t;
+            if (!K.vis[(size_t)key]) continue;
+            ++visible;
+            if (K.pt[(size_t)key] >= 0) {
+                ++hits;
+                continue;
+            }
+            if ((int64_t)slots.size() >= budget || (int64_t)slots.size() >= ring) continue;
+            const int64_t pg = K.next;
+            if (K.stamp[(size_t)pg] == K.calls) continue;  // the ring is full of this call's tiles
+            K.next = K.next + 1 < K.pages ? K.next + 1 : K.fixed;
+            const int64_t old = K.owner[(size_t)pg];
+            if (old >= 0) {
+                K.pt[(size_t)old] = -1;
+                touched.push_back(old);
+                ++evicted;
+            }
+            K.owner[(size_t)pg] = key;
+            K.stamp[(size_t)pg] = K.calls;
+            K.pt[(size_t)key] = (int32_t)pg;
+            touched.push_back(key);
+            slots.push_back((int32_t)pg);
+            keys.push_back(key);
+        }
+    // each changed entry once, with its final value (an entry evicted and
+    // filled again by this call appears twice in `touched`)
+    std::sort(touched.begin(), touched.end());
+    touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+    std::vector<int2> patch(touched.size());
+    for (size_t k = 0; k < touched.size(); ++k) patch[k] = make_int2((int)touched[k], K.pt[(size_t)touched[k]]);
+
+    // 3. one upload: patches, pages, then the tiles; applied by one kernel
+    const size_t off_slot = ((patch.size() * sizeof(int2)) + 15) & ~(size_t)15;
+    const size_t off_tiles = (off_slot + slots.size() * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t need = off_tiles + slots.size() * page_bytes;
+    if (need > K.stage_bytes) {
+        if (K.stage_host) (void)hipHostFree(K.stage_host);
+        if (K.stage_dev) (void)hipFree(K.stage_dev);
+        K.stage_host = K.stage_dev = nullptr;
+        K.stage_bytes = 0;
+        const size_t want = std::max(need, (size_t)1 << 20);
+        LF_HIP(hipHostMalloc((void **)&K.stage_host, want, hipHostMallocDefault), "hipHostMalloc(tile staging)");
+        LF_HIP(hipMalloc((void **)&K.stage_dev, want), "hipMalloc(tile staging)");
+        K.stage_bytes = want;
+    }
+    if (!patch.empty()) {
+        std::memcpy(K.stage_host, patch.data(), patch.size() * sizeof(int2));
+        std::memcpy(K.stage_host + off_slot, slots.data(), slots.size() * sizeof(int32_t));
+        for (size_t k = 0; k < keys.size(); ++k)
+            std::memcpy(K.stage_host + off_tiles + k * page_bytes, K.host + (size_t)keys[k] * kPage * kPage, page_bytes);
+        LF_HIP(hipMemcpyAsync(K.stage_dev, K.stage_host, need, hipMemcpyHostToDevice, s), "copy tiles");
+        LF_HIP(launch_cache_apply((int32_t *)c->img, (const int2 *)K.stage_dev, (int32_t)patch.size(),
+                                  (const uint4 *)(K.stage_dev + off_tiles), (const int32_t *)(K.stage_dev + off_slot),
+                                  (int32_t)slots.size(), K.pool, s),
+               "k_cache_apply launch");
+    }
+
+    // 4. a fine view is available iff every tile it showed is in the cache;
+    // the view mask takes the available fine views and the coarse level's fill-in
+    std::vector<uint8_t> avail((size_t)std::max(nf, 1), 1);
+    int64_t missing_views = 0;
+    for (int32_t v = 0; v < nf; ++v) {
+        for (int32_t t = 0; t < K.tpv && avail[(size_t)v]; ++t) {
+            const size_t key = (size_t)v * K.tpv + t;
+            if (K.vis[key] && K.pt[key] < 0) avail[(size_t)v] = 0;
+        }
+        missing_views += !avail[(size_t)v];
+    }
+    if (nf < n) {
+        if (nf > 0) {
+            rc = lf_two_level_mask(c, nf, avail.data(), m.data());
+            if (rc) return rc;
+        } else {
+            std::fill(m.begin(), m.end(), 1);
+        }
+    } else {
+        for (int32_t v = 0; v < n; ++v) m[(size_t)v] = avail[(size_t)v];
+    }
+    LF_HIP(hipMemcpyAsync(c->vmask, m.data(), (size_t)n, hipMemcpyHostToDevice, s), "copy view mask");
+    LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (fine_available)
+        for (int32_t v = 0; v < nf; ++v) fine_available[v] = avail[(size_t)v];
+    if (visible_out) std::memcpy(visible_out, K.vis.data(), K.vis.size());
+    if (stats) {
+        stats[0] = visible;
+        stats[1] = hits;
+        stats[2] = (int64_t)slots.size();
+        stats[3] = evicted;
+        stats[4] = missing_views;
+    }
+    return LF_OK;
+}
+
+int lf_cache_resident(const lf_ctx *c, uint8_t *resident_out) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (c->img_fmt != LF_IMG_PAGED_RGBA8) return fail(LF_ESTATE, "the context's images are not paged");
+    if (!resident_out) return fail(LF_EINVAL, "resident_out must not be NULL");
+    for (size_t k = 0; k < c->cache.pt.size(); ++k) resident_out[k] = c->cache.pt[k] >= 0;
+    return LF_OK;
+}
+
+int lf_cache_page_misses(lf_ctx *c, uint64_t *misses) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!misses) return fail(LF_EINVAL, "misses must not be NULL");
+    *misses = 0;
+    if (!c->cache.miss_dev) return LF_OK;
+    unsigned int m = 0;
+    LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    LF_HIP(hipMemcpy(&m, c->cache.miss_dev, sizeof m, hipMemcpyDeviceToHost), "copy page misses");
+    LF_HIP(hipMemset(c->cache.miss_dev, 0, sizeof(unsigned int)), "hipMemset");
+    *misses = m;
     return LF_OK;
 }
 
@@ -1010,6 +1259,12 @@ void lf_free(lf_ctx *c) {
     if (c->vrad) (void)hipFree(c->vrad);
     if (c->vmask) (void)hipFree(c->vmask);
     if (c->scratch) (void)hipFree(c->scratch);
+    if (c->cache.host) (void)hipHostFree(c->cache.host);
+    if (c->cache.pool) (void)hipFree(c->cache.pool);
+    if (c->cache.vis_dev) (void)hipFree(c->cache.vis_dev);
+    if (c->cache.stage_dev) (void)hipFree(c->cache.stage_dev);
+    if (c->cache.stage_host) (void)hipHostFree(c->cache.stage_host);
+    if (c->cache.miss_dev) (void)hipFree(c->cache.miss_dev);
     for (auto &t : c->timed) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);

@@ -14,6 +14,8 @@ constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
 constexpr int kQueueStride = 32;       // batch queue counters: one per XCD, 128 bytes apart
 constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
 constexpr int kSuperCap = 256;         // super-tile survivor list capacity (exact beyond: every view)
+constexpr int kPage = 64;              // image tile (cache page) side in texels, paged images
+constexpr int kPageShift = 6;
 
 inline int num_blocks(int M) { return (M - 1 + kBlk - 1) / kBlk; }
 
@@ -104,7 +106,7 @@ struct BatchArgs {
     int32_t q_len[kXcds];         // slots of each XCD's queue (one band of every eye)
 };
 
-enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3, MODE_PREFILTER = 4 };
+enum { MODE_RENDER = 0, MODE_SUBPIXEL = 1, MODE_DEBUG = 2, MODE_STATS = 3, MODE_PREFILTER = 4, MODE_VISIBILITY = 5 };
 enum { DISK_CIRCLE = 0, DISK_OVAL = 1 };
 
 struct RenderArgs {
@@ -131,6 +133,13 @@ struct RenderArgs {
     int32_t dbg_cap;
     // work counters: pixels, disk tests, candidates, mesh cells visited, samples
     unsigned long long *stats;
+    // paged images: kPage x kPage-texel RGBA8 tiles in a cache of pages (pool,
+    // 16 KB each); a view's record points at its row of the page table (page
+    // of each image tile, row-major, -1 = not in the cache)
+    const char *pool;
+    int32_t tiles_x, tiles_y;       // image tiles per row / column
+    uint8_t *vis;                   // visibility pass: [n_views][tiles] set to 1 where a tap lies
+    unsigned int *page_miss;        // paged renders: samples left out for a tile not in the cache
 };
 
 // Record an error message for lf_last_error and return code (lf_api.cpp).
@@ -160,6 +169,11 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
                         hipEvent_t ev_a, hipEvent_t ev_b);
 // occupancy of the persistent render kernel (oval: the oval-disk form)
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu);
+// RGBA8 [n][H][W] device images -> kPage x kPage tiles, [n][tiles_y][tiles_x][kPage][kPage]
+hipError_t launch_tile_images(const uint32_t *src, uint32_t *dst, int32_t n, int32_t W, int32_t H, hipStream_t s);
+// tile cache update: pt[patch[k].x] = patch[k].y for k < n_patch, then staged tile k (16 KB) -> page slot[k]
+hipError_t launch_cache_apply(int32_t *pt, const int2 *patch, int32_t n_patch, const uint4 *staged,
+                              const int32_t *slot, int32_t n_tiles, char *pool, hipStream_t s);
 // out[p] /= wsum[p] (0 where wsum[p] == 0), p < n pixels of RGB
 hipError_t launch_prefilter_finish(float *out_rgb, const float *wsum, int64_t n, hipStream_t s);
 

@@ -574,7 +574,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     const uint32_t *tl = reinterpret_cast<const uint32_t *>(a.tile_list + (int64_t)tile * kListCap);
 
     float accr = 0.0f, accg = 0.0f, accb = 0.0f, ws = 0.0f;
-    int nc = 0, nh = 0, n_tests = 0, n_cells = 0;
+    int nc = 0, nh = 0, n_tests = 0, n_cells = 0, n_miss = 0;
     if (inside) {
         for (int c = 0; c < total; ++c) {
             int vid = c;
@@ -606,10 +606,23 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             }
             const float Xs = fmaf(wh, rv.Dx, rv.Vx), Ys = fmaf(wh, rv.Dy, rv.Vy);
             const float tpx = fmaf(Xs, a.sW, a.cW), tpy = fmaf(-Ys, a.sH, a.cH);
+            if constexpr (MODE == MODE_VISIBILITY) {
+                mark_taps(a.vis + (int64_t)v.view * (a.tiles_x * a.tiles_y), a.tiles_x, a.img_w, a.img_h, tpx, tpy);
+                continue;
+            }
             Rgb col;
-            if constexpr (IMG == 3) col = bilinear_yuv(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
-            else if constexpr (IMG == 4) col = bilinear_rgtc(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
-            else col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
+            if constexpr (IMG == 5) {
+                if (!bilinear_paged(v.img, a.pool, a.tiles_x, a.img_w, a.img_h, tpx, tpy, col)) {
+                    ++n_miss;
+                    continue;
+                }
+            } else if constexpr (IMG == 3) {
+                col = bilinear_yuv(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
+            } else if constexpr (IMG == 4) {
+                col = bilinear_rgtc(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
+            } else {
+                col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
+            }
             accr = fmaf(rv.rho, col.r, accr);
             accg = fmaf(rv.rho, col.g, accg);
             accb = fmaf(rv.rho, col.b, accb);
@@ -617,6 +630,8 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             ++nh;
         }
     }
+    if (IMG == 5 && MODE != MODE_VISIBILITY && n_miss > 0 && a.page_miss) atomicAdd(a.page_miss, (unsigned)n_miss);
+    if (MODE == MODE_VISIBILITY) return;
     if (MODE == MODE_PREFILTER) {
         // one sample of Eq. (5): out += scale * L, wsum += scale where L is defined
         if (inside && ws > 0.0f) {
@@ -829,6 +844,49 @@ hipError_t launch_convert_rgtc(const uint8_t *y, const uint8_t *uv, void *yb, vo
     return hipGetLastError();
 }
 
+// RGBA8 images to kPage x kPage tiles: one workgroup per tile row of kPage texels (uint4 = 4 texels)
+__global__ void k_tile_images(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int32_t n, int32_t W, int32_t H) {
+    const int tx = W / kPage, ty = H / kPage;
+    const int64_t rows = (int64_t)n * H;  // one source row per (view, y)
+    constexpr int q = kPage / 4;          // uint4 per tile row
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int64_t v = r / H;
+        const int y = (int)(r % H);
+        for (int k = threadIdx.x; k < W / 4; k += blockDim.x) {
+            const int x4 = k * 4;
+            const int64_t tile = (v * ty + (y >> kPageShift)) * tx + (x4 >> kPageShift);
+            dst[tile * (kPage * q) + (y & (kPage - 1)) * q + ((x4 & (kPage - 1)) >> 2)] = src[r * (W / 4) + k];
+        }
+    }
+}
+
+hipError_t launch_tile_images(const uint32_t *src, uint32_t *dst, int32_t n, int32_t W, int32_t H, hipStream_t s) {
+    const int g = (int)std::min<int64_t>((int64_t)n * H, 65536);
+    hipLaunchKernelGGL(k_tile_images, dim3(g), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n, W, H);
+    return hipGetLastError();
+}
+
+// Tile cache update: workgroup 0 patches the page table; workgroup 1 + k
+// copies staged tile k into its page (16 KB: 1024 uint4, 4 per thread).
+__global__ void k_cache_apply(int32_t *__restrict__ pt, const int2 *__restrict__ patch, int32_t n_patch,
+                              const uint4 *__restrict__ staged, const int32_t *__restrict__ slot, char *__restrict__ pool) {
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k < n_patch; k += blockDim.x) pt[patch[k].x] = patch[k].y;
+        return;
+    }
+    const int k = blockIdx.x - 1;
+    constexpr int per = kPage * kPage * 4 / 16;
+    uint4 *dst = reinterpret_cast<uint4 *>(pool + (int64_t)slot[k] * (kPage * kPage * 4));
+    const uint4 *src = staged + (int64_t)k * per;
+    for (int i = threadIdx.x; i < per; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_cache_apply(int32_t *pt, const int2 *patch, int32_t n_patch, const uint4 *staged,
+                              const int32_t *slot, int32_t n_tiles, char *pool, hipStream_t s) {
+    hipLaunchKernelGGL(k_cache_apply, dim3(1 + n_tiles), dim3(256), 0, s, pt, patch, n_patch, staged, slot, pool);
+    return hipGetLastError();
+}
+
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s) {
     const int g = grid_for((int64_t)(M - 1) * (M - 1) * n, 256);
     if (geo_fmt == 0)
@@ -877,15 +935,31 @@ static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_
         else if (img_fmt == 1) LF_R(1, 0);
         else if (img_fmt == 2) LF_R(2, 0);
         else if (img_fmt == 3) LF_R(3, 0);
-        else LF_R(4, 0);
+        else if (img_fmt == 4) LF_R(4, 0);
+        else LF_R(5, 0);
     } else {
         if (img_fmt == 0) LF_R(0, 1);
         else if (img_fmt == 1) LF_R(1, 1);
         else if (img_fmt == 2) LF_R(2, 1);
         else if (img_fmt == 3) LF_R(3, 1);
-        else LF_R(4, 1);
+        else if (img_fmt == 4) LF_R(4, 1);
+        else LF_R(5, 1);
     }
 #undef LF_R
+}
+
+// the visibility pass exists for paged images only
+static void launch_visibility(const EyeChunk &ch, const RenderArgs &a, int geo_fmt, hipStream_t s) {
+    const dim3 grid(ch.total_tiles), block(ch.tile_w * ch.tile_h);
+#define LF_V(G, D) hipLaunchKernelGGL((k_render<5, G, MODE_VISIBILITY, D>), grid, block, 0, s, ch, a)
+    if (a.ext_inv) {
+        if (geo_fmt == 0) LF_V(0, DISK_OVAL);
+        else LF_V(1, DISK_OVAL);
+    } else {
+        if (geo_fmt == 0) LF_V(0, DISK_CIRCLE);
+        else LF_V(1, DISK_CIRCLE);
+    }
+#undef LF_V
 }
 
 template <int MODE>
@@ -904,13 +978,15 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
         else if (img_fmt == 1) LF_P(1, 0);
         else if (img_fmt == 2) LF_P(2, 0);
         else if (img_fmt == 3) LF_P(3, 0);
-        else LF_P(4, 0);
+        else if (img_fmt == 4) LF_P(4, 0);
+        else LF_P(5, 0);
     } else {
         if (img_fmt == 0) LF_P(0, 1);
         else if (img_fmt == 1) LF_P(1, 1);
         else if (img_fmt == 2) LF_P(2, 1);
         else if (img_fmt == 3) LF_P(3, 1);
-        else LF_P(4, 1);
+        else if (img_fmt == 4) LF_P(4, 1);
+        else LF_P(5, 1);
     }
 #undef LF_P
 }
@@ -936,12 +1012,12 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
 
 template <int DISK>
 static const void *persistent_fn(int img_fmt, int geo_fmt) {
-    const void *f0[5] = {(const void *)k_render_persistent<0, 0, DISK>, (const void *)k_render_persistent<1, 0, DISK>,
+    const void *f0[6] = {(const void *)k_render_persistent<0, 0, DISK>, (const void *)k_render_persistent<1, 0, DISK>,
                          (const void *)k_render_persistent<2, 0, DISK>, (const void *)k_render_persistent<3, 0, DISK>,
-                         (const void *)k_render_persistent<4, 0, DISK>};
-    const void *f1[5] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
+                         (const void *)k_render_persistent<4, 0, DISK>, (const void *)k_render_persistent<5, 0, DISK>};
+    const void *f1[6] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
                          (const void *)k_render_persistent<2, 1, DISK>, (const void *)k_render_persistent<3, 1, DISK>,
-                         (const void *)k_render_persistent<4, 1, DISK>};
+                         (const void *)k_render_persistent<4, 1, DISK>, (const void *)k_render_persistent<5, 1, DISK>};
     return geo_fmt == 0 ? f0[img_fmt] : f1[img_fmt];
 }
 
@@ -961,6 +1037,7 @@ hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, i
     else if (mode == MODE_SUBPIXEL) launch_render_disk<MODE_SUBPIXEL>(ch, a, img_fmt, geo_fmt, s);
     else if (mode == MODE_STATS) launch_render_disk<MODE_STATS>(ch, a, img_fmt, geo_fmt, s);
     else if (mode == MODE_PREFILTER) launch_render_disk<MODE_PREFILTER>(ch, a, img_fmt, geo_fmt, s);
+    else if (mode == MODE_VISIBILITY) launch_visibility(ch, a, geo_fmt, s);
     else launch_render_disk<MODE_DEBUG>(ch, a, img_fmt, geo_fmt, s);
     return hipGetLastError();
 }

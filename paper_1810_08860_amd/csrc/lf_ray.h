@@ -360,6 +360,53 @@ LF_HD Rgb bilinear_yuv(const void *__restrict__ yp, const void *__restrict__ uvp
     return {fmaf(1.402f, cr, lum), fmaf(-0.714136f, cr, fmaf(-0.344136f, cb, lum)), fmaf(1.772f, cb, lum)};
 }
 
+// Paged RGBA8 images (tile streaming): texel (x, y) lives in image tile
+// (x >> 6, y >> 6), whose cache page pt[tile] holds it at (y & 63, x & 63);
+// pages are 16 KB apart in pool. A sample is taken only if the pages of all
+// four taps are in the cache (pt >= 0); otherwise the view is left out for
+// this ray (result false).
+LF_HD uint32_t paged_texel(const char *__restrict__ pool, int32_t page, int x, int y) {
+    return at<uint32_t>(pool + (int64_t)page * (kPage * kPage * 4), (uint32_t)(((y & (kPage - 1)) << kPageShift) | (x & (kPage - 1))));
+}
+LF_HD bool bilinear_paged(const void *__restrict__ pt, const char *__restrict__ pool, int tiles_x, int W, int H,
+                          float px, float py, Rgb &out) {
+    const float x0f = floorf(px), y0f = floorf(py);
+    const float fx = px - x0f, fy = py - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
+    x0 = min(max(x0, 0), W - 1);
+    y0 = min(max(y0, 0), H - 1);
+    const uint32_t r0 = mul24(y0 >> kPageShift, tiles_x), r1 = mul24(y1 >> kPageShift, tiles_x);
+    const int32_t p00 = at<int32_t>(pt, r0 + (x0 >> kPageShift)), p10 = at<int32_t>(pt, r0 + (x1 >> kPageShift));
+    const int32_t p01 = at<int32_t>(pt, r1 + (x0 >> kPageShift)), p11 = at<int32_t>(pt, r1 + (x1 >> kPageShift));
+    if ((p00 | p10 | p01 | p11) < 0) return false;
+    const uint32_t ta = paged_texel(pool, p00, x0, y0), tb = paged_texel(pool, p10, x1, y0);
+    const uint32_t tc = paged_texel(pool, p01, x0, y1), td = paged_texel(pool, p11, x1, y1);
+    const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
+    float c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t sh = 8u * k;
+        c[k] = fmaf(w11, (float)((td >> sh) & 255u),
+                    fmaf(w01, (float)((tc >> sh) & 255u), fmaf(w10, (float)((tb >> sh) & 255u), fmaf(w00, (float)((ta >> sh) & 255u), 0.0f))));
+    }
+    out = {c[0], c[1], c[2]};
+    return true;
+}
+
+// Visibility pass: mark the image tiles of the four taps of a sample.
+LF_HD void mark_taps(uint8_t *__restrict__ vis, int tiles_x, int W, int H, float px, float py) {
+    int x0 = (int)floorf(px), y0 = (int)floorf(py);
+    const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
+    x0 = min(max(x0, 0), W - 1);
+    y0 = min(max(y0, 0), H - 1);
+    const int r0 = (y0 >> kPageShift) * tiles_x, r1 = (y1 >> kPageShift) * tiles_x;
+    vis[r0 + (x0 >> kPageShift)] = 1;
+    vis[r0 + (x1 >> kPageShift)] = 1;
+    vis[r1 + (x0 >> kPageShift)] = 1;
+    vis[r1 + (x1 >> kPageShift)] = 1;
+}
+
 // One texel of an RGTC1 (BC4 unsigned) block held as two little-endian words:
 // endpoints e0 = byte 0, e1 = byte 1, then the 3-bit code of texel t = 4 y + x
 // at bit 16 + 3 t. Code 0 is e0 and code 1 is e1; with e0 > e1 codes 2..7 are

@@ -12,12 +12,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblf.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
-LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420, LF_IMG_YUV420_RGTC = 0, 1, 2, 3, 4
+LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420, LF_IMG_YUV420_RGTC, LF_IMG_PAGED_RGBA8 = 0, 1, 2, 3, 4, 5
 LF_GEO_F32, LF_GEO_F16 = 0, 1
 LF_SRC_DEVICE = 1
 
 IMG_FORMATS = {"rgba8": LF_IMG_RGBA8, "rgba16f": LF_IMG_RGBA16F, "rgba32f": LF_IMG_RGBA32F, "yuv420": LF_IMG_YUV420,
-               "yuv420_rgtc": LF_IMG_YUV420_RGTC}
+               "yuv420_rgtc": LF_IMG_YUV420_RGTC, "paged_rgba8": LF_IMG_PAGED_RGBA8}
 GEO_FORMATS = {"f32": LF_GEO_F32, "f16": LF_GEO_F16}
 
 
@@ -69,6 +69,10 @@ def lib():
         L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
         L.lf_set_view_mask.argtypes = [vp, vp]
         L.lf_two_level_mask.argtypes = [vp, i32, vp, vp]
+        L.lf_cache_config.argtypes = [vp, ctypes.c_int64, i32]
+        L.lf_cache_update.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, vp, vp, vp, vp]
+        L.lf_cache_resident.argtypes = [vp, vp]
+        L.lf_cache_page_misses.argtypes = [vp, vp]
         L.lf_debug_candidates.argtypes = [vp, ctypes.POINTER(lf_eye), f64, i32, i32, i32, vp, vp, vp, vp]
         L.lf_query.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
@@ -250,6 +254,46 @@ def lf_two_level_mask(ctx: Context, n_fine, fine_available):
     return out
 
 
+def lf_cache_config(ctx: Context, pages, first_resident=None):
+    """Tile cache of `pages` 64 x 64-texel pages for a paged context; views
+    [first_resident, n_views) stay resident (None: none)."""
+    fr = ctx.n_views if first_resident is None else int(first_resident)
+    _check(lib().lf_cache_config(ctx.handle, int(pages), fr))
+
+
+def lf_cache_update(ctx: Context, eyes, hfov_deg, res, budget, n_fine=None, stream=None):
+    """One frame of tile streaming for these eyes (visibility pass, FIFO
+    uploads within the budget, view mask). Returns (fine_available [n_fine],
+    visible [n_views, tiles] uint8, stats dict)."""
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    nf = ctx.n_views if n_fine is None else int(n_fine)
+    q = lf_query(ctx)
+    tiles = (q[1] // 64) ** 2
+    avail = np.zeros(max(nf, 1), np.uint8)
+    vis = np.zeros((ctx.n_views, tiles), np.uint8)
+    st = np.zeros(5, np.int64)
+    _check(lib().lf_cache_update(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, int(budget), avail.ctypes.data,
+                                 vis.ctypes.data, st.ctypes.data, _stream(stream)))
+    keys = ("visible", "cached", "copied", "evicted", "views_unavailable")
+    return avail[:nf], vis, dict(zip(keys, (int(x) for x in st)))
+
+
+def lf_cache_resident(ctx: Context):
+    """uint8 [n_views, tiles]: 1 where the tile is in the cache."""
+    q = lf_query(ctx)
+    out = np.zeros((ctx.n_views, (q[1] // 64) ** 2), np.uint8)
+    _check(lib().lf_cache_resident(ctx.handle, out.ctypes.data))
+    return out
+
+
+def lf_cache_page_misses(ctx: Context):
+    """Samples left out for a missing tile since the last call (resets it)."""
+    m = ctypes.c_uint64(0)
+    _check(lib().lf_cache_page_misses(ctx.handle, ctypes.byref(m)))
+    return int(m.value)
+
+
 BASIS = {"box": 0, "lanczos2": 1}
 
 
@@ -399,7 +443,8 @@ def lf_last_error() -> str:
 
 # names of every symbol include/lf.h declares (checked by the ABI test)
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_reference",
-           "lf_prefilter", "lf_set_view_mask", "lf_two_level_mask",
+           "lf_prefilter", "lf_set_view_mask", "lf_two_level_mask", "lf_cache_config", "lf_cache_update",
+           "lf_cache_resident", "lf_cache_page_misses",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
            "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",

@@ -50,7 +50,8 @@ def _desc(**kw):
     ("src_fov_deg", 180.0, "src_fov"),
     ("disk_radius", 0.0, "disk_radius"),
     ("img_fmt", 7, "img_fmt"),
-    ("img_fmt", 5, "img_fmt"),
+    ("img_fmt", 6, "img_fmt"),
+    ("img_fmt", 5, "multiples of 64"),  # paged images: 64 x 64-texel tiles
     ("img_fmt", 4, "multiples of 8"),  # RGTC blocks of 4 x 4 chroma samples
     ("geo_fmt", 5, "geo_fmt"),
     ("flags", 8, "flags"),
@@ -102,6 +103,11 @@ def test_null_context_and_arguments():
     dp = np.zeros(2)
     assert L.lf_prefilter(None, v.ctypes.data, 1, 0.05, dp.ctypes.data, dp.ctypes.data, 1, 1, 1, 1,
                           None) == lf.LF_EINVAL
+    assert "context" in lf.lf_last_error()
+    assert L.lf_cache_config(None, 16, 0) == lf.LF_EINVAL
+    assert L.lf_cache_update(None, e, 1, 90.0, res.ctypes.data, 8, None, None, None, None) == lf.LF_EINVAL
+    assert L.lf_cache_resident(None, None) == lf.LF_EINVAL
+    assert L.lf_cache_page_misses(None, None) == lf.LF_EINVAL
     assert "context" in lf.lf_last_error()
     L.lf_free(None)  # no-op
 

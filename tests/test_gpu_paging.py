@@ -1,0 +1,192 @@
+"""Tile streaming and caching (Sec. 4.2, tile streaming and caching; Sec. 7.2)
+on the GPU: images held as 64 x 64-texel tiles in host memory and sampled
+from a device cache of pages through a per-view page table.
+
+Checked: with every shown tile cached the paged render equals the resident
+RGBA8 render bit for bit; the visibility pass shows the tiles the FP64 oracle
+finds; with part of the tiles cached the render matches the oracle's
+residency model; a sequence of frames through a small FIFO cache keeps the
+cache consistent and renders, bit for bit, what the resident images give
+under the same view mask, with no sample ever reaching a missing page; and
+with a resident coarse level the two-level fill-in does the same."""
+import numpy as np
+import pytest
+
+import lfsynth
+import oracle
+from lfcheck import check_eye, gpu_context, gpu_render
+
+pytestmark = pytest.mark.gpu
+
+PAGE = 64
+
+
+class _Views:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def _eye(tiny):
+    return [(tiny.head_pos[0], tiny.head_rot[0])]
+
+
+def _tpv(V):
+    return (V.rgba8.shape[1] // PAGE) * (V.rgba8.shape[2] // PAGE)
+
+
+@pytest.fixture(scope="module")
+def ctxs(tiny):
+    paged = gpu_context(tiny.views, "paged_rgba8", "f32")
+    plain = gpu_context(tiny.views, "rgba8", "f32")
+    yield paged, plain
+    paged.close()
+    plain.close()
+
+
+def test_full_cache_equals_resident_render(tiny, ctxs):
+    from paper_1810_08860_amd import lf
+    paged, plain = ctxs
+    V = tiny.views
+    lf.lf_cache_config(paged, V.n * _tpv(V))
+    eye = _eye(tiny)
+    avail, vis, st = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], 1 << 20)
+    print("first frame:", st)
+    assert st["copied"] == st["visible"] == int(vis.sum()) > 0 and st["cached"] == 0
+    assert st["evicted"] == 0 and st["views_unavailable"] == 0 and avail.all()
+    assert np.array_equal(lf.lf_cache_resident(paged), vis)
+    lf.lf_set_view_mask(plain, None)
+    a = gpu_render(paged, eye, tiny.hfov_deg, [(256, 256)])[0]
+    b = gpu_render(plain, eye, tiny.hfov_deg, [(256, 256)])[0]
+    assert lf.lf_cache_page_misses(paged) == 0
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    _, _, st2 = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], 1 << 20)
+    assert st2["copied"] == 0 and st2["cached"] == st2["visible"] == st["visible"]
+
+
+def test_visibility_matches_oracle(tiny, tiny_oracle, ctxs):
+    from paper_1810_08860_amd import lf
+    paged, _ = ctxs
+    V = tiny.views
+    lf.lf_cache_config(paged, V.n * _tpv(V))
+    for k, (W, H, fov) in enumerate([(256, 256, tiny.hfov_deg), (320, 200, 75.0)]):
+        p, R = (tiny.head_pos[0], tiny.head_rot[0]) if k == 0 else [a[0] for a in lfsynth.poses(43, 1, 0.2)]
+        _, vis, _ = lf.lf_cache_update(paged, [(p, R)], fov, [(W, H)], 0)
+        want = oracle.visible_tiles(tiny_oracle, p, R, fov, W, H, page=PAGE).reshape(V.n, -1)
+        diff = int((vis != want).sum())
+        print(f"eye {k}: {int(want.sum())} tiles shown, {diff} differ")
+        # a tile can differ only through an ill-conditioned decision (a tap on
+        # a tile border, a disk rim, a mesh edge) of some ray
+        assert diff <= max(1, want.sum() // 100)
+
+
+def test_partial_cache_matches_oracle_residency(tiny, tiny_oracle, ctxs):
+    from paper_1810_08860_amd import lf
+    paged, _ = ctxs
+    V = tiny.views
+    lf.lf_cache_config(paged, V.n * _tpv(V))
+    eye = _eye(tiny)
+    _, vis, st = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], 0)
+    _, _, st = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], int(vis.sum()) // 2)
+    res = lf.lf_cache_resident(paged)
+    assert 0 < res.sum() < vis.sum() and st["views_unavailable"] > 0
+    lf.lf_set_view_mask(paged, None)  # every view, cached tiles or not
+    ov = tiny_oracle.with_residency(res.reshape(V.n, V.rgba8.shape[1] // PAGE, -1), PAGE)
+    s = check_eye(ov, paged, tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg, 256, 256, lists=False)
+    misses = lf.lf_cache_page_misses(paged)
+    print("half the shown tiles cached:", s, "samples left out:", misses)
+    assert misses > 0
+
+
+def test_fifo_sequence_renders_as_resident(tiny, ctxs):
+    """Eight poses along a short head path through a cache of 40 pages with
+    8 copies per frame: the FIFO evicts, views come and go, and every frame
+    renders exactly what the resident images give under the frame's mask."""
+    import torch
+    from paper_1810_08860_amd import lf
+    paged, plain = ctxs
+    V = tiny.views
+    pages, budget = 40, 8
+    lf.lf_cache_config(paged, pages)
+    p0, R0 = tiny.head_pos[0], tiny.head_rot[0]
+    copied = evicted = 0
+    for f in range(8):
+        a = 0.08 * f
+        Rz = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1.0]])
+        eye = [(p0 + np.array([0.01 * f, 0, 0]), Rz @ R0)]
+        avail, vis, st = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], budget)
+        res = lf.lf_cache_resident(paged)
+        assert res.sum() <= pages and st["copied"] <= budget
+        shown_missing = (vis & (1 - res)).reshape(V.n, -1).any(1)
+        assert np.array_equal(avail, (~shown_missing).astype(np.uint8))
+        copied += st["copied"]
+        evicted += st["evicted"]
+        lf.lf_set_view_mask(plain, avail)
+        a_ = gpu_render(paged, eye, tiny.hfov_deg, [(256, 256)])[0]
+        b_ = gpu_render(plain, eye, tiny.hfov_deg, [(256, 256)])[0]
+        assert lf.lf_cache_page_misses(paged) == 0
+        for x, y in zip(a_, b_):
+            assert np.array_equal(x, y)
+    lf.lf_set_view_mask(plain, None)
+    torch.cuda.synchronize()
+    print("copied", copied, "evicted", evicted)
+    assert evicted > 0
+
+
+def test_resident_coarse_level_fills_in(tiny):
+    """Fine views paged, every 4th view again as a resident coarse level with
+    disks for its spacing: after a budget-limited update the paged render
+    equals the resident render under lf_two_level_mask of the available fine
+    views, and no sample reaches a missing page."""
+    from paper_1810_08860_amd import lf
+    V = tiny.views
+    coarse = np.arange(0, V.n, 4)
+    R_f, R_c = V.disk_radius, 1.5 * lfsynth.mean_nn(V.centres[coarse])
+    idx = np.concatenate([np.arange(V.n), coarse])
+    ext = np.concatenate([np.full((V.n, 4), R_f), np.full((len(coarse), 4), R_c)])
+    tl = _Views(centres=V.centres[idx], rot=V.rot[idx], rgba8=V.rgba8[idx], zdepth=V.zdepth[idx],
+                src_fov_deg=V.src_fov_deg, disk_radius=R_f)
+    paged = gpu_context(tl, "paged_rgba8", "f32", disk_ext=ext)
+    plain = gpu_context(tl, "rgba8", "f32", disk_ext=ext)
+    tpv = _tpv(V)
+    lf.lf_cache_config(paged, len(coarse) * tpv + 24, first_resident=V.n)
+    res0 = lf.lf_cache_resident(paged)
+    assert res0[V.n:].all() and not res0[:V.n].any()
+    eye = _eye(tiny)
+    avail, vis, st = lf.lf_cache_update(paged, eye, tiny.hfov_deg, [(256, 256)], 12, n_fine=V.n)
+    print("coarse level resident, 12 copies:", st)
+    assert 0 < avail.sum() < V.n and not vis[V.n:].any()
+    mask = lf.lf_two_level_mask(plain, V.n, avail)
+    assert mask[V.n:].any()
+    lf.lf_set_view_mask(plain, mask)
+    a = gpu_render(paged, eye, tiny.hfov_deg, [(256, 256)])[0]
+    b = gpu_render(plain, eye, tiny.hfov_deg, [(256, 256)])[0]
+    assert lf.lf_cache_page_misses(paged) == 0
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    paged.close()
+    plain.close()
+
+
+def test_full_size_paged_frame(tiny):
+    """The full light field paged into a 2 GB cache (the paper's limit):
+    one stereo frame streamed in, then rendered exactly as from resident
+    RGBA8 images."""
+    from paper_1810_08860_amd import lf
+    w = lfsynth.make_workload("full", seed=0, n_poses=1)
+    V = w.views
+    paged = gpu_context(V, "paged_rgba8", "f16")
+    plain = gpu_context(V, "rgba8", "f16")
+    lf.lf_cache_config(paged, (2 << 30) // (PAGE * PAGE * 4))
+    eyes = [(np.array(e.pos), np.array(e.rot).reshape(3, 3))
+            for e in lf.lf_stereo_eyes(w.head_pos[0], w.head_rot[0], 0.064)]
+    avail, vis, st = lf.lf_cache_update(paged, eyes, 100.0, [(1440, 1600)] * 2, 1 << 30)
+    print("full stereo frame:", st)
+    assert avail.all() and st["copied"] == st["visible"]
+    a = gpu_render(paged, eyes, 100.0, [(1440, 1600)] * 2, want_aux=False)
+    b = gpu_render(plain, eyes, 100.0, [(1440, 1600)] * 2, want_aux=False)
+    assert lf.lf_cache_page_misses(paged) == 0
+    for x, y in zip(a, b):
+        assert np.array_equal(x[0], y[0])
+    paged.close()
+    plain.close()
