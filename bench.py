@@ -24,7 +24,11 @@ leg times the light field prefilter of Sec. 5 (Eq. (5)): 16 views of a
 real-time model (every 4th view) prefiltered at full resolution with 16
 Lanczos-2 samples per pixel against the whole view set as the offline model.
 The two-level leg renders with half the fine views available and the coarse
-level (every 4th capture, larger disks) filling in (Sec. 7.2).
+level (every 4th capture, larger disks) filling in (Sec. 7.2). The YUV420
+form is also timed transcoded to RGTC blocks (0.75 bytes per texel). The
+streaming leg pages the fine views' 64x64 image tiles from host memory into a
+2 GB device cache (FIFO, at most 128 tiles per frame) along a turning head
+path, with the coarse level resident (Sec. 4.2 and Sec. 7.2).
 """
 from __future__ import annotations
 
@@ -387,6 +391,65 @@ def two_level_leg(lf, torch, V, eyes_all, steps=200, avail_frac=0.5):
             "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"]}
 
 
+def streaming_leg(lf, torch, V, head_pos, head_rot, frames=270, budget=128, cache_gb=2.0, yaw_deg_s=60.0):
+    """Tile streaming and caching (Sec. 4.2, Sec. 7.2) along a head path:
+    fine level = every view, paged (64x64 RGBA8 tiles in pinned host memory,
+    a 2 GB device cache of pages, FIFO); coarse level = every 4th capture
+    again with disks for its spacing, resident in the cache. Each 90 Hz frame
+    runs lf_cache_update (visibility pass, at most `budget` tiles copied in,
+    mask = available fine views + coarse fill-in) and then renders the stereo
+    frame. The path starts cold (empty fine cache) and turns the head at
+    yaw_deg_s while drifting 5 cm/s."""
+    import lfsynth
+    coarse = np.arange(0, V.n, 4)
+    idx = np.concatenate([np.arange(V.n), coarse])
+    ext = np.concatenate([np.full((V.n, 4), V.disk_radius),
+                          np.full((len(coarse), 4), 1.5 * lfsynth.mean_nn(V.centres[coarse]))])
+    ctx = lf.lf_load_views(V.centres[idx], V.rot[idx], V.rgba8[idx], V.zdepth[idx], V.src_fov_deg, V.disk_radius,
+                           img_fmt="paged_rgba8", geo_fmt="f16", disk_ext=ext)
+    pages = int(cache_gb * (1 << 30)) // (64 * 64 * 4)
+    lf.lf_cache_config(ctx, pages, first_resident=V.n)
+    res = np.array([[EYE_W, EYE_H], [EYE_W, EYE_H]], np.int32)
+    out = torch.empty(2 * EYE_W * EYE_H * 3, dtype=torch.float32, device="cuda")
+    up_ms, rd_ms, copied, missing, visible = [], [], [], [], []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+    for f in range(frames):
+        a = np.radians(yaw_deg_s) * f / 90.0
+        Rz = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1.0]])
+        pos = head_pos + np.array([0.05 * f / 90.0, 0.0, 0.0])
+        eyes = [(np.array(e.pos), np.array(e.rot).reshape(3, 3)) for e in lf.lf_stereo_eyes(pos, Rz @ head_rot, IPD)]
+        t0 = time.perf_counter()
+        _, _, st = lf.lf_cache_update(ctx, eyes, HFOV, res, budget, n_fine=V.n)
+        up_ms.append(1e3 * (time.perf_counter() - t0))
+        ev[f][0].record()
+        lf.lf_render(ctx, eyes, HFOV, res, out)
+        ev[f][1].record()
+        copied.append(st["copied"])
+        missing.append(st["views_unavailable"])
+        visible.append(st["visible"])
+    torch.cuda.synchronize()
+    rd_ms = np.array([x.elapsed_time(y) for x, y in ev])
+    misses = lf.lf_cache_page_misses(ctx)
+    ctx.close()
+    up_ms, copied, missing = np.array(up_ms), np.array(copied), np.array(missing)
+    warm = int(np.argmax(missing == 0)) if (missing == 0).any() else frames
+    steady = slice(warm, frames)
+    return {
+        "frames": frames, "budget_tiles": budget, "cache_gb": cache_gb, "yaw_deg_s": yaw_deg_s,
+        "visible_tiles_mean": float(np.mean(visible)),
+        "cold_start_frames": warm,
+        "copied_tiles_cold_mean": float(copied[:warm].mean()) if warm else 0.0,
+        "copied_tiles_steady_mean": float(copied[steady].mean()) if warm < frames else None,
+        "copied_tiles_steady_max": int(copied[steady].max()) if warm < frames else None,
+        "fine_views_unavailable_steady_mean": float(missing[steady].mean()) if warm < frames else None,
+        "update_ms_p50": float(np.percentile(up_ms, 50)), "update_ms_p99": float(np.percentile(up_ms, 99)),
+        "render_ms_p50": float(np.percentile(rd_ms, 50)), "render_ms_p99": float(np.percentile(rd_ms, 99)),
+        "page_misses": misses,
+        "note": "update = visibility pass + host FIFO + tile copies + mask (synchronous); render = lf_render of the "
+                "stereo frame from the cache",
+    }
+
+
 def mixed_batch(lf, torch, ctx, seed, n_poses=64, reps=10):
     """64 stereo poses of uneven per-eye sizes in one persistent launch."""
     import lfsynth
@@ -447,6 +510,7 @@ def main():
     ap.add_argument("--no-corrector", action="store_true", help="skip the learned-corrector leg")
     ap.add_argument("--no-prefilter", action="store_true", help="skip the prefilter leg")
     ap.add_argument("--no-two-level", action="store_true", help="skip the two-level progressive leg")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the tile streaming leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
     ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,yuv420_rgtc,fp16_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
@@ -541,6 +605,14 @@ def main():
         log(f"[bench] two-level: {two['fine_available']} fine + {two['coarse_drawn']} coarse views, "
             f"{two['mpix_s']:.0f} Mpix/s, {two['ms_per_stereo_frame']:.4f} ms/stereo frame")
 
+    stream = None
+    if not args.no_streaming:
+        log("[bench] tile streaming ...")
+        stream = streaming_leg(lf, torch, V, w.head_pos[0], w.head_rot[0])
+        log(f"[bench] streaming: cold start {stream['cold_start_frames']} frames, steady "
+            f"{stream['copied_tiles_steady_mean']} tiles/frame, update p50 {stream['update_ms_p50']:.3f} ms, "
+            f"render p50 {stream['render_ms_p50']:.3f} ms, page misses {stream['page_misses']}")
+
     pref = None
     if not args.no_prefilter and ("rgba32f", "f32", "circle") in ctxs:
         log("[bench] prefilter ...")
@@ -616,6 +688,7 @@ def main():
         "corrector": corr,
         "prefilter": pref,
         "two_level": two,
+        "streaming": stream,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
