@@ -341,6 +341,9 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (d->img_fmt == LF_IMG_PAGED_RGBA8 && (d->img_w % kPage || d->img_h % kPage))
         return fail(LF_EINVAL, "paged images need sizes that are multiples of %d (got %dx%d)", kPage, d->img_w,
                     d->img_h);
+    if (d->img_fmt == LF_IMG_PAGED_RGBA8 &&
+        (int64_t)d->n_views * (d->img_w / kPage) * (d->img_h / kPage) > INT32_MAX)
+        return fail(LF_EINVAL, "paged images: more than 2^31 tiles in all");
     if (d->img_fmt == LF_IMG_YUV420 && (d->img_w % 2 || d->img_h % 2))
         return fail(LF_EINVAL, "YUV420 needs even image sizes (got %dx%d)", d->img_w, d->img_h);
     if (d->img_fmt == LF_IMG_YUV420_RGTC && (d->img_w % 8 || d->img_h % 8))

@@ -133,6 +133,34 @@ def test_fifo_sequence_renders_as_resident(tiny, ctxs):
     assert evicted > 0
 
 
+def test_paged_batch_matches_per_eye(tiny, ctxs):
+    """The persistent batch path reads the same pages: after one update for
+    three stereo poses, the batch equals the per-eye renders bit for bit."""
+    import torch
+    from paper_1810_08860_amd import lf
+    paged, _ = ctxs
+    V = tiny.views
+    lf.lf_cache_config(paged, V.n * _tpv(V))
+    p, R = lfsynth.poses(47, 3, 0.2)
+    eyes, res = [], []
+    for k in range(3):
+        for e in lf.lf_stereo_eyes(p[k], R[k], 0.064):
+            eyes.append((np.array(e.pos), np.array(e.rot).reshape(3, 3)))
+            res.append((136, 120))
+    avail, _, st = lf.lf_cache_update(paged, eyes, 90.0, res, 1 << 20)
+    assert avail.all() and st["copied"] == st["visible"] > 0
+    npx = sum(w * h for w, h in res)
+    ref = torch.zeros(npx * 3, dtype=torch.float32, device="cuda")
+    off = 0
+    for (pp, RR), (w, h) in zip(eyes, res):
+        lf.lf_render(paged, [(pp, RR)], 90.0, (w, h), ref[off:off + 3 * w * h])
+        off += 3 * w * h
+    got = torch.full((npx * 3,), -5.0, dtype=torch.float32, device="cuda")
+    lf.lf_render_batch(paged, eyes, 90.0, np.array(res, np.int32), got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref) and lf.lf_cache_page_misses(paged) == 0
+
+
 def test_resident_coarse_level_fills_in(tiny):
     """Fine views paged, every 4th view again as a resident coarse level with
     disks for its spacing: after a budget-limited update the paged render
