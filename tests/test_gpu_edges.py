@@ -1,0 +1,70 @@
+"""Edge cases of the render path on the GPU: degenerate and extreme inputs.
+
+A 1 x 1 eye and a one-pixel-wide eye against the oracle; more eyes in one call
+than one launch carries (the chunked path) against per-eye renders; every
+view disabled (Eq. 2's empty denominator: colour, weight sum and count all 0);
+and the input checks (no eyes, zero or oversized resolutions)."""
+import numpy as np
+import pytest
+
+import lfsynth
+from lfcheck import check_eye, gpu_render
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(tiny):
+    from lfcheck import gpu_context
+    c = gpu_context(tiny.views, "rgba32f", "f32")
+    yield c
+    c.close()
+
+
+def test_single_pixel_and_single_column_eyes(tiny, tiny_oracle, ctx):
+    p, R = tiny.head_pos[0], tiny.head_rot[0]
+    for W, H in [(1, 1), (1, 37), (29, 1)]:
+        s = check_eye(tiny_oracle, ctx, p, R, 60.0, W, H)
+        print((W, H), s)
+
+
+def test_more_eyes_than_one_launch(tiny, ctx):
+    """17 eyes in one call (one launch carries 16): the same pixels as 17
+    separate calls, bit for bit."""
+    import torch
+    from paper_1810_08860_amd import lf
+    p, R = lfsynth.poses(91, 17, 0.2)
+    eyes = [(p[k], R[k]) for k in range(17)]
+    res = [(24 + 3 * k, 20 + k) for k in range(17)]
+    got = gpu_render(ctx, eyes, 80.0, res)
+    for e, r, g in zip(eyes, res, got):
+        one = gpu_render(ctx, [e], 80.0, [r])[0]
+        for x, y in zip(g, one):
+            assert np.array_equal(x, y)
+    torch.cuda.synchronize()
+
+
+def test_every_view_disabled_renders_zero(tiny, ctx):
+    from paper_1810_08860_amd import lf
+    lf.lf_set_view_mask(ctx, np.zeros(tiny.views.n, np.uint8))
+    try:
+        rgb, ws, cnt = gpu_render(ctx, [(tiny.head_pos[0], tiny.head_rot[0])], tiny.hfov_deg, [(64, 48)])[0]
+    finally:
+        lf.lf_set_view_mask(ctx, None)
+    assert (rgb == 0).all() and (ws == 0).all() and (cnt == 0).all()
+
+
+def test_input_checks(tiny, ctx):
+    import torch
+    from paper_1810_08860_amd import lf
+    out = torch.zeros(16 * 16 * 3, dtype=torch.float32, device="cuda")
+    e = lf.make_eyes([(tiny.head_pos[0], tiny.head_rot[0])])
+    L = lf.lib()
+    for res in ([0, 16], [16, 0], [32769, 16], [16, -1]):
+        r = np.array(res, np.int32)
+        assert L.lf_render(ctx.handle, e, 1, 90.0, r.ctypes.data, out.data_ptr(), None, None, None) == lf.LF_EINVAL
+        assert "resolution" in lf.lf_last_error()
+    r = np.array([16, 16], np.int32)
+    assert L.lf_render(ctx.handle, e, 0, 90.0, r.ctypes.data, out.data_ptr(), None, None, None) == lf.LF_EINVAL
+    assert L.lf_render(ctx.handle, e, 1, 180.0, r.ctypes.data, out.data_ptr(), None, None, None) == lf.LF_EINVAL
+    assert L.lf_render(ctx.handle, e, 1, 90.0, r.ctypes.data, None, None, None, None) == lf.LF_EINVAL
