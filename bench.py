@@ -48,7 +48,11 @@ METRIC = "eye-view Mpix/s + ms/stereo frame, FP16/batched vs plain FP32 at ≤2/
 EYE_W, EYE_H, HFOV, IPD = 1440, 1600, 100.0, 0.064
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
-# algorithmic FP32 operations per counted unit of k_render
+# algorithmic FP32 operations per counted unit of k_render: a disk test (2 dot
+# products, a reciprocal, 2 products, the offset, a square root), a candidate's
+# march set-up (grid transform, domain clip), a mesh cell (exit inverse depths,
+# local coordinates, triangle select, field evaluation, sign test), a bilinear
+# sample with its accumulation (texel coordinates, 9 lerps as FMAs, 4 sums)
 FLOPS_PER = {"disk_tests": 25, "candidates": 30, "cells": 28, "samples": 50}
 
 
