@@ -166,6 +166,25 @@ def time_variant(lf, torch, ctx, eyes_all, steps, warmup, profile=False):
     }
 
 
+def achievable_hbm(lf, torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth: the library's plain streaming copy of 2 GiB
+    (each byte read once and written once), median of 10 timed copies."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        lf.lf_stream_copy(src, dst, nbytes)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        lf.lf_stream_copy(src, dst, nbytes)
+        b.record()
+    torch.cuda.synchronize()
+    assert torch.equal(src[:1024], dst[:1024])
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(lf, torch, views, head_pos, head_rot, ctx_plain, seconds):
     """FP64 oracle on a bounded sample of the same workload (pixels of the
     first stereo frame, strided), on all host cores; also the largest
@@ -655,6 +674,12 @@ def main():
             "work_per_launch": work,
             "output_write_gbs": (per_launch * 2 * EYE_W * EYE_H * 12) / (render_ms * 1e-3) / 1e9,
         }
+        hbm = achievable_hbm(lf, torch)
+        roofline["hbm_achievable_gbs"] = hbm
+        if traffic:
+            roofline["traffic_gbs"] = traffic / (render_ms * 1e-3) / 1e9
+            roofline["traffic_frac_of_achievable"] = roofline["traffic_gbs"] / hbm
+        log(f"[bench] achievable HBM (lf_stream_copy): {hbm:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline and ("rgba32f", "f32", "circle") in ctxs:

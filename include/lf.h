@@ -356,6 +356,16 @@ int lf_render_stats(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
 int lf_profile(lf_ctx *c, int32_t enable);
 int lf_profile_read(lf_ctx *c, double out[6]);
 
+/*
+ * Plain streaming copy of `bytes` from src to dst (both DEVICE, 16-byte
+ * aligned, bytes a positive multiple of 16, not overlapping), 16-byte loads
+ * and stores in a grid-stride loop; asynchronous on hip_stream. It reads and
+ * writes every byte once, so timing it gives the achievable HBM bandwidth
+ * that the render's measured traffic is compared with (not part of the
+ * paper's method). Errors: LF_EINVAL for the conditions above.
+ */
+int lf_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Learned residual corrector (a post-process of the render; not in the paper,
  * whose learning-based methods are related work only, Sec. 2).

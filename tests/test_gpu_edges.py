@@ -68,3 +68,19 @@ def test_input_checks(tiny, ctx):
     assert L.lf_render(ctx.handle, e, 0, 90.0, r.ctypes.data, out.data_ptr(), None, None, None) == lf.LF_EINVAL
     assert L.lf_render(ctx.handle, e, 1, 180.0, r.ctypes.data, out.data_ptr(), None, None, None) == lf.LF_EINVAL
     assert L.lf_render(ctx.handle, e, 1, 90.0, r.ctypes.data, None, None, None, None) == lf.LF_EINVAL
+
+
+def test_stream_copy():
+    """The bandwidth yardstick copies exactly and rejects misaligned or
+    partial-vector sizes."""
+    import torch
+    from paper_1810_08860_amd import lf
+    src = torch.randint(0, 2**31 - 1, (3 << 18,), dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    lf.lf_stream_copy(src, dst, src.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    L = lf.lib()
+    assert L.lf_stream_copy(src.data_ptr(), dst.data_ptr(), 20, None) == lf.LF_EINVAL
+    assert L.lf_stream_copy(src.data_ptr() + 4, dst.data_ptr(), 64, None) == lf.LF_EINVAL
+    assert L.lf_stream_copy(None, dst.data_ptr(), 64, None) == lf.LF_EINVAL
