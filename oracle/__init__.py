@@ -27,7 +27,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# LF_ORACLE_LIB may name another build of these sources: the mutation test
+# points it at copies with a planted mistake to show that the pins catch it
+_SO = os.environ.get("LF_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "conv_oracle.c")]
 
 
