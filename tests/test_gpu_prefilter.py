@@ -76,6 +76,22 @@ def test_tiny_prefilter_matches_oracle(tiny, tiny_oracle, ctx32, basis, half):
     check_views(tiny_oracle, ctx32, [3, 40], V.disk_radius, dp, po, basis, idx, V.img_res ** 2, f"tiny {basis}")
 
 
+def test_tiny_prefilter_with_oval_offline_disks(tiny, tiny_oracle):
+    """The offline model's disks as the asymmetric ovals of Sec. 4.4 (the
+    oracle's Delaunay 1-ring extents, given to both sides): the prefilter's
+    queries take the oval disk test and weights."""
+    V = tiny.views
+    ext, _ = oracle.disk_extents(V.centres, V.rot)
+    ov = tiny_oracle.with_disk_extents(ext)
+    ctx = gpu_context(V, "rgba32f", "f32", disk_ext=ext)
+    dp, po = lfsynth.prefilter_samples(23, 16, 2.0)
+    idx = np.arange(0, V.img_res ** 2, 17)
+    try:
+        check_views(ov, ctx, [7, 58], V.disk_radius, dp, po, "lanczos2", idx, V.img_res ** 2, "tiny oval")
+    finally:
+        ctx.close()
+
+
 def test_point_aperture_delta_basis_is_identity(tiny):
     """One sample at the disk centre with a zero offset and offline disks too
     small to reach a neighbour: the GPU prefilter returns the view's own
