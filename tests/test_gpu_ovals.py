@@ -102,3 +102,26 @@ def test_ovals_tighten_candidate_lists(full, full_ext):
     print(out)
     assert out["oval"]["candidates"] < out["circle"]["candidates"]
     assert out["oval"]["uncovered"] < 1e-2
+
+
+def test_oval_reference_render_scales_extents(tiny, tiny_oracle):
+    """The offline reference with oval disks grows every extent by the disk
+    scale: 3 x 3 sub-pixel rays with extents doubled against the oracle."""
+    import torch
+    from paper_1810_08860_amd import lf
+    V = tiny.views
+    ext, _ = oracle.disk_extents(V.centres, V.rot)
+    ov = tiny_oracle.with_disk_extents(ext)
+    ctx = gpu_context(V, "rgba32f", "f32", disk_ext=ext)
+    p, R = tiny.head_pos[0], tiny.head_rot[0]
+    Wr = Hr = 64
+    out = torch.zeros(Wr * Hr * 3, dtype=torch.float32, device="cuda")
+    lf.lf_render_reference(ctx, [(p, R)], 90.0, (Wr, Hr), 3, 2.0, out)
+    torch.cuda.synchronize()
+    ctx.close()
+    got = out.view(-1, 3).cpu().numpy()
+    idx = np.arange(0, Wr * Hr, 7)
+    ref = oracle.render_reference(ov, p, R, 90.0, Wr, Hr, idx, ss=3, disk_scale=2.0)
+    err = np.abs(got[idx] - ref).max(1)
+    print(f"oval reference ss=3: max err {err.max():.3g}, >1e-4: {(err > 1e-4).mean() * 100:.2f}%")
+    assert (err > 1e-4).mean() < 0.01 and err.max() < 2.0 / 255
