@@ -3,11 +3,13 @@
 A 1 x 1 eye and a one-pixel-wide eye against the oracle; more eyes in one call
 than one launch carries (the chunked path) against per-eye renders; every
 view disabled (Eq. 2's empty denominator: colour, weight sum and count all 0);
-and the input checks (no eyes, zero or oversized resolutions)."""
+the input checks (no eyes, zero or oversized resolutions); the bandwidth
+yardstick; and the work counters against the oracle's totals."""
 import numpy as np
 import pytest
 
 import lfsynth
+import oracle
 from lfcheck import check_eye, gpu_render
 
 pytestmark = pytest.mark.gpu
@@ -84,3 +86,24 @@ def test_stream_copy():
     assert L.lf_stream_copy(src.data_ptr(), dst.data_ptr(), 20, None) == lf.LF_EINVAL
     assert L.lf_stream_copy(src.data_ptr() + 4, dst.data_ptr(), 64, None) == lf.LF_EINVAL
     assert L.lf_stream_copy(None, dst.data_ptr(), 64, None) == lf.LF_EINVAL
+
+
+def test_work_counters_match_oracle(tiny, tiny_oracle, ctx):
+    """The work counters behind the bench's algorithmic flop count: pixels,
+    candidates and samples are the oracle's own totals over a full frame (up
+    to the (ray, view) pairs whose disk or hit decision is ill-conditioned);
+    every pixel tests its tile's list, so disk tests >= candidates, and every
+    sample needs a visited mesh cell, so cells >= samples."""
+    from paper_1810_08860_amd import lf
+    p, R = tiny.head_pos[0], tiny.head_rot[0]
+    lf.lf_set_view_mask(ctx, None)
+    st = lf.lf_render_stats(ctx, [(p, R)], tiny.hfov_deg, [(256, 256)])
+    ref = oracle.render(tiny_oracle, p, R, tiny.hfov_deg, 256, 256, cap=32)
+    band_c = int((ref["cand_band"] >= 0).sum())
+    band_h = int((ref["contrib_band"] >= 0).sum())
+    print(st, "oracle candidates", int(ref["n_cand"].sum()), "samples", int(ref["count"].sum()),
+          "band pairs", band_c, band_h)
+    assert st["pixels"] == 256 * 256
+    assert abs(st["candidates"] - int(ref["n_cand"].sum())) <= band_c
+    assert abs(st["samples"] - int(ref["count"].sum())) <= band_c + band_h
+    assert st["disk_tests"] >= st["candidates"] and st["cells"] >= st["samples"]
