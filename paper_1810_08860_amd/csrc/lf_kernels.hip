@@ -222,24 +222,80 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
 }
 
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
+// Can any ray of a plain eye's image rectangle [-tx, tx] x [-ty, ty] cross
+// the disk of radius R (view frame: ray direction m (X, Y, 1), eye at o)? The
+// tile test of the culling kernel applied to the whole rectangle, in FP64:
+// the corner rays of a wide eye can graze a disk plane, where FP32 would lose
+// the shape of their quad. Conservative like the tile test, so a view it
+// rejects is a candidate for no pixel of the eye.
+__device__ bool eye_sees_disk(const double (&m)[9], const double (&o)[3], double R, double tx, double ty) {
+    const double cx[4] = {-tx, tx, tx, -tx}, cy[4] = {ty, ty, -ty, -ty};
+    double ex[4], ey[4], ez[4], dx[4], dy[4];
+    int npos = 0;
+    for (int q = 0; q < 4; ++q) {
+        ex[q] = m[0] * cx[q] + m[1] * cy[q] + m[2];
+        ey[q] = m[3] * cx[q] + m[4] * cy[q] + m[5];
+        ez[q] = m[6] * cx[q] + m[7] * cy[q] + m[8];
+        npos += ez[q] > 0.0;
+        dx[q] = o[0] - o[2] * ex[q] / ez[q];
+        dy[q] = o[1] - o[2] * ey[q] / ez[q];
+    }
+    if (npos == 0) return false;
+    if (npos < 4) {
+        // the disk's bounding sphere against the four planes of the eye's frustum
+        for (int q = 0; q < 4; ++q) {
+            const int q1 = (q + 1) & 3, q2 = (q + 2) & 3;
+            double nx = ey[q] * ez[q1] - ez[q] * ey[q1];
+            double ny = ez[q] * ex[q1] - ex[q] * ez[q1];
+            double nz = ex[q] * ey[q1] - ey[q] * ex[q1];
+            if (nx * ex[q2] + ny * ey[q2] + nz * ez[q2] < 0.0) {
+                nx = -nx;
+                ny = -ny;
+                nz = -nz;
+            }
+            const double dist = -(nx * o[0] + ny * o[1] + nz * o[2]);
+            if (dist < -R * sqrt(nx * nx + ny * ny + nz * nz)) return false;
+        }
+        return true;
+    }
+    // circle against the convex quad of the corner rays' crossings
+    bool allp = true, alln = true;
+    double best = INFINITY;
+    for (int q = 0; q < 4; ++q) {
+        const int q1 = (q + 1) & 3;
+        const double fx = dx[q1] - dx[q], fy = dy[q1] - dy[q];
+        const double cr = fx * (-dy[q]) - fy * (-dx[q]);
+        allp = allp && cr >= 0.0;
+        alln = alln && cr <= 0.0;
+        const double ee = fx * fx + fy * fy;
+        double t = ee > 0.0 ? -(dx[q] * fx + dy[q] * fy) / ee : 0.0;
+        t = fmin(fmax(t, 0.0), 1.0);
+        const double px = dx[q] + t * fx, py = dy[q] + t * fy;
+        best = fmin(best, px * px + py * py);
+    }
+    return allp || alln || best <= R * R;
+}
+
 __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__restrict__ vt,
                                             const float2 *__restrict__ wr, int v, const DiskBound &db,
                                             const ViewBases &vb) {
     const double *c = vt + 12 * (int64_t)v;
     const double *R = c + 3;
     EyeView out;
-    double oz = 0.0;
+    double md[9], od[3];
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b) {
             double s = 0.0;
             for (int r = 0; r < 3; ++r) s += R[3 * r + a] * E.rot[3 * r + b];
+            md[3 * a + b] = s;
             out.m[3 * a + b] = (float)s;
         }
         double s = 0.0;
         for (int r = 0; r < 3; ++r) s += R[3 * r + a] * (E.pos[r] - c[r]);
+        od[a] = s;
         out.o[a] = (float)s;
-        oz = s;
     }
+    const double oz = od[2];
     const float2 w = wr[v];
     out.wmin = w.x;
     out.wmax = w.y;
@@ -251,6 +307,9 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     // disk that the exact per-ray test keeps
     out.rk = (float)((db.vrad ? (double)db.vrad[v] * db.vscale : db.R) * (1.0 + 1e-4) + 1e-7);
     if (db.vmask && !db.vmask[v]) out.rk = -1.0f;  // disabled: culled everywhere
+    // a view whose disk no ray of a plain eye can cross is culled for that eye
+    // (prefilter eyes send their rays off the pixel rectangle: kept)
+    if (E.src_view < 0 && out.rk > 0.0f && !eye_sees_disk(md, od, (double)out.rk, E.tx, E.ty)) out.rk = -1.0f;
     out.cells = vb.geo + v * vb.geo_bytes;
     out.img = vb.img + v * vb.img_bytes;
     out.blk = vb.blk + v * vb.blk_per_view;
