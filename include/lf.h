@@ -72,8 +72,9 @@ enum {
  * (the Cb block, then the Cr block), 0.75 bytes per texel in all. Each block
  * takes e0 = its maximum and e1 = its minimum and every value the nearest of
  * the eight points that split [e1, e0] into sevenths (halves rounded towards
- * e1); the render decodes the texels it reads from their blocks and samples
- * as for YUV420. It needs image sizes that are multiples of 8. All sampling
+ * e1; a constant block takes code 0 everywhere, so the five-point form is
+ * never used); the render decodes the texels it reads from their blocks and
+ * samples as for YUV420. It needs image sizes that are multiples of 8. All sampling
  * and blending arithmetic is FP32 in every format. */
 enum {
     LF_IMG_RGBA8 = 0,

@@ -409,20 +409,18 @@ LF_HD void mark_taps(uint8_t *__restrict__ vis, int tiles_x, int W, int H, float
 
 // One texel of an RGTC1 (BC4 unsigned) block held as two little-endian words:
 // endpoints e0 = byte 0, e1 = byte 1, then the 3-bit code of texel t = 4 y + x
-// at bit 16 + 3 t. Code 0 is e0 and code 1 is e1; with e0 > e1 codes 2..7 are
-// the sevenths from e0 towards e1 (code c at c - 1 sevenths), otherwise codes
-// 2..5 are the fifths, code 6 is 0 and code 7 is 255 (result in 0..255 units).
+// at bit 16 + 3 t. Code 0 is e0, code 1 is e1 and codes 2..7 are the sevenths
+// from e0 towards e1 (code c at c - 1 sevenths); result in 0..255 units. Only
+// the eight-point form is decoded: the blocks come from this library's own
+// encoder, which writes e0 > e1, or e0 = e1 with every code 0 (where both
+// forms give e0), never the five-point form's codes.
 LF_HD float rgtc1_texel(uint32_t lo, uint32_t hi, uint32_t t) {
     const uint64_t bits = ((uint64_t)hi << 32) | lo;
     const uint32_t c = (uint32_t)(bits >> (16u + 3u * t)) & 7u;
-    const uint32_t e0 = lo & 255u, e1 = (lo >> 8) & 255u;
-    const bool eight = e0 > e1;
-    const uint32_t steps = eight ? 7u : 5u;
-    const uint32_t p = c == 0u ? 0u : (c == 1u ? steps : c - 1u);
-    const float f0 = (float)e0;
-    float v = fmaf((float)p * (eight ? (1.0f / 7.0f) : 0.2f), (float)e1 - f0, f0);
-    if (!eight && c >= 6u) v = c == 6u ? 0.0f : 255.0f;
-    return v;
+    // sevenths from e0 by code: 0, 7, 1, 2, 3, 4, 5, 6 (3-bit fields of an octal constant)
+    const uint32_t p = (065432170u >> (3u * c)) & 7u;
+    const float f0 = (float)(lo & 255u), f1 = (float)((lo >> 8) & 255u);
+    return fmaf((float)p * (1.0f / 7.0f), f1 - f0, f0);
 }
 
 // RGTC form of the YUV420 planes (result in 0..255 units): the luma plane as
