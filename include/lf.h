@@ -231,7 +231,8 @@ int lf_cache_config(lf_ctx *c, int64_t pages, int32_t first_resident);
  * [n_views][tiles] (the visibility pass, 1 = shown) or NULL; stats: host
  * int64 [5] or NULL = visible tiles, of them already cached, tiles copied in,
  * tiles evicted, fine views unavailable. Synchronous on hip_stream (waits for
- * the copies). Errors: LF_ESTATE without lf_cache_config or paged images;
+ * the copies); it rewrites the view mask in stream order, so renders of this
+ * context on other streams must not be in flight. Errors: LF_ESTATE without lf_cache_config or paged images;
  * LF_EINVAL as lf_render or for budget < 0.
  */
 int lf_cache_update(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,

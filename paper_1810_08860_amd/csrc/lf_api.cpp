@@ -106,7 +106,11 @@ struct lf_ctx {
         std::vector<int64_t> stamp;         // page -> update call that filled it
         int64_t calls = 0;
         uint8_t *vis_dev = nullptr;         // visibility pass output [n][tiles]
-        std::vector<uint8_t> vis;
+        int32_t *keys_dev = nullptr;        // its set entries, compacted [n * tiles]
+        unsigned int *count_host = nullptr; // pinned: number of keys (device-written count in count_host[0])
+        unsigned int *count_dev = nullptr;
+        uint8_t *mask_host = nullptr;       // pinned: view mask staging [n]
+        std::vector<int32_t> vis_keys;      // visible tiles of the last update, ascending
         char *stage_host = nullptr, *stage_dev = nullptr;  // patches, pages, tiles of one update
         size_t stage_bytes = 0;
         unsigned int *miss_dev = nullptr;   // samples left out for a missing page
@@ -636,12 +640,16 @@ int lf_two_level_mask(const lf_ctx *c, int32_t n_fine, const uint8_t *fine_avail
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (!fine_available || !mask_out) return fail(LF_EINVAL, "fine_available and mask_out must not be NULL");
     if (n_fine <= 0 || n_fine > c->n) return fail(LF_EINVAL, "n_fine must be in [1, n_views] (got %d)", n_fine);
-    for (int32_t v = 0; v < n_fine; ++v) mask_out[v] = fine_available[v] ? 1 : 0;
+    std::vector<int32_t> missing;  // unavailable fine views (usually few or none)
+    for (int32_t v = 0; v < n_fine; ++v) {
+        mask_out[v] = fine_available[v] ? 1 : 0;
+        if (!fine_available[v]) missing.push_back(v);
+    }
     for (int32_t j = n_fine; j < c->n; ++j) {
         const double *cj = &c->h_vt[12 * (size_t)j];
         uint8_t need = 0;
-        for (int32_t i = 0; i < n_fine && !need; ++i) {
-            if (fine_available[i]) continue;
+        for (size_t q = 0; q < missing.size() && !need; ++q) {
+            const int32_t i = missing[q];
             const double *ci = &c->h_vt[12 * (size_t)i];
             const double dx = ci[0] - cj[0], dy = ci[1] - cj[1], dz = ci[2] - cj[2];
             need = dx * dx + dy * dy + dz * dz < c->h_rad[j] * c->h_rad[j];
@@ -669,6 +677,13 @@ int lf_cache_config(lf_ctx *c, int64_t pages, int32_t first_resident) {
     const size_t page_bytes = (size_t)kPage * kPage * 4;
     LF_HIP(hipMalloc((void **)&K.pool, page_bytes * pages), "hipMalloc(tile cache)");
     if (!K.vis_dev) LF_HIP(hipMalloc((void **)&K.vis_dev, (size_t)c->n * K.tpv), "hipMalloc(visibility)");
+    if (!K.keys_dev)
+        LF_HIP(hipMalloc((void **)&K.keys_dev, sizeof(int32_t) * ((size_t)c->n * K.tpv)), "hipMalloc(visible keys)");
+    if (!K.count_dev) LF_HIP(hipMalloc((void **)&K.count_dev, sizeof(unsigned int)), "hipMalloc(key count)");
+    if (!K.count_host)
+        LF_HIP(hipHostMalloc((void **)&K.count_host, sizeof(unsigned int), hipHostMallocDefault), "hipHostMalloc(key count)");
+    if (!K.mask_host)
+        LF_HIP(hipHostMalloc((void **)&K.mask_host, (size_t)c->n, hipHostMallocDefault), "hipHostMalloc(mask)");
     if (!K.miss_dev) {
         LF_HIP(hipMalloc((void **)&K.miss_dev, sizeof(unsigned int)), "hipMalloc(page misses)");
         LF_HIP(hipMemset(K.miss_dev, 0, sizeof(unsigned int)), "hipMemset");
@@ -709,52 +724,59 @@ int lf_cache_update(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     const size_t page_bytes = (size_t)kPage * kPage * 4;
     ++K.calls;
 
-    // 1. visibility pass over the fine views (the resident ones need nothing)
-    std::vector<uint8_t> m((size_t)n, 0);
-    for (int32_t v = 0; v < nf; ++v) m[(size_t)v] = 1;
-    LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    LF_HIP(hipMemcpy(c->vmask, m.data(), (size_t)n, hipMemcpyHostToDevice), "copy view mask");
+    // 1. visibility pass over the fine views (the resident ones need nothing);
+    // its set bytes come back as a compacted list of tile keys
+    uint8_t *m = K.mask_host;
+    for (int32_t v = 0; v < n; ++v) m[v] = v < nf ? 1 : 0;
+    LF_HIP(hipMemcpyAsync(c->vmask, m, (size_t)n, hipMemcpyHostToDevice, s), "copy view mask");
     LF_HIP(hipMemsetAsync(K.vis_dev, 0, (size_t)n * K.tpv, s), "hipMemsetAsync");
+    LF_HIP(hipMemsetAsync(K.count_dev, 0, sizeof(unsigned int), s), "hipMemsetAsync");
     rc = render_impl(c, eyes, n_eyes, hfov_deg, res, nullptr, nullptr, nullptr, MODE_VISIBILITY, c->R, 0.5f, 0.5f,
                      1.0f, 0, s);
     if (rc) return rc;
-    K.vis.resize((size_t)n * K.tpv);
-    LF_HIP(hipMemcpyAsync(K.vis.data(), K.vis_dev, K.vis.size(), hipMemcpyDeviceToHost, s), "copy visibility");
+    LF_HIP(launch_vis_compact(K.vis_dev, (int64_t)n * K.tpv, K.keys_dev, K.count_dev, s), "k_vis_compact launch");
+    LF_HIP(hipMemcpyAsync(K.count_host, K.count_dev, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "copy key count");
     LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    K.vis_keys.resize(*K.count_host);
+    if (!K.vis_keys.empty()) {
+        LF_HIP(hipMemcpyAsync(K.vis_keys.data(), K.keys_dev, sizeof(int32_t) * K.vis_keys.size(),
+                              hipMemcpyDeviceToHost, s),
+               "copy visible keys");
+        LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    std::sort(K.vis_keys.begin(), K.vis_keys.end());  // view by view, tile by tile
 
     // 2. FIFO: fill pages with visible tiles not in the cache, view by view, up
     // to the budget; a page filled by this call is never taken again by it
-    int64_t visible = 0, hits = 0, evicted = 0;
+    int64_t hits = 0, evicted = 0;
+    const int64_t visible = (int64_t)K.vis_keys.size();
     std::vector<int64_t> touched;  // page-table entries changed by this call
     std::vector<int32_t> slots;
     std::vector<int64_t> keys;
     const int64_t ring = K.pages - K.fixed;
-    for (int32_t v = 0; v < nf; ++v)
-        for (int32_t t = 0; t < K.tpv; ++t) {
-            const int64_t key = (int64_t)v * K.tpv + t;
-            if (!K.vis[(size_t)key]) continue;
-            ++visible;
-            if (K.pt[(size_t)key] >= 0) {
-                ++hits;
-                continue;
-            }
-            if ((int64_t)slots.size() >= budget || (int64_t)slots.size() >= ring) continue;
-            const int64_t pg = K.next;
-            if (K.stamp[(size_t)pg] == K.calls) continue;  // the ring is full of this call's tiles
-            K.next = K.next + 1 < K.pages ? K.next + 1 : K.fixed;
-            const int64_t old = K.owner[(size_t)pg];
-            if (old >= 0) {
-                K.pt[(size_t)old] = -1;
-                touched.push_back(old);
-                ++evicted;
-            }
-            K.owner[(size_t)pg] = key;
-            K.stamp[(size_t)pg] = K.calls;
-            K.pt[(size_t)key] = (int32_t)pg;
-            touched.push_back(key);
-            slots.push_back((int32_t)pg);
-            keys.push_back(key);
+    for (const int32_t k32 : K.vis_keys) {
+        const int64_t key = k32;
+        if (K.pt[(size_t)key] >= 0) {
+            ++hits;
+            continue;
         }
+        if ((int64_t)slots.size() >= budget || (int64_t)slots.size() >= ring) continue;
+        const int64_t pg = K.next;
+        if (K.stamp[(size_t)pg] == K.calls) continue;  // the ring is full of this call's tiles
+        K.next = K.next + 1 < K.pages ? K.next + 1 : K.fixed;
+        const int64_t old = K.owner[(size_t)pg];
+        if (old >= 0) {
+            K.pt[(size_t)old] = -1;
+            touched.push_back(old);
+            ++evicted;
+        }
+        K.owner[(size_t)pg] = key;
+        K.stamp[(size_t)pg] = K.calls;
+        K.pt[(size_t)key] = (int32_t)pg;
+        touched.push_back(key);
+        slots.push_back((int32_t)pg);
+        keys.push_back(key);
+    }
     // each changed entry once, with its final value (an entry evicted and
     // filled again by this call appears twice in `touched`)
     std::sort(touched.begin(), touched.end());
@@ -791,29 +813,28 @@ int lf_cache_update(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     // 4. a fine view is available iff every tile it showed is in the cache;
     // the view mask takes the available fine views and the coarse level's fill-in
     std::vector<uint8_t> avail((size_t)std::max(nf, 1), 1);
+    for (const int32_t key : K.vis_keys)
+        if (K.pt[(size_t)key] < 0) avail[(size_t)(key / K.tpv)] = 0;
     int64_t missing_views = 0;
-    for (int32_t v = 0; v < nf; ++v) {
-        for (int32_t t = 0; t < K.tpv && avail[(size_t)v]; ++t) {
-            const size_t key = (size_t)v * K.tpv + t;
-            if (K.vis[key] && K.pt[key] < 0) avail[(size_t)v] = 0;
-        }
-        missing_views += !avail[(size_t)v];
-    }
+    for (int32_t v = 0; v < nf; ++v) missing_views += !avail[(size_t)v];
     if (nf < n) {
         if (nf > 0) {
-            rc = lf_two_level_mask(c, nf, avail.data(), m.data());
+            rc = lf_two_level_mask(c, nf, avail.data(), m);
             if (rc) return rc;
         } else {
-            std::fill(m.begin(), m.end(), 1);
+            std::fill(m, m + n, (uint8_t)1);
         }
     } else {
-        for (int32_t v = 0; v < n; ++v) m[(size_t)v] = avail[(size_t)v];
+        for (int32_t v = 0; v < n; ++v) m[v] = avail[(size_t)v];
     }
-    LF_HIP(hipMemcpyAsync(c->vmask, m.data(), (size_t)n, hipMemcpyHostToDevice, s), "copy view mask");
+    LF_HIP(hipMemcpyAsync(c->vmask, m, (size_t)n, hipMemcpyHostToDevice, s), "copy view mask");
     LF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (fine_available)
         for (int32_t v = 0; v < nf; ++v) fine_available[v] = avail[(size_t)v];
-    if (visible_out) std::memcpy(visible_out, K.vis.data(), K.vis.size());
+    if (visible_out) {
+        std::memset(visible_out, 0, (size_t)n * K.tpv);
+        for (const int32_t key : K.vis_keys) visible_out[key] = 1;
+    }
     if (stats) {
         stats[0] = visible;
         stats[1] = hits;
@@ -1265,6 +1286,10 @@ void lf_free(lf_ctx *c) {
     if (c->cache.host) (void)hipHostFree(c->cache.host);
     if (c->cache.pool) (void)hipFree(c->cache.pool);
     if (c->cache.vis_dev) (void)hipFree(c->cache.vis_dev);
+    if (c->cache.keys_dev) (void)hipFree(c->cache.keys_dev);
+    if (c->cache.count_dev) (void)hipFree(c->cache.count_dev);
+    if (c->cache.count_host) (void)hipHostFree(c->cache.count_host);
+    if (c->cache.mask_host) (void)hipHostFree(c->cache.mask_host);
     if (c->cache.stage_dev) (void)hipFree(c->cache.stage_dev);
     if (c->cache.stage_host) (void)hipHostFree(c->cache.stage_host);
     if (c->cache.miss_dev) (void)hipFree(c->cache.miss_dev);

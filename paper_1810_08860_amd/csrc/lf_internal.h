@@ -171,6 +171,8 @@ hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *v
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu);
 // RGBA8 [n][H][W] device images -> kPage x kPage tiles, [n][tiles_y][tiles_x][kPage][kPage]
 hipError_t launch_tile_images(const uint32_t *src, uint32_t *dst, int32_t n, int32_t W, int32_t H, hipStream_t s);
+// keys[0, *count) = indices of the set bytes of vis[0, n), any order (*count must start at 0)
+hipError_t launch_vis_compact(const uint8_t *vis, int64_t n, int32_t *keys, unsigned int *count, hipStream_t s);
 // tile cache update: pt[patch[k].x] = patch[k].y for k < n_patch, then staged tile k (16 KB) -> page slot[k]
 hipError_t launch_cache_apply(int32_t *pt, const int2 *patch, int32_t n_patch, const uint4 *staged,
                               const int32_t *slot, int32_t n_tiles, char *pool, hipStream_t s);

@@ -940,6 +940,30 @@ __global__ void k_cache_apply(int32_t *__restrict__ pt, const int2 *__restrict__
     for (int i = threadIdx.x; i < per; i += blockDim.x) dst[i] = src[i];
 }
 
+// Keys of the set bytes of vis[0, n) (the visible tiles of a visibility
+// pass), in no particular order: one atomic per wavefront reserves the slots
+// of its set lanes. keys holds room for n entries; *count starts at 0.
+__global__ void k_vis_compact(const uint8_t *__restrict__ vis, int64_t n, int32_t *__restrict__ keys,
+                              unsigned int *__restrict__ count) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool set = i < n && vis[i] != 0;
+        const uint64_t mask = __ballot(set);
+        unsigned int first = 0;
+        if (lane == 0 && mask) first = atomicAdd(count, (unsigned int)__popcll(mask));
+        first = __shfl(first, 0);
+        if (set) keys[first + __popcll(mask & below)] = (int32_t)i;
+    }
+}
+
+hipError_t launch_vis_compact(const uint8_t *vis, int64_t n, int32_t *keys, unsigned int *count, hipStream_t s) {
+    const int g = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_vis_compact, dim3(g), dim3(256), 0, s, vis, n, keys, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_cache_apply(int32_t *pt, const int2 *patch, int32_t n_patch, const uint4 *staged,
                               const int32_t *slot, int32_t n_tiles, char *pool, hipStream_t s) {
     hipLaunchKernelGGL(k_cache_apply, dim3(1 + n_tiles), dim3(256), 0, s, pt, patch, n_patch, staged, slot, pool);
