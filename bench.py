@@ -442,7 +442,7 @@ def streaming_leg(lf, torch, V, head_pos, head_rot, frames=270, budget=128, cach
         pos = head_pos + np.array([0.05 * f / 90.0, 0.0, 0.0])
         eyes = [(np.array(e.pos), np.array(e.rot).reshape(3, 3)) for e in lf.lf_stereo_eyes(pos, Rz @ head_rot, IPD)]
         t0 = time.perf_counter()
-        _, _, st = lf.lf_cache_update(ctx, eyes, HFOV, res, budget, n_fine=V.n)
+        _, _, st = lf.lf_cache_update(ctx, eyes, HFOV, res, budget, n_fine=V.n, want_visible=False)
         up_ms.append(1e3 * (time.perf_counter() - t0))
         ev[f][0].record()
         lf.lf_render(ctx, eyes, HFOV, res, out)

@@ -262,20 +262,21 @@ def lf_cache_config(ctx: Context, pages, first_resident=None):
     _check(lib().lf_cache_config(ctx.handle, int(pages), fr))
 
 
-def lf_cache_update(ctx: Context, eyes, hfov_deg, res, budget, n_fine=None, stream=None):
+def lf_cache_update(ctx: Context, eyes, hfov_deg, res, budget, n_fine=None, stream=None, want_visible=True):
     """One frame of tile streaming for these eyes (visibility pass, FIFO
     uploads within the budget, view mask). Returns (fine_available [n_fine],
-    visible [n_views, tiles] uint8, stats dict)."""
+    visible [n_views, tiles] uint8 or None, stats dict)."""
     e = make_eyes(eyes)
     r = _res(res, len(e))
     nf = ctx.n_views if n_fine is None else int(n_fine)
-    q = lf_query(ctx)
-    tiles = (q[1] // 64) ** 2
     avail = np.zeros(max(nf, 1), np.uint8)
-    vis = np.zeros((ctx.n_views, tiles), np.uint8)
+    vis = None
+    if want_visible:
+        q = lf_query(ctx)
+        vis = np.zeros((ctx.n_views, (q[1] // 64) ** 2), np.uint8)
     st = np.zeros(5, np.int64)
     _check(lib().lf_cache_update(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, int(budget), avail.ctypes.data,
-                                 vis.ctypes.data, st.ctypes.data, _stream(stream)))
+                                 None if vis is None else vis.ctypes.data, st.ctypes.data, _stream(stream)))
     keys = ("visible", "cached", "copied", "evicted", "views_unavailable")
     return avail[:nf], vis, dict(zip(keys, (int(x) for x in st)))
 
