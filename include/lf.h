@@ -146,7 +146,13 @@ typedef struct {
  * inverse-depth range. The caller may free every input on return.
  * Errors: LF_EINVAL for a null pointer, non-positive size, mesh_m < 2,
  * img_w != img_h, FOV outside (0,180), a frame not orthonormal to 1e-6, a
- * depth that is not finite and positive, or R <= 0; LF_ENOMEM; LF_EHIP.
+ * depth that is not finite and positive, or R <= 0; LF_EINVAL also when an
+ * image dimension reaches 2^24 or one view's share of any per-view array
+ * (the image in img_fmt or its second plane, the RGBA8 source image, the
+ * mesh cells in geo_fmt) reaches 2^32 bytes: the kernels address within a
+ * view with 32-bit offsets (e.g. RGBA32F views must be below 16384^2,
+ * RGBA8 below 32768^2). These size checks come before any device use.
+ * LF_ENOMEM; LF_EHIP.
  * On success *out owns the device data until lf_free.
  */
 int lf_load_views(const lf_views_desc *d, lf_ctx **out);
@@ -393,7 +399,10 @@ int lf_corrector_set_params(lf_corrector *c, const float *params);
 int lf_corrector_get_params(lf_corrector *c, float *params, int64_t *step);
 /* Corrected images (device out_rgb [P][3]); out_fallback (device [P] u8, 1 =
  * kept the render) and out_resid (device [P][3] FP32) may be NULL. A
- * threshold of 0 returns the render exactly. Asynchronous on hip_stream. */
+ * threshold of 0 returns the render exactly. Asynchronous on hip_stream.
+ * The outputs must not overlap the inputs (rgb, wsum, count) or each other:
+ * the kernel reads each tile's neighbourhood while other tiles are written
+ * (no in-place correction); LF_EINVAL otherwise. */
 int lf_corrector_apply(lf_corrector *c, const float *rgb, const float *wsum, const uint8_t *count, int32_t n_images,
                        int32_t W, int32_t H, float fallback_thresh, float *out_rgb, uint8_t *out_fallback,
                        float *out_resid, void *hip_stream);

@@ -75,6 +75,10 @@ int64_t img2_view_bytes(int fmt, int64_t W, int64_t H) {
 }
 size_t geo_bytes_per_cell(int fmt) { return fmt == LF_GEO_F32 ? 16 : 8; }
 
+// Limits of the per-view addressing of the kernels (at<T>, mul24 in lf_ray.h).
+constexpr int64_t kMaxViewBytes = (int64_t)1 << 32;
+constexpr int64_t kMaxDim = (int64_t)1 << 24;
+
 }  // namespace
 
 struct lf_ctx {
@@ -354,6 +358,21 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         return fail(LF_EINVAL, "RGTC needs image sizes that are multiples of 8 (got %dx%d)", d->img_w, d->img_h);
     if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
     if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
+    {
+        // the kernels address each view's share of an array with a 32-bit byte
+        // offset and form texel indices with 24-bit products
+        const int64_t W = d->img_w, H = d->img_h, Mc = d->mesh_m - 1;
+        if (W >= kMaxDim || H >= kMaxDim)
+            return fail(LF_EINVAL, "image size %lldx%lld: each dimension must be below 2^24", (long long)W,
+                        (long long)H);
+        const int64_t per_view[4] = {img_view_bytes(d->img_fmt, W, H), img2_view_bytes(d->img_fmt, W, H), 4 * W * H,
+                                     Mc * Mc * (int64_t)geo_bytes_per_cell(d->geo_fmt)};
+        static const char *what[4] = {"image", "second image plane", "RGBA8 source image", "mesh"};
+        for (int k = 0; k < 4; ++k)
+            if (per_view[k] >= kMaxViewBytes)
+                return fail(LF_EINVAL, "one view's %s takes %lld bytes; each view's share of an array must stay below 2^32 bytes",
+                            what[k], (long long)per_view[k]);
+    }
     const int32_t n = d->n_views, M = d->mesh_m;
     if (d->disk_ext)
         for (int64_t k = 0; k < 4 * (int64_t)n; ++k)

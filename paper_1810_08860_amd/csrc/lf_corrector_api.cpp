@@ -34,6 +34,17 @@ int cfail(int code, const char *fmt, ...) {
             return cfail(_e == hipErrorOutOfMemory ? LF_ENOMEM : LF_EHIP, "%s: %s", what, hipGetErrorString(_e)); \
     } while (0)
 
+// A byte range of a caller buffer (null pointers never overlap anything).
+struct Span {
+    const void *p;
+    int64_t bytes;
+};
+bool overlaps(const Span &a, const Span &b) {
+    if (!a.p || !b.p) return false;
+    const uintptr_t a0 = (uintptr_t)a.p, b0 = (uintptr_t)b.p;
+    return a0 < b0 + (uintptr_t)b.bytes && b0 < a0 + (uintptr_t)a.bytes;
+}
+
 constexpr int kDwSlots = 512;   // workgroups (and partial-sum slots) of a weight-gradient pass
 constexpr int kLossBlocks = 1024;
 
@@ -206,11 +217,31 @@ int lf_corrector_get_params(lf_corrector *c, float *params, int64_t *step) {
 int lf_corrector_apply(lf_corrector *c, const float *rgb, const float *wsum, const uint8_t *count, int32_t n_images,
                        int32_t W, int32_t H, float fallback_thresh, float *out_rgb, uint8_t *out_fallback,
                        float *out_resid, void *hip_stream) {
-    if (!c) return cfail(LF_EINVAL, "NULL corrector");
+    // buffer arguments first (host-side checks only), then the handle
     int rc = check_images(rgb, wsum, count, n_images, W, H);
     if (rc) return rc;
     if (!out_rgb) return cfail(LF_EINVAL, "out_rgb must not be NULL");
     if (std::isnan(fallback_thresh) || fallback_thresh < 0.0f) return cfail(LF_EINVAL, "fallback_thresh must be >= 0");
+    {
+        // the fused kernel reads a halo around each tile and the next tile's
+        // inputs while other workgroups write their outputs: outputs may not
+        // overlap any input
+        const int64_t P = (int64_t)n_images * W * H;
+        const Span in[3] = {{rgb, P * 12}, {wsum, P * 4}, {count, P}};
+        const Span out[3] = {{out_rgb, P * 12}, {out_fallback, P}, {out_resid, P * 12}};
+        static const char *in_name[3] = {"rgb", "wsum", "count"};
+        static const char *out_name[3] = {"out_rgb", "out_fallback", "out_resid"};
+        for (int i = 0; i < 3; ++i)
+            for (int o = 0; o < 3; ++o)
+                if (overlaps(in[i], out[o]))
+                    return cfail(LF_EINVAL, "%s overlaps %s: outputs must not share memory with inputs", out_name[o],
+                                 in_name[i]);
+        for (int o = 0; o < 3; ++o)
+            for (int q = o + 1; q < 3; ++q)
+                if (overlaps(out[o], out[q]))
+                    return cfail(LF_EINVAL, "%s overlaps %s: outputs must be distinct", out_name[o], out_name[q]);
+    }
+    if (!c) return cfail(LF_EINVAL, "NULL corrector");
     hipStream_t s = (hipStream_t)hip_stream;
     rc = pack(c, s);
     if (rc) return rc;

@@ -127,3 +127,59 @@ def test_stereo_eyes_matches_oracle_definition():
         lf.lf_stereo_eyes(p, bad, 0.064)
     with pytest.raises(lf.LFError):
         lf.lf_stereo_eyes(p, R, -1.0)
+
+
+@pytest.mark.parametrize("fmt,side,msg", [
+    (2, 16384, "image"),            # RGBA32F: 16 B x 2^28 texels = 2^32 bytes
+    (1, 23171, "image"),            # RGBA16F: 8 B x 23171^2 > 2^32
+    (0, 32768, "image"),            # RGBA8: 4 B x 2^30
+    (0, 1 << 24, "below 2^24"),     # a dimension of 2^24
+])
+def test_load_views_rejects_views_beyond_32bit_offsets(fmt, side, msg):
+    """Each view's share of a device array is addressed with a 32-bit byte
+    offset: a descriptor whose views reach 2^32 bytes (or a dimension of 2^24)
+    is rejected before anything is read or allocated (the image pointer is a
+    small dummy buffer here)."""
+    d, keep = _desc(img_w=side, img_h=side, img_fmt=fmt)
+    h = ctypes.c_void_p()
+    rc = lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h))
+    assert rc == lf.LF_EINVAL and h.value is None
+    assert msg in lf.lf_last_error()
+
+
+def test_load_views_size_limit_is_per_format():
+    """The largest RGBA16F view below the limit (23170^2) passes the size
+    check: the call then fails on a negative depth, a check that runs after
+    the size check and before any allocation."""
+    d, (c, r, img, z) = _desc(img_w=23170, img_h=23170, img_fmt=1)
+    z[0, 1, 1] = -1.0
+    h = ctypes.c_void_p()
+    assert lf.lib().lf_load_views(ctypes.byref(d), ctypes.byref(h)) == lf.LF_EINVAL
+    assert "depth" in lf.lf_last_error()
+
+
+def test_corrector_apply_rejects_aliased_buffers():
+    """The fused corrector reads each tile's neighbourhood while other tiles
+    are written, so an in-place call (or outputs overlapping each other) is
+    rejected before the handle is used: the buffers here are fake addresses
+    that are never dereferenced and the handle is NULL."""
+    L = lf.lib()
+    W, H, N = 64, 32, 2
+    P = N * W * H
+    base = 1 << 40
+    rgb, ws, cnt = base, base + 16 * P, base + 32 * P
+    out, fb, res = base + 64 * P, base + 80 * P, base + 96 * P
+    cases = [
+        (rgb, fb, res, "out_rgb overlaps rgb"),
+        (rgb + 12 * P - 4, fb, res, "out_rgb overlaps rgb"),      # last float of rgb
+        (out, ws, res, "out_fallback overlaps wsum"),
+        (out, fb, cnt, "out_resid overlaps count"),
+        (out, fb, out + 8, "out_rgb overlaps out_resid"),
+    ]
+    for o, f, r, msg in cases:
+        rc = L.lf_corrector_apply(None, rgb, ws, cnt, N, W, H, ctypes.c_float(8 / 255), o, f, r, None)
+        assert rc == lf.LF_EINVAL
+        assert msg in lf.lf_last_error(), (msg, lf.lf_last_error())
+    # adjacent but disjoint buffers pass the checks and stop at the NULL handle
+    rc = L.lf_corrector_apply(None, rgb, ws, cnt, N, W, H, ctypes.c_float(8 / 255), cnt + P, fb, res, None)
+    assert rc == lf.LF_EINVAL and "NULL corrector" in lf.lf_last_error()
