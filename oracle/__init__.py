@@ -86,7 +86,7 @@ def lib():
         L.orc_sample.argtypes = [ctypes.POINTER(_Views), i32, f64, f64, vp]
         L.orc_render_rays.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, vp, vp, vp, ctypes.POINTER(_Lists)]
         L.orc_ray_records.argtypes = [ctypes.POINTER(_Views), vp, vp, vp]
-        L.orc_prefilter.argtypes = [ctypes.POINTER(_Views), ctypes.POINTER(_Views), i32, f64, i32, vp, vp, i32,
+        L.orc_prefilter.argtypes = [ctypes.POINTER(_Views), ctypes.POINTER(_Views), i32, f64, vp, i32, vp, vp, i32,
                                     i64, vp, vp, vp]
         L.orc_basis.argtypes = [i32, f64]
         L.orc_yuv420_encode.argtypes = [i32, i32, i32, vp, vp, vp]
@@ -369,7 +369,8 @@ def basis(kind, d):
     return float(lib().orc_basis(BASIS[kind], float(d)))
 
 
-def prefilter(lbar: OracleViews, target: OracleViews, i, radius, disk_pts, pix_offs, kind="lanczos2", idx=None):
+def prefilter(lbar: OracleViews, target: OracleViews, i, radius, disk_pts, pix_offs, kind="lanczos2", idx=None,
+              aperture_ext=None):
     """Prefiltered colour (Sec. 5.1, Eq. (5)) of the pixels idx (all if None) of
     view i of the real-time model `target`: J samples pair the unit-disk points
     disk_pts (J,2) (scaled by the target disk radius) with pixel offsets
@@ -377,8 +378,12 @@ def prefilter(lbar: OracleViews, target: OracleViews, i, radius, disk_pts, pix_o
     point and passes through target view i's mesh point at the offset image
     position; `lbar` (the offline model) answers the ray query. A sample
     without a mesh point or whose ray no offline disk covers is left out of
-    both sums. Returns
-    {"rgb": (n,3), "wsum": (n,)} with wsum the denominator of Eq. (5)."""
+    both sums. aperture_ext (e+u, e-u, e+v, e-v) in metres makes view i's
+    aperture the oval disk of Sec. 4.4 instead of the circle of `radius`: a
+    unit-disk point maps by the extents of its quadrant, and its weight carries
+    that quadrant's area factor e_u e_v (Eq. (4) integrates over the disk's
+    area). Returns {"rgb": (n,3), "wsum": (n,)} with wsum the denominator of
+    Eq. (5)."""
     W, H = target.s.img_w, target.s.img_h
     if idx is None:
         idx = np.arange(W * H)
@@ -388,8 +393,14 @@ def prefilter(lbar: OracleViews, target: OracleViews, i, radius, disk_pts, pix_o
     assert dp.shape == po.shape
     rgb = np.zeros((len(idx), 3))
     ws = np.zeros(len(idx))
-    lib().orc_prefilter(ctypes.byref(lbar.s), ctypes.byref(target.s), int(i), float(radius), dp.shape[0], _p(dp),
-                        _p(po), BASIS[kind], len(idx), _p(idx), _p(rgb), _p(ws))
+    ext = None
+    if aperture_ext is not None:
+        ext = np.ascontiguousarray(aperture_ext, np.float64).reshape(4)
+        if not (np.isfinite(ext).all() and (ext > 0).all()):
+            raise ValueError("aperture extents must be finite and positive")
+    lib().orc_prefilter(ctypes.byref(lbar.s), ctypes.byref(target.s), int(i), float(radius),
+                        None if ext is None else _p(ext), dp.shape[0], _p(dp), _p(po), BASIS[kind], len(idx), _p(idx),
+                        _p(rgb), _p(ws))
     return {"rgb": rgb, "wsum": ws}
 
 

@@ -678,16 +678,23 @@ void orc_render_rays(const orc_views *V, int64_t n_rays, const double *o, const 
  *     sum_j rho_i(u_j, v_j) sigma(s_j, t_j) Lbar(o_j, e_j) / sum_j rho_i(u_j, v_j) sigma(s_j, t_j)
  *
  * over J sample pairs: (u_j, v_j) a point of view i's disk (the synthetic
- * aperture; disk_pts are points of the unit disk scaled by the target disk
- * radius), (s_j, t_j) a point of the pixel basis' support around the pixel
- * centre (pix_offs, in pixels). The ray origin o_j is the disk point in 3-D
+ * aperture, the real-time disk of Sec. 4.1 or Sec. 4.4; disk_pts are points
+ * (du, dv) of the unit disk, scaled by the target disk radius, or for an oval
+ * aperture with extents ext = (e+u, e-u, e+v, e-v) by the extents of their
+ * quadrant: u = du e+u for du >= 0, du e-u otherwise, v likewise), (s_j, t_j)
+ * a point of the pixel basis' support around the pixel centre (pix_offs, in
+ * pixels). The ray origin o_j is the disk point in 3-D
  * (c_i + u_j r_i + v_j u_i); the ray passes through the 3-D point of view i's
  * mesh that projects to image position (s_j, t_j) (the nearest hit of the ray
  * from c_i through that image point). Lbar is Eq. (2) over the offline model
  * (its own views, meshes and disks).
  *
  * Readings: rho is the linear falloff of Sec. 4.1 (1 - |(du, dv)| for a unit
- * disk point); sigma is separable, box (1 on |d| <= 1/2) or Lanczos-2
+ * disk point, which is also the oval kernel of Sec. 4.4 at the mapped point);
+ * Eq. (4) integrates over the disk's area, and a uniform point of the unit
+ * disk lands in an oval quadrant with density 1 / (e_u e_v), so an oval
+ * sample's weight also carries the factor e_u e_v of its quadrant (a circle's
+ * factor is the same for every sample and cancels); sigma is separable, box (1 on |d| <= 1/2) or Lanczos-2
  * (sinc(d) sinc(d/2) on |d| < 2); a sample whose image point has no mesh
  * point (outside the mesh domain), or whose ray no disk of the offline model
  * covers (Lbar undefined), is left out of both sums; a pixel whose
@@ -706,7 +713,7 @@ double orc_basis(int32_t basis, double d) {
     return fabs(d) <= 0.5 ? 1.0 : 0.0;
 }
 
-void orc_prefilter(const orc_views *Lbar, const orc_views *T, int32_t i, double radius, int32_t J,
+void orc_prefilter(const orc_views *Lbar, const orc_views *T, int32_t i, double radius, const double *ext, int32_t J,
                    const double *disk_pts, const double *pix_offs, int32_t basis, int64_t n_pix,
                    const int64_t *pix, double *rgb, double *wsum) {
 #ifdef _OPENMP
@@ -726,7 +733,14 @@ void orc_prefilter(const orc_views *Lbar, const orc_views *T, int32_t i, double 
             const double du = disk_pts[2 * j], dv = disk_pts[2 * j + 1];
             const double rho = 1.0 - sqrt(du * du + dv * dv);
             const double sigma = orc_basis(basis, pix_offs[2 * j]) * orc_basis(basis, pix_offs[2 * j + 1]);
-            const double wgt = rho * sigma;
+            /* the aperture point in metres along r and u: the circle of the
+             * given radius, or the oval whose quadrant holds (du, dv) */
+            const double su = ext ? (du >= 0.0 ? ext[0] : ext[1]) : radius;
+            const double sv = ext ? (dv >= 0.0 ? ext[2] : ext[3]) : radius;
+            /* uniform points of the unit disk land in an oval quadrant with
+             * density 1 / (su sv): the area factor restores the uniform
+             * measure du dv of Eq. (4) (constant for a circle, so left out) */
+            const double wgt = ext ? rho * sigma * su * sv : rho * sigma;
             if (!(rho > 0.0) || wgt == 0.0) continue;
             /* the 3-D point of view i's mesh seen at image position (s, t) */
             const double s = xc + pix_offs[2 * j], t = yc + pix_offs[2 * j + 1];
@@ -737,7 +751,7 @@ void orc_prefilter(const orc_views *Lbar, const orc_views *T, int32_t i, double 
             if (!isfinite(th)) continue;
             double o[3], e[3];
             for (int a = 0; a < 3; ++a) {
-                o[a] = c[a] + radius * (du * r[a] + dv * u[a]);
+                o[a] = c[a] + su * du * r[a] + sv * dv * u[a];
                 e[a] = c[a] + th * dir[a] - o[a];
             }
             double L[3], ws;

@@ -64,6 +64,11 @@ MUTATIONS = {
         "tiles[1] = (y0 / P) * tw + x1 / P;", "tiles[1] = (y0 / P) * tw + x0 / P;")]),
     "prefilter aperture without falloff": ("tests/test_oracle_prefilter.py", [(
         "const double rho = 1.0 - sqrt(du * du + dv * dv);", "const double rho = 1.0;")]),
+    "oval prefilter aperture without the quadrant area factor": ("tests/test_oracle_prefilter.py", [(
+        "const double wgt = ext ? rho * sigma * su * sv : rho * sigma;", "const double wgt = rho * sigma;")]),
+    "oval prefilter aperture maps u by the opposite quadrant": ("tests/test_oracle_prefilter.py", [(
+        "const double su = ext ? (du >= 0.0 ? ext[0] : ext[1]) : radius;",
+        "const double su = ext ? (du >= 0.0 ? ext[1] : ext[0]) : radius;")]),
 }
 
 

@@ -407,6 +407,119 @@ def test_reference_render_reduces_to_plain_query(tiny, tiny_oracle):
     b = oracle.render_reference(tiny_oracle, tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg, 256, 256, idx,
                                 ss=1, disk_scale=1.0)
     assert np.array_equal(a["rgb"], b)
-    c4 = oracle.render_reference(tiny_oracle, tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg, 256, 256, idx,
-                                 ss=2, disk_scale=2.0)
-    assert c4.shape == (len(idx), 3) and np.isfinite(c4).all() and (c4 >= 0).all() and (c4 <= 1).all()
+
+
+def _bilinear_by_hand(img, px, py):
+    """Bilinear sample of an RGBA8 image at texel coordinates (px, py):
+    texel centres at integers here, clamp-to-edge, RGB / 255."""
+    H, W = img.shape[:2]
+    x0, y0 = np.floor(px).astype(int), np.floor(py).astype(int)
+    fx, fy = (px - x0)[:, None], (py - y0)[:, None]
+    cx = lambda x: np.clip(x, 0, W - 1)
+    cy = lambda y: np.clip(y, 0, H - 1)
+    t = lambda x, y: img[cy(y), cx(x), :3].astype(np.float64) / 255.0
+    return ((1 - fx) * (1 - fy) * t(x0, y0) + fx * (1 - fy) * t(x0 + 1, y0)
+            + (1 - fx) * fy * t(x0, y0 + 1) + fx * fy * t(x0 + 1, y0 + 1))
+
+
+def _reference_camera_centre_ok(tiny, ref_fn, k=21, ss=4):
+    """Offline reference (Sec. 5.1's L-bar analogue) at a source camera: the
+    eye at view k's centre with its frame, FOV and resolution, and disks that
+    isolate view k even when doubled. Every sub-pixel ray then meets mesh k at
+    a point that projects back to its own image position, so pixel (x, y) is
+    the mean of the ss x ss bilinear samples of image k at texel coordinates
+    (x + (s + 1/2)/ss - 1/2, y + (t + 1/2)/ss - 1/2), a sub-ray outside the
+    mesh domain (the square of depth-pixel centres, [1/2, W - 1/2] in pixel
+    units here) counting as 0. Expected values by hand in numpy. ss is even
+    so that no sub-ray lies on the domain edge, where hit or miss is decided
+    by rounding."""
+    V = tiny.views
+    W = V.img_res
+    assert V.mesh_m == W
+    ov = oracle.OracleViews(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, 0.2 * lfsynth.min_nn(V.centres))
+    idx = np.concatenate([np.arange(0, W), np.arange(W, W * W, 37)])  # the top row (domain edge) + a spread
+    got = ref_fn(ov, V.centres[k], V.rot[k], V.src_fov_deg, W, W, idx, ss=ss, disk_scale=2.0)
+    x, y = (idx % W).astype(np.float64), (idx // W).astype(np.float64)
+    acc = np.zeros((len(idx), 3))
+    for t in range(ss):
+        for s_ in range(ss):
+            qx, qy = x + (s_ + 0.5) / ss, y + (t + 0.5) / ss  # continuous pixel position of the sub-ray
+            inside = ((qx > 0.5) & (qx < W - 0.5) & (qy > 0.5) & (qy < W - 0.5))[:, None]
+            acc += np.where(inside, _bilinear_by_hand(V.rgba8[k], qx - 0.5, qy - 0.5), 0.0)
+    return np.abs(got - acc / (ss * ss)).max() < 1e-12
+
+
+def _reference_by_records(tiny, ref_fn, ext_scale=None, ss=2, disk_scale=2.0):
+    """The reference rebuilt from per-view ray records: sub-pixel positions
+    (x + (s + 1/2)/ss, y + (t + 1/2)/ss) by hand, their rays (Eq. (1)), every
+    facing view's mesh hit and sample from a field with a disk radius large
+    enough to make every facing view a candidate, and the scaled falloff
+    rho = 1 - r / (disk_scale R) (or the oval's normalised radius with the
+    extents times disk_scale) by hand; each sub-ray is Eq. (2) over the views
+    with rho > 0 and a hit (0 if none), the pixel their mean."""
+    V = tiny.views
+    R_d = V.disk_radius
+    ext = None if ext_scale is None else oracle.disk_extents(V.centres, V.rot)[0] * ext_scale
+    ov = oracle.OracleViews.from_views(V, disk_ext=ext)
+    W = H = 96
+    hfov, pos, rot = tiny.hfov_deg, tiny.head_pos[0], tiny.head_rot[0]
+    idx = np.random.default_rng(3).integers(0, W * H, 24)
+    got = ref_fn(ov, pos, rot, hfov, W, H, idx, ss=ss, disk_scale=disk_scale)
+    wide = oracle.OracleViews.from_views(V, disk_radius=100.0)
+    want = np.zeros((len(idx), 3))
+    n_multi = 0
+    for q, p in enumerate(idx):
+        for t in range(ss):
+            for s_ in range(ss):
+                pxy = np.array([[p % W + (s_ + 0.5) / ss, p // W + (t + 0.5) / ss]])
+                o, e = oracle.eye_rays(pos, rot, hfov, W, H, pxy)
+                rec = oracle.records(wide, o[0], e[0])
+                if ext is None:
+                    rho = 1.0 - np.hypot(rec["u"], rec["v"]) / (disk_scale * R_d)
+                else:
+                    eu = np.where(rec["u"] >= 0, ext[:, 0], ext[:, 1]) * disk_scale
+                    ev = np.where(rec["v"] >= 0, ext[:, 2], ext[:, 3]) * disk_scale
+                    rho = 1.0 - np.hypot(rec["u"] / eu, rec["v"] / ev)
+                use = (rec["a"] > 0) & (rho > 0) & (rec["hit"] == 1)
+                n_multi += use.sum() >= 2
+                if use.any():
+                    want[q] += (rho[use, None] * rec["rgb"][use]).sum(0) / rho[use].sum()
+    want /= ss * ss
+    assert n_multi > len(idx)  # most sub-rays blend several views: the falloff's scale matters
+    return np.abs(got - want).max() < 1e-10
+
+
+def _ref_offsets_without_half(ov, pos, rot, hfov, W, H, idx, ss=4, disk_scale=2.0):
+    """A planted mistake: sub-pixel rays at s / ss instead of (s + 1/2) / ss."""
+    idx = np.asarray(idx, np.int64)
+    base = np.stack([(idx % W).astype(np.float64), (idx // W).astype(np.float64)], 1)
+    offs = np.arange(ss) / ss
+    sub = np.stack(np.meshgrid(offs, offs, indexing="xy"), -1).reshape(-1, 2)
+    o, e = oracle.eye_rays(pos, rot, hfov, W, H, (base[:, None, :] + sub[None, :, :]).reshape(-1, 2))
+    big = ov.with_disk_radius(ov.s.disk_radius * disk_scale)
+    if ov.disk_ext is not None:
+        big = big.with_disk_extents(ov.disk_ext * disk_scale)
+    return oracle.render_rays(big, o, e)["rgb"].reshape(len(idx), ss * ss, 3).mean(1)
+
+
+def _ref_unscaled_disks(ov, pos, rot, hfov, W, H, idx, ss=4, disk_scale=2.0):
+    """A planted mistake: the disks keep their real-time size."""
+    return oracle.render_reference(ov, pos, rot, hfov, W, H, idx, ss=ss, disk_scale=1.0)
+
+
+def test_reference_render_at_camera_centre_is_subpixel_box_filter(tiny):
+    assert _reference_camera_centre_ok(tiny, oracle.render_reference)
+    assert _reference_camera_centre_ok(tiny, oracle.render_reference, ss=2)
+    assert not _reference_camera_centre_ok(tiny, _ref_offsets_without_half)
+
+
+def test_reference_render_equals_scaled_disk_blend_of_subrays(tiny):
+    assert _reference_by_records(tiny, oracle.render_reference)
+    assert _reference_by_records(tiny, oracle.render_reference, ss=3, disk_scale=1.5)
+    assert not _reference_by_records(tiny, _ref_offsets_without_half)
+    assert not _reference_by_records(tiny, _ref_unscaled_disks)
+
+
+def test_reference_render_scales_oval_extents(tiny):
+    assert _reference_by_records(tiny, oracle.render_reference, ext_scale=1.0)
+    assert not _reference_by_records(tiny, _ref_unscaled_disks, ext_scale=1.0)

@@ -177,3 +177,113 @@ def test_prefilter_python_brute_force_agrees_on_tiny_field():
             den += w
         assert got["wsum"][q] == pytest.approx(den, abs=1e-9)
         assert np.allclose(got["rgb"][q], num / den if den != 0 else 0.0, atol=1e-9)
+
+
+# ----------------------------------------------------------------------------- oval apertures (Sec. 4.4 disks)
+
+_EXT = np.array([0.031, 0.017, 0.024, 0.041])  # e+u, e-u, e+v, e-v in metres, deliberately unequal
+
+
+def test_oval_aperture_with_equal_extents_is_the_circle(tiny):
+    """Four equal extents r make the oval the circle of radius r: the same ray
+    origins and the same ratio; every weight carries the constant factor r^2."""
+    V = tiny.views
+    ov = oracle.OracleViews.from_views(V)
+    dp, po = lfsynth.prefilter_samples(9, 8, 2.0)
+    idx = np.arange(0, V.img_res ** 2, 211)
+    r = 0.037
+    a = oracle.prefilter(ov, ov, 17, r, dp, po, "lanczos2", idx)
+    b = oracle.prefilter(ov, ov, 17, 1.0, dp, po, "lanczos2", idx, aperture_ext=[r, r, r, r])
+    assert (a["wsum"] != 0).mean() > 0.9
+    assert np.abs(a["rgb"] - b["rgb"]).max() < 1e-12
+    assert np.allclose(b["wsum"], r * r * a["wsum"], rtol=1e-12, atol=0)
+
+
+def test_oval_aperture_maps_unit_disk_points_by_quadrant(tiny):
+    """A one-sample prefilter returns the offline query of its single ray. The
+    oval sends a unit-disk point (du, dv) to du e_u along r and dv e_v along u,
+    with e_u = e+u for du >= 0 else e-u (e_v likewise): the same ray as a
+    circle aperture of any radius Rc with the point (du e_u, dv e_v) / Rc."""
+    V = tiny.views
+    ov = oracle.OracleViews.from_views(V)
+    idx = np.arange(0, V.img_res ** 2, 173)
+    eu = lambda du: _EXT[0] if du >= 0 else _EXT[1]
+    ev = lambda dv: _EXT[2] if dv >= 0 else _EXT[3]
+    n_checked = 0
+    for du, dv in ((0.6, 0.0), (-0.6, 0.0), (0.0, 0.5), (0.0, -0.5), (0.4, -0.5), (-0.3, 0.7)):
+        oval = oracle.prefilter(ov, ov, 30, 1.0, [[du, dv]], [[0.2, -0.1]], "box", idx, aperture_ext=_EXT)
+        Rc = 0.1
+        circ = oracle.prefilter(ov, ov, 30, Rc, [[du * eu(du) / Rc, dv * ev(dv) / Rc]], [[0.2, -0.1]], "box", idx)
+        ok = oval["wsum"] != 0
+        assert np.array_equal(ok, circ["wsum"] != 0)
+        assert np.abs(oval["rgb"] - circ["rgb"]).max() < 1e-12
+        n_checked += ok.sum()
+    assert n_checked > 6 * 0.8 * len(idx)
+
+
+def test_oval_aperture_weights_quadrants_by_their_area(tiny):
+    """Eq. (4) integrates over the disk's area; a uniform point of the unit
+    disk lands in an oval quadrant with density 1 / (e_u e_v), so the weight of
+    a sample is rho sigma e_u e_v. Two samples in quadrants of different area:
+    the two-sample estimate is the mean of the one-sample results weighted so,
+    by hand."""
+    V = tiny.views
+    ov = oracle.OracleViews.from_views(V)
+    idx = np.arange(0, V.img_res ** 2, 97)
+    pts = np.array([[0.5, 0.3], [-0.2, -0.6]])
+    offs = np.array([[0.1, 0.3], [-0.4, 0.2]])
+    one = [oracle.prefilter(ov, ov, 44, 1.0, pts[j:j + 1], offs[j:j + 1], "lanczos2", idx, aperture_ext=_EXT)
+           for j in range(2)]
+    both = oracle.prefilter(ov, ov, 44, 1.0, pts, offs, "lanczos2", idx, aperture_ext=_EXT)
+    area = np.array([_EXT[0] * _EXT[2], _EXT[1] * _EXT[3]])
+    rho = 1 - np.hypot(pts[:, 0], pts[:, 1])
+    sig = np.array([oracle.basis("lanczos2", a) * oracle.basis("lanczos2", b) for a, b in offs])
+    w = rho * sig * area
+    ok = (one[0]["wsum"] != 0) & (one[1]["wsum"] != 0)
+    assert ok.mean() > 0.8
+    want = (w[0] * one[0]["rgb"][ok] + w[1] * one[1]["rgb"][ok]) / w.sum()
+    assert np.abs(both["rgb"][ok] - want).max() < 1e-12
+    assert np.allclose(both["wsum"][ok], w.sum(), rtol=1e-12, atol=0)
+    # without the area factor the estimate differs where the two rays disagree
+    plain = (rho[0] * sig[0] * one[0]["rgb"][ok] + rho[1] * sig[1] * one[1]["rgb"][ok]) / (rho * sig).sum()
+    assert np.abs(plain - want).max() > 1e-3
+
+
+def test_oval_prefilter_python_brute_force_agrees_on_tiny_field():
+    """Eq. (5) with an oval aperture by plain Python loops on a 12-view field:
+    the unit-disk point mapped by its quadrant's extents, weights with the
+    quadrant's area factor, mesh points and the offline query by linear
+    solves over every triangle."""
+    rng = np.random.default_rng(8)
+    c, R = lfsynth.rig(12, 0.35)
+    M, Wi = 6, 9
+    z = rng.uniform(0.8, 2.0, (12, M, M)).astype(np.float32)
+    img = rng.integers(0, 256, (12, Wi, Wi, 4)).astype(np.uint8)
+    R_d = 1.5 * lfsynth.mean_nn(c)
+    ov = oracle.OracleViews(c, R, img, z, 120.0, R_d)
+    dp, po = lfsynth.prefilter_samples(4, 8, 2.0)
+    i = 7
+    ext = np.array([0.9, 0.5, 0.7, 1.2]) * R_d
+    idx = np.array([11, 30, 40, 49, 62])
+    got = oracle.prefilter(ov, ov, i, 1.0, dp, po, "lanczos2", idx, aperture_ext=ext)
+    ts = np.tan(np.radians(60))
+    lz = lambda x: np.sinc(x) * np.sinc(x / 2) if abs(x) < 2 else 0.0
+    for q, p in enumerate(idx):
+        num, den = np.zeros(3), 0.0
+        for (du, dv), (ds, dt) in zip(dp, po):
+            eu = ext[0] if du >= 0 else ext[1]
+            ev = ext[2] if dv >= 0 else ext[3]
+            rho = 1 - np.hypot(du, dv)
+            w = rho * lz(ds) * lz(dt) * eu * ev
+            s, t = p % Wi + 0.5 + ds, p // Wi + 0.5 + dt
+            P = _py_mesh_point(c, R, z, 120.0, i, (2 * s / Wi - 1) * ts, (1 - 2 * t / Wi) * ts)
+            if P is None or rho <= 0 or w == 0:
+                continue
+            o = c[i] + du * eu * R[i][:, 0] + dv * ev * R[i][:, 1]
+            col, wq = _py_query(c, R, img, z, 120.0, R_d, o, P - o)
+            if wq <= 0:
+                continue
+            num += w * col
+            den += w
+        assert got["wsum"][q] == pytest.approx(den, abs=1e-12)
+        assert np.allclose(got["rgb"][q], num / den if den != 0 else 0.0, atol=1e-9)
