@@ -261,12 +261,17 @@ enum { LF_BASIS_BOX = 0, LF_BASIS_LANCZOS2 = 1 };
  * Light field prefilter (Sec. 5, Eqs. (4)-(5)). For every pixel (x, y) of each
  * listed view i the result is the Monte Carlo ratio estimate
  *
- *   sum_j rho(du_j, dv_j) sigma(ds_j) sigma(dt_j) Lbar(o_j, e_j) / sum_j (same weights)
+ *   sum_j a_j rho(du_j, dv_j) sigma(ds_j) sigma(dt_j) Lbar(o_j, e_j) / sum_j (same weights)
  *
  * with rho = 1 - |(du, dv)| the linear disk falloff and sigma the basis. The
- * ray of sample j starts at the point o_j = c_i + radius (du_j r_i + dv_j u_i)
- * of view i's disk (the synthetic aperture of the real-time model, radius in
- * metres) and passes through the point of view i's mesh that view i sees at
+ * ray of sample j starts at the point o_j = c_i + su_j du_j r_i + sv_j dv_j u_i
+ * of view i's disk, the synthetic aperture of the real-time model (metres):
+ * for the circle of radius `radius` su = sv = radius and a_j = 1; for an oval
+ * disk (Sec. 4.4) with extents aperture_ext[k] = (e+u, e-u, e+v, e-v) of the
+ * k-th listed view, su = e+u for du >= 0 and e-u otherwise, sv = e+v for
+ * dv >= 0 and e-v otherwise, and a_j = su sv (a uniform point of the unit
+ * disk lands in an oval quadrant with density 1 / (su sv); the factor keeps
+ * the disk-area measure of Eq. (4)). The ray passes through the point of view i's mesh that view i sees at
  * image position (x + 1/2 + ds_j, y + 1/2 + dt_j) (pixel units). Lbar is the
  * query of Eq. (2) over the context's views, meshes and disks (the offline
  * model). A sample whose image position has no mesh point (outside the mesh
@@ -276,6 +281,9 @@ enum { LF_BASIS_BOX = 0, LF_BASIS_LANCZOS2 = 1 };
  *
  *   views      host int32 [n_views], indices of the views to prefilter (any order,
  *              repeats allowed); each is rendered at the context's image size
+ *   radius     circle aperture radius in metres (> 0); unused with aperture_ext
+ *   aperture_ext  host float64 [n_views][4] oval extents of the listed views
+ *              (each finite and > 0, e.g. from lf_disk_extents), or NULL for circles
  *   disk_pts   host float64 [J][2], points of the unit disk (|p| <= 1)
  *   pix_offs   host float64 [J][2], offsets from the pixel centre in pixels (|.| <= 64)
  *   basis      LF_BASIS_BOX or LF_BASIS_LANCZOS2
@@ -284,11 +292,12 @@ enum { LF_BASIS_BOX = 0, LF_BASIS_LANCZOS2 = 1 };
  *
  * Source images must be square. Asynchronous on hip_stream; LF_EINVAL for a
  * NULL pointer, an empty list, a view index out of range, a non-positive
- * radius, a disk point outside the unit disk or an unknown basis.
+ * radius (circles) or extent (ovals), a disk point outside the unit disk or an
+ * unknown basis.
  */
-int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *disk_pts,
-                 const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb, float *out_wsum,
-                 void *hip_stream);
+int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *aperture_ext,
+                 const double *disk_pts, const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb,
+                 float *out_wsum, void *hip_stream);
 
 /*
  * Offline reference render (the analogue of the high-quality offline query of

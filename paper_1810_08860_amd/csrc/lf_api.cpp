@@ -244,6 +244,7 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
         E.super_off = supers;
         E.pix_off = pix_off;
         E.src_view = -1;
+        E.pf_w = 1.0f;
         tiles += E.tiles_x * E.tiles_y;
         supers += E.supers_x * E.supers_y;
         pix_off += (int64_t)E.W * E.H;
@@ -885,16 +886,21 @@ int lf_cache_page_misses(lf_ctx *c, uint64_t *misses) {
     return LF_OK;
 }
 
-int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *disk_pts,
-                 const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb, float *out_wsum,
-                 void *hip_stream) {
+int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius, const double *aperture_ext,
+                 const double *disk_pts, const double *pix_offs, int32_t n_samples, int32_t basis, float *out_rgb,
+                 float *out_wsum, void *hip_stream) {
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (!views || !disk_pts || !pix_offs) return fail(LF_EINVAL, "views, disk_pts and pix_offs must not be NULL");
     if (!out_rgb || !out_wsum) return fail(LF_EINVAL, "out_rgb and out_wsum must not be NULL");
     if (n_views <= 0) return fail(LF_EINVAL, "n_views must be positive (got %d)", n_views);
     if (n_samples <= 0 || n_samples > (1 << 20)) return fail(LF_EINVAL, "n_samples must be in [1, 2^20] (got %d)", n_samples);
     if (basis != LF_BASIS_BOX && basis != LF_BASIS_LANCZOS2) return fail(LF_EINVAL, "unknown basis %d", basis);
-    if (!(radius > 0.0) || !std::isfinite(radius)) return fail(LF_EINVAL, "radius must be finite and > 0");
+    if (!aperture_ext && (!(radius > 0.0) || !std::isfinite(radius)))
+        return fail(LF_EINVAL, "radius must be finite and > 0");
+    if (aperture_ext)
+        for (int64_t k = 0; k < 4 * (int64_t)n_views; ++k)
+            if (!(aperture_ext[k] > 0.0) || !std::isfinite(aperture_ext[k]))
+                return fail(LF_EINVAL, "aperture_ext[%d][%d] is not finite and positive", (int)(k / 4), (int)(k % 4));
     if (c->img_w != c->img_h) return fail(LF_EINVAL, "the prefilter needs square source images");
     for (int32_t k = 0; k < n_views; ++k)
         if (views[k] < 0 || views[k] >= c->n) return fail(LF_EINVAL, "views[%d] = %d out of range", k, views[k]);
@@ -911,6 +917,7 @@ int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius
     const double hfov = 2.0 * std::atan(c->tan_s) * 180.0 / M_PI;
     std::vector<lf_eye> eyes(kMaxEyesPerLaunch);
     std::vector<int32_t> res(2 * kMaxEyesPerLaunch);
+    double pu[kMaxEyesPerLaunch], pv[kMaxEyesPerLaunch], pw[kMaxEyesPerLaunch];
     for (int32_t j = 0; j < n_samples; ++j) {
         const double du = disk_pts[2 * j], dv = disk_pts[2 * j + 1], ds = pix_offs[2 * j], dt = pix_offs[2 * j + 1];
         const double rho = 1.0 - std::sqrt(du * du + dv * dv);
@@ -918,11 +925,19 @@ int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius
         if (!(rho > 0.0) || wgt == 0.0) continue;
         for (int32_t k0 = 0; k0 < n_views; k0 += kMaxEyesPerLaunch) {
             const int32_t nk = std::min(kMaxEyesPerLaunch, n_views - k0);
-            // one eye per target view: at the sample's point of the view's disk, with the view's frame
+            // one eye per target view: at the sample's point of the view's disk
+            // (the circle of `radius`, or the oval whose quadrant holds (du, dv)),
+            // with the view's frame
             for (int32_t k = 0; k < nk; ++k) {
                 const double *vc = &c->h_vt[12 * (size_t)views[k0 + k]];
                 const double *R = vc + 3;
-                for (int a = 0; a < 3; ++a) eyes[k].pos[a] = vc[a] + radius * (du * R[3 * a] + dv * R[3 * a + 1]);
+                const double *ext = aperture_ext ? aperture_ext + 4 * (size_t)(k0 + k) : nullptr;
+                pu[k] = (ext ? (du >= 0.0 ? ext[0] : ext[1]) : radius) * du;
+                pv[k] = (ext ? (dv >= 0.0 ? ext[2] : ext[3]) : radius) * dv;
+                // uniform unit-disk points land in an oval quadrant with density
+                // 1 / (e_u e_v): the area factor restores Eq. (4)'s measure
+                pw[k] = ext ? (du >= 0.0 ? ext[0] : ext[1]) * (dv >= 0.0 ? ext[2] : ext[3]) : 1.0;
+                for (int a = 0; a < 3; ++a) eyes[k].pos[a] = vc[a] + pu[k] * R[3 * a] + pv[k] * R[3 * a + 1];
                 std::memcpy(eyes[k].rot, R, sizeof(double) * 9);
                 res[2 * k] = c->img_w;
                 res[2 * k + 1] = c->img_h;
@@ -934,8 +949,9 @@ int lf_prefilter(lf_ctx *c, const int32_t *views, int32_t n_views, double radius
                 E.src_view = views[k0 + k];
                 E.off_x = (float)ds;
                 E.off_y = (float)dt;
-                E.par_u = (float)(radius * du);
-                E.par_v = (float)(radius * dv);
+                E.par_u = (float)pu[k];
+                E.par_v = (float)pv[k];
+                E.pf_w = (float)pw[k];
             }
             RenderArgs a = base_args(c, c->R);
             int rc = prep_and_cull(c, ch, a, c->R, s);

@@ -38,6 +38,7 @@ struct EyeParam {
     int32_t src_view;
     float off_x, off_y;
     float par_u, par_v;
+    float pf_w;        // prefilter eyes: weight factor of the eye's sample (an oval quadrant's area; 1 for circles)
     // batches: first slot of this eye's band in each XCD's tile queue (band k
     // = tile rows [k tiles_y / kXcds, (k + 1) tiles_y / kXcds); queue x holds
     // band (x + e / 2) mod kXcds of eye e)

@@ -692,14 +692,16 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     if (IMG == 5 && MODE != MODE_VISIBILITY && n_miss > 0 && a.page_miss) atomicAdd(a.page_miss, (unsigned)n_miss);
     if (MODE == MODE_VISIBILITY) return;
     if (MODE == MODE_PREFILTER) {
-        // one sample of Eq. (5): out += scale * L, wsum += scale where L is defined
+        // one sample of Eq. (5): out += w * L, wsum += w where L is defined,
+        // w = the sample's rho sigma times the eye's aperture-area factor
         if (inside && ws > 0.0f) {
             const float k = texel_scale<IMG>() * fast_rcp(ws);
+            const float sw = a.scale * E.pf_w;
             float *o = a.out_rgb + pix * 3;
-            o[0] = fmaf(a.scale, accr * k, o[0]);
-            o[1] = fmaf(a.scale, accg * k, o[1]);
-            o[2] = fmaf(a.scale, accb * k, o[2]);
-            a.out_wsum[pix] += a.scale;
+            o[0] = fmaf(sw, accr * k, o[0]);
+            o[1] = fmaf(sw, accg * k, o[1]);
+            o[2] = fmaf(sw, accb * k, o[2]);
+            a.out_wsum[pix] += sw;
         }
         return;
     }

@@ -66,7 +66,7 @@ def lib():
         L.lf_set_tune.argtypes = [vp, ctypes.POINTER(lf_tune)]
         L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
         L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
-        L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
+        L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, vp, i32, i32, vp, vp, vp]
         L.lf_set_view_mask.argtypes = [vp, vp]
         L.lf_two_level_mask.argtypes = [vp, i32, vp, vp]
         L.lf_cache_config.argtypes = [vp, ctypes.c_int64, i32]
@@ -299,15 +299,22 @@ def lf_cache_page_misses(ctx: Context):
 BASIS = {"box": 0, "lanczos2": 1}
 
 
-def lf_prefilter(ctx: Context, views, radius, disk_pts, pix_offs, basis, out_rgb, out_wsum, stream=None):
+def lf_prefilter(ctx: Context, views, radius, disk_pts, pix_offs, basis, out_rgb, out_wsum, stream=None,
+                 aperture_ext=None):
     """Prefilter (Sec. 5, Eq. (5)) of the listed views; outputs are device
-    buffers of n_views x img_h x img_w RGB floats and weight sums."""
+    buffers of n_views x img_h x img_w RGB floats and weight sums. The aperture
+    is the circle of `radius`, or with aperture_ext (n_views, 4) each listed
+    view's oval disk (e+u, e-u, e+v, e-v)."""
     v = np.ascontiguousarray(views, np.int32).reshape(-1)
     dp = np.ascontiguousarray(disk_pts, np.float64).reshape(-1, 2)
     po = np.ascontiguousarray(pix_offs, np.float64).reshape(-1, 2)
     if dp.shape != po.shape:
         raise ValueError("disk_pts and pix_offs must both be (J, 2)")
-    _check(lib().lf_prefilter(ctx.handle, v.ctypes.data, len(v), float(radius), dp.ctypes.data, po.ctypes.data,
+    ext = None
+    if aperture_ext is not None:
+        ext = np.ascontiguousarray(aperture_ext, np.float64).reshape(len(v), 4)
+    _check(lib().lf_prefilter(ctx.handle, v.ctypes.data, len(v), float(radius),
+                              None if ext is None else ext.ctypes.data, dp.ctypes.data, po.ctypes.data,
                               dp.shape[0], BASIS[basis] if isinstance(basis, str) else int(basis), _ptr(out_rgb),
                               _ptr(out_wsum), _stream(stream)))
 

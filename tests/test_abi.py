@@ -101,7 +101,7 @@ def test_null_context_and_arguments():
     assert L.lf_disk_extents(8, None, None, 1.0, None) == lf.LF_EINVAL
     v = np.zeros(1, np.int32)
     dp = np.zeros(2)
-    assert L.lf_prefilter(None, v.ctypes.data, 1, 0.05, dp.ctypes.data, dp.ctypes.data, 1, 1, 1, 1,
+    assert L.lf_prefilter(None, v.ctypes.data, 1, 0.05, None, dp.ctypes.data, dp.ctypes.data, 1, 1, 1, 1,
                           None) == lf.LF_EINVAL
     assert "context" in lf.lf_last_error()
     assert L.lf_cache_config(None, 16, 0) == lf.LF_EINVAL

@@ -19,32 +19,34 @@ from lfcheck import gpu_context, torch_mod
 pytestmark = pytest.mark.gpu
 
 
-def gpu_prefilter(ctx, views, radius, dp, po, basis, npx):
+def gpu_prefilter(ctx, views, radius, dp, po, basis, npx, ext=None):
     torch = torch_mod()
     from paper_1810_08860_amd import lf
     n = len(views)
     rgb = torch.full((n * npx * 3,), -1.0, dtype=torch.float32, device="cuda")
     ws = torch.full((n * npx,), -1.0, dtype=torch.float32, device="cuda")
-    lf.lf_prefilter(ctx, views, radius, dp, po, basis, rgb, ws)
+    lf.lf_prefilter(ctx, views, radius, dp, po, basis, rgb, ws,
+                    aperture_ext=None if ext is None else np.asarray(ext)[list(views)])
     torch.cuda.synchronize()
     return (rgb.view(n, npx, 3).cpu().numpy().astype(np.float64),
             ws.view(n, npx).cpu().numpy().astype(np.float64))
 
 
-def unstable(lbar, i, radius, dp, po, basis, idx, ref):
+def unstable(lbar, i, radius, dp, po, basis, idx, ref, ext=None):
     span = np.zeros(len(idx))
     for d in ((1e-3, 0.0), (-1e-3, 0.0), (0.0, 1e-3), (0.0, -1e-3)):
-        r = oracle.prefilter(lbar, lbar, i, radius, dp, po + np.array(d), basis, idx)
+        r = oracle.prefilter(lbar, lbar, i, radius, dp, po + np.array(d), basis, idx,
+                             aperture_ext=None if ext is None else ext[i])
         span = np.maximum(span, np.abs(r["rgb"] - ref).max(1))
     return span > 1e-2
 
 
-def check_views(ov, ctx, views, radius, dp, po, basis, idx, npx, label):
-    got, gws = gpu_prefilter(ctx, views, radius, dp, po, basis, npx)
+def check_views(ov, ctx, views, radius, dp, po, basis, idx, npx, label, ext=None):
+    got, gws = gpu_prefilter(ctx, views, radius, dp, po, basis, npx, ext)
     assert np.isfinite(got).all() and np.isfinite(gws).all()
     for q, i in enumerate(views):
-        ref = oracle.prefilter(ov, ov, i, radius, dp, po, basis, idx)
-        bad = unstable(ov, i, radius, dp, po, basis, idx, ref["rgb"])
+        ref = oracle.prefilter(ov, ov, i, radius, dp, po, basis, idx, aperture_ext=None if ext is None else ext[i])
+        bad = unstable(ov, i, radius, dp, po, basis, idx, ref["rgb"], ext)
         err = np.abs(got[q][idx] - ref["rgb"]).max(1)
         werr = np.abs(gws[q][idx] - ref["wsum"])
         print(f"{label} view {i}: {len(idx)} px, max err stable {err[~bad].max():.3g}, all {err.max():.3g}, "
@@ -90,6 +92,21 @@ def test_tiny_prefilter_with_oval_offline_disks(tiny, tiny_oracle):
         check_views(ov, ctx, [7, 58], V.disk_radius, dp, po, "lanczos2", idx, V.img_res ** 2, "tiny oval")
     finally:
         ctx.close()
+
+
+def test_tiny_prefilter_with_oval_apertures(tiny, tiny_oracle, ctx32):
+    """The synthetic aperture as the real-time model's own oval disks (Sec. 5.1
+    uses the disks of the reconstruction; Sec. 4.4 makes them ovals): each
+    listed view's unit-disk samples map by its extents quadrant by quadrant,
+    weighted by the quadrant's area (the oracle's Delaunay 1-ring extents at
+    0.8 of their size, given to both sides). Views listed out of order and
+    repeated, so each eye of a launch has its own aperture."""
+    V = tiny.views
+    ext = 0.8 * oracle.disk_extents(V.centres, V.rot)[0]
+    dp, po = lfsynth.prefilter_samples(29, 16, 2.0)
+    idx = np.arange(0, V.img_res ** 2, 19)
+    check_views(tiny_oracle, ctx32, [50, 9, 50], 1.0, dp, po, "lanczos2", idx, V.img_res ** 2, "tiny oval aperture",
+                ext=ext)
 
 
 def test_point_aperture_delta_basis_is_identity(tiny):
