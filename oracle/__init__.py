@@ -93,6 +93,7 @@ def lib():
         L.orc_rgtc_encode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
         L.orc_rgtc_decode.argtypes = [i32, i32, i32, vp, vp, vp, vp]
         L.orc_visible_tiles.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, i32, vp]
+        L.orc_visible_tiles_band.argtypes = [ctypes.POINTER(_Views), i64, vp, vp, i32, f64, vp, vp]
         L.orc_basis.restype = f64
         L.orc_views_size.restype = i32
         L.orc_rec_size.restype = i32
@@ -273,14 +274,44 @@ def visible_tiles(ov: OracleViews, pos, rot, hfov_deg, W, H, page=64, idx=None):
     return vis
 
 
-def render_reference(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, ss: int = 4, disk_scale: float = 2.0):
+def visible_tiles_band(ov: OracleViews, pos, rot, hfov_deg, W, H, page=64, margin=1e-3, jitter=1e-3):
+    """The visible tiles of an eye split by how firmly they are decided, for
+    comparison with a float implementation: (must, may), each (n, H_src/page,
+    W_src/page). must holds the tiles that the pixel-centre rays, and the same
+    rays shifted by +-jitter pixels along x and y, all show through
+    well-conditioned decisions (disk margin, mesh domain edge, taps more than
+    `margin` texels from a texel boundary); may holds every tile one of those
+    rays could show under a decision inside those bands (a surface flip under
+    the jitter included). The exact visible set lies between the two."""
+    Hs, Ws = ov.rgba8.shape[1:3]
+    if Hs % page or Ws % page:
+        raise ValueError("image sizes must be multiples of the tile size")
+    if not 0.0 <= margin < 1.0:
+        raise ValueError("margin must be in [0, 1) texels (the two tap choices around a boundary)")
+    shape = (ov.n, Hs // page, Ws // page)
+    must_all = np.ones(shape, np.uint8)
+    may = np.zeros(shape, np.uint8)
+    for d in ((0.0, 0.0), (jitter, 0.0), (-jitter, 0.0), (0.0, jitter), (0.0, -jitter)):
+        o, e = eye_rays(pos, rot, hfov_deg, W, H, pixel_centres(W, H) + np.array(d))
+        must = np.zeros(shape, np.uint8)
+        lib().orc_visible_tiles_band(ctypes.byref(ov.s), o.shape[0], _p(o), _p(e), int(page), float(margin),
+                                     _p(must), _p(may))
+        must_all &= must
+    return must_all, may
+
+
+def render_reference(ov: OracleViews, pos, rot, hfov_deg, W, H, idx=None, ss: int = 4, disk_scale: float = 2.0,
+                     jitter=None):
     """Offline reference: ss x ss regular sub-pixel rays per pixel, disks scaled by
     disk_scale, every view considered; the pixel is the box average of the sub-ray
-    values (an uncovered sub-ray counts as 0)."""
+    values (an uncovered sub-ray counts as 0). jitter (dx, dy) shifts every
+    sub-ray by that many pixels (stability checks)."""
     if idx is None:
         idx = np.arange(W * H)
     idx = np.asarray(idx, np.int64)
     base = np.stack([(idx % W).astype(np.float64), (idx // W).astype(np.float64)], 1)
+    if jitter is not None:
+        base = base + np.asarray(jitter, np.float64)
     offs = (np.arange(ss) + 0.5) / ss
     sub = np.stack(np.meshgrid(offs, offs, indexing="xy"), -1).reshape(-1, 2)  # (ss*ss, 2) as (x, y)
     pxy = (base[:, None, :] + sub[None, :, :]).reshape(-1, 2)

@@ -611,6 +611,71 @@ void orc_visible_tiles(const orc_views *V, int64_t n_rays, const double *o, cons
         }
 }
 
+/*
+ * The visible tiles of a set of rays split by how firmly the oracle decides
+ * them, for comparisons with a float implementation: must[i][tile] = 1 where a
+ * ray shows the tile through decisions that are all well-conditioned (disk
+ * margin |rho| > 1e-5 and a > 1e-9 |e|, hit more than 1e-6 inside the mesh
+ * domain, and both tap coordinates more than `margin` texels away from a
+ * texel boundary, so the tap columns and rows cannot change); may[i][tile] = 1
+ * for every tile some ray could show under a decision within those bands
+ * (both tap choices at a boundary, the hit of a view whose disk decision is
+ * ill-conditioned either way). must is within the plain visible set and that
+ * set within may. margin is below one texel (a position is then near at most
+ * one boundary per axis). Arrays are OR-ed into (the caller clears them).
+ */
+void orc_visible_tiles_band(const orc_views *V, int64_t n_rays, const double *o, const double *e, int32_t page,
+                            double margin, uint8_t *must, uint8_t *may) {
+    const double md_band = 1e-5, a_band = 1e-9, edge_band = 1e-6;
+    const double ts = tan(0.5 * V->src_fov_deg * M_PI / 180.0);
+    const double dom = 1.0 - 1.0 / V->mesh_m;
+    const int32_t W = V->img_w, H = V->img_h;
+    const int64_t tw = W / page, tpv = (int64_t)tw * (H / page);
+#ifdef _OPENMP
+    if (V->threads > 0) omp_set_num_threads(V->threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_rays; ++k) {
+        const double *ok = o + 3 * k, *ek = e + 3 * k;
+        const double en = sqrt(dot3(ek, ek));
+        for (int32_t i = 0; i < V->n; ++i) {
+            double a, u, v, rho;
+            orc_disk(V, i, ok, ek, &a, &u, &v, &rho);
+            const double md = isnan(rho) ? INFINITY : fabs(rho);
+            const int band_c = md <= md_band || fabs(a) <= a_band * en;
+            const int cand = a > 0.0 && rho > 0.0;
+            if (!cand && !band_c) continue;
+            const double t = orc_mesh_hit(V, i, ok, ek);
+            if (!isfinite(t)) continue;
+            const double *c = V->centres + 3 * i, *R = V->rot + 9 * i;
+            double P[3] = {ok[0] + t * ek[0] - c[0], ok[1] + t * ek[1] - c[1], ok[2] + t * ek[2] - c[2]}, Pl[3];
+            to_local(R, P, Pl);
+            const double Xs = Pl[0] / Pl[2], Ys = Pl[1] / Pl[2];
+            const int band_h = fmin(dom - fabs(Xs / ts), dom - fabs(Ys / ts)) < edge_band;
+            const double px = (Xs / ts + 1.0) * 0.5 * W - 0.5, py = (1.0 - Ys / ts) * 0.5 * H - 0.5;
+            /* the first tap column / row for the position and for positions within the margin */
+            const double fx[2] = {floor(px - margin), floor(px + margin)};
+            const double fy[2] = {floor(py - margin), floor(py + margin)};
+            const int firm = cand && !band_c && !band_h && fx[0] == fx[1] && fy[0] == fy[1];
+            for (int sy = 0; sy < 2; ++sy)
+                for (int sx = 0; sx < 2; ++sx)
+                    for (int dy = 0; dy < 2; ++dy)
+                        for (int dx = 0; dx < 2; ++dx) {
+                            int64_t x = (int64_t)fx[sx] + dx, y = (int64_t)fy[sy] + dy;
+                            if (x < 0) x = 0; if (x > W - 1) x = W - 1;
+                            if (y < 0) y = 0; if (y > H - 1) y = H - 1;
+                            const int64_t q = (int64_t)i * tpv + (y / page) * tw + x / page;
+#pragma omp atomic write
+                            may[q] = 1;
+                            if (firm) {
+#pragma omp atomic write
+                                must[q] = 1;
+                            }
+                        }
+        }
+    }
+}
+
 static void list_put(int32_t *list, int32_t cap, int32_t *cnt, int32_t id) {
     if (list && *cnt < cap) list[*cnt] = id;
     (*cnt)++;

@@ -99,6 +99,32 @@ def unstable_mask(ov, pos, rot, hfov, W, H, idx, ref_rgb, tol=COLOUR_TOL, jitter
     return bad
 
 
+def reference_unstable_mask(ov, pos, rot, hfov, W, H, idx, ref_rgb, ss, disk_scale, tol=COLOUR_TOL, jitter=JITTER,
+                            pos_err=POS_ERR):
+    """unstable_mask for the offline reference render: the whole pixel (all
+    its sub-rays) shifted by +-jitter px along x and y."""
+    bad = np.zeros(len(idx), bool)
+    limit = tol * jitter / pos_err
+    for d in ((jitter, 0.0), (-jitter, 0.0), (0.0, jitter), (0.0, -jitter)):
+        r = oracle.render_reference(ov, pos, rot, hfov, W, H, idx, ss=ss, disk_scale=disk_scale, jitter=d)
+        bad |= np.abs(r - ref_rgb).max(1) > limit
+    return bad
+
+
+def check_reference(ov, got, pos, rot, hfov, W, H, idx, ss, disk_scale, label):
+    """Offline reference render against the oracle's: within COLOUR_TOL on
+    stable pixels, unstable pixels at most MAX_UNSTABLE of the sample (2 on
+    samples too small for the fraction to mean anything)."""
+    ref = oracle.render_reference(ov, pos, rot, hfov, W, H, idx, ss=ss, disk_scale=disk_scale)
+    unst = reference_unstable_mask(ov, pos, rot, hfov, W, H, idx, ref, ss, disk_scale)
+    err = np.abs(got[idx] - ref).max(1)
+    stable_max = float(err[~unst].max())
+    print(f"{label}: max err stable {stable_max:.3g}, all {err.max():.3g}, unstable {int(unst.sum())} of {len(idx)}")
+    assert unst.sum() <= max(2, MAX_UNSTABLE * len(idx))
+    assert stable_max <= COLOUR_TOL
+    return stable_max
+
+
 def check_eye(ov, ctx, pos, rot, hfov, W, H, idx=None, gpu=None, colour_tol=COLOUR_TOL, lists=True, cap=32,
               max_unstable=MAX_UNSTABLE):
     """Full parity check of one eye on pixel indices idx (all if None).

@@ -1,0 +1,132 @@
+"""The batched path at the shapes the benchmark times (Sec. 4.1, Eq. (2)).
+
+* The headline batch: 16 stereo poses of 2 x 1440 x 1600 eyes from the full
+  light field (1024 views of 1024^2, 256^2 depth meshes) with FP16 images and
+  geometry, in one persistent graph-captured launch, equals the 32 per-eye
+  lf_render images bit for bit (colour, weight sum, view count).
+* A mixed-size batch with 2160 x 2160 eyes, large enough that every
+  workgroup of the persistent grid renders hundreds of tiles (eye switches,
+  the one-ahead tile fetch and the queue stealing all run many times), equals
+  the per-eye images for every tile shape of the tuner.
+* The batched FP16 output is within 2/255 of the FP64 oracle on stable
+  sampled pixels (the error bound of the precision form), with the unstable
+  fraction under 0.1 %.
+"""
+import numpy as np
+import pytest
+
+import lfsynth
+import oracle
+from lfcheck import MAX_UNSTABLE, gpu_context, unstable_mask
+
+pytestmark = pytest.mark.gpu
+
+HFOV, IPD = 100.0, 0.064
+PERSISTENT_WG_PER_CU, N_CU = 7, 256
+
+
+@pytest.fixture(scope="module")
+def full():
+    return lfsynth.make_workload("full", seed=0, n_poses=48)
+
+
+@pytest.fixture(scope="module")
+def ctx16(full):
+    c = gpu_context(full.views, "rgba16f", "f16")
+    yield c
+    c.close()
+
+
+def _eyes(full, poses):
+    from paper_1810_08860_amd import lf
+    out = []
+    for k in poses:
+        out += [(np.array(e.pos), np.array(e.rot).reshape(3, 3))
+                for e in lf.lf_stereo_eyes(full.head_pos[k], full.head_rot[k], IPD)]
+    return out
+
+
+def _per_eye(ctx, eyes, res):
+    import torch
+    from paper_1810_08860_amd import lf
+    npx = int(sum(w * h for w, h in res))
+    rgb = torch.full((npx * 3,), -3.0, dtype=torch.float32, device="cuda")
+    ws = torch.full((npx,), -3.0, dtype=torch.float32, device="cuda")
+    cnt = torch.full((npx,), 99, dtype=torch.uint8, device="cuda")
+    off = 0
+    for (p, R), (w, h) in zip(eyes, res):
+        n = w * h
+        lf.lf_render(ctx, [(p, R)], HFOV, (w, h), rgb[3 * off:3 * (off + n)], ws[off:off + n], cnt[off:off + n])
+        off += n
+    torch.cuda.synchronize()
+    return rgb, ws, cnt
+
+
+def _batch(ctx, eyes, res, tune=None):
+    import torch
+    from paper_1810_08860_amd import lf
+    npx = int(sum(w * h for w, h in res))
+    rgb = torch.full((npx * 3,), -5.0, dtype=torch.float32, device="cuda")
+    ws = torch.full((npx,), -5.0, dtype=torch.float32, device="cuda")
+    cnt = torch.full((npx,), 77, dtype=torch.uint8, device="cuda")
+    lf.lf_render_batch(ctx, eyes, HFOV, np.array(res, np.int32), rgb, ws, cnt, tune=tune)
+    torch.cuda.synchronize()
+    return rgb, ws, cnt
+
+
+@pytest.fixture(scope="module")
+def headline(full, ctx16):
+    eyes = _eyes(full, range(16))
+    res = [(1440, 1600)] * len(eyes)
+    return eyes, res, _batch(ctx16, eyes, res)
+
+
+def test_headline_batch_equals_per_eye_renders(ctx16, headline):
+    import torch
+    eyes, res, got = headline
+    ref = _per_eye(ctx16, eyes, res)
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    assert float((got[1] > 0).float().mean()) > 0.99
+
+
+def test_mixed_batch_with_2160_eyes_equals_per_eye_renders(full, ctx16):
+    import torch
+    from paper_1810_08860_amd import lf
+    sizes = [(2160, 2160), (1080, 1200), (1440, 1600)]
+    poses = list(range(16, 40))
+    res = []
+    for q, _ in enumerate(poses):
+        res += [sizes[q % 3]] * 2
+    eyes = _eyes(full, poses)
+    ref = _per_eye(ctx16, eyes, res)
+    for tune in lf.TUNE_GRID:
+        tiles = sum(-(-w // tune[0]) * -(-h // tune[1]) for w, h in res)
+        assert tiles >= 50 * PERSISTENT_WG_PER_CU * N_CU  # >= 50 tiles per workgroup of the persistent grid
+        got = _batch(ctx16, eyes, res, tune)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), tune
+
+
+def test_headline_batch_within_2_over_255_of_oracle(full, headline):
+    """cfg 2's bound on the batched FP16 output itself (not the plain path):
+    1,000 random pixels on each of 6 eyes of the headline batch."""
+    eyes, res, got = headline
+    ov = oracle.OracleViews.from_views(full.views)
+    rgb = got[0].view(-1, 3).cpu().numpy().astype(np.float64)
+    W, H = res[0]
+    worst, worst_all, unst_n, n = 0.0, 0.0, 0, 0
+    for e in (0, 1, 10, 17, 28, 31):
+        idx = np.sort(np.random.default_rng(500 + e).choice(W * H, 1000, replace=False))
+        pos, rot = eyes[e]
+        ref = oracle.render(ov, pos, rot, HFOV, W, H, idx)["rgb"]
+        unst = unstable_mask(ov, pos, rot, HFOV, W, H, idx, ref)
+        err = np.abs(rgb[e * W * H + idx] - ref).max(1)
+        worst = max(worst, float(err[~unst].max()))
+        worst_all = max(worst_all, float(err.max()))
+        unst_n += int(unst.sum())
+        n += len(idx)
+    print(f"headline batch vs oracle: max err stable {worst:.3g}, all {worst_all:.3g}, "
+          f"unstable {unst_n} of {n}")
+    assert worst <= 2.0 / 255
+    assert unst_n <= MAX_UNSTABLE * n

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from lfcheck import check_eye, gpu_context, gpu_render
+from lfcheck import check_reference, check_eye, gpu_context, gpu_render
 
 pytestmark = pytest.mark.gpu
 
@@ -119,9 +119,5 @@ def test_oval_reference_render_scales_extents(tiny, tiny_oracle):
     lf.lf_render_reference(ctx, [(p, R)], 90.0, (Wr, Hr), 3, 2.0, out)
     torch.cuda.synchronize()
     ctx.close()
-    got = out.view(-1, 3).cpu().numpy()
-    idx = np.arange(0, Wr * Hr, 7)
-    ref = oracle.render_reference(ov, p, R, 90.0, Wr, Hr, idx, ss=3, disk_scale=2.0)
-    err = np.abs(got[idx] - ref).max(1)
-    print(f"oval reference ss=3: max err {err.max():.3g}, >1e-4: {(err > 1e-4).mean() * 100:.2f}%")
-    assert (err > 1e-4).mean() < 0.01 and err.max() < 2.0 / 255
+    got = out.view(-1, 3).cpu().numpy().astype(np.float64)
+    check_reference(ov, got, p, R, 90.0, Wr, Hr, np.arange(0, Wr * Hr, 7), 3, 2.0, "oval reference ss=3")

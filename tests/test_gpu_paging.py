@@ -73,11 +73,17 @@ def test_visibility_matches_oracle(tiny, tiny_oracle, ctxs):
         p, R = (tiny.head_pos[0], tiny.head_rot[0]) if k == 0 else [a[0] for a in lfsynth.poses(43, 1, 0.2)]
         _, vis, _ = lf.lf_cache_update(paged, [(p, R)], fov, [(W, H)], 0)
         want = oracle.visible_tiles(tiny_oracle, p, R, fov, W, H, page=PAGE).reshape(V.n, -1)
-        diff = int((vis != want).sum())
-        print(f"eye {k}: {int(want.sum())} tiles shown, {diff} differ")
-        # a tile can differ only through an ill-conditioned decision (a tap on
-        # a tile border, a disk rim, a mesh edge) of some ray
-        assert diff <= max(1, want.sum() // 100)
+        must, may = oracle.visible_tiles_band(tiny_oracle, p, R, fov, W, H, page=PAGE)
+        must, may = must.reshape(V.n, -1).astype(bool), may.reshape(V.n, -1).astype(bool)
+        shown = vis.astype(bool)
+        band = may & ~must
+        print(f"eye {k}: {int(want.sum())} tiles shown by the oracle, {int(shown.sum())} by the GPU; "
+              f"{int(band.sum())} (view, tile) pairs in the band, of them {int((band & shown).sum())} shown, "
+              f"{int((shown != want.astype(bool)).sum())} differ from the oracle (all inside the band)")
+        # exact outside the band: every firmly decided tile is shown, nothing
+        # outside what some ill-conditioned decision could show
+        assert not (must & ~shown).any()
+        assert not (shown & ~may).any()
 
 
 def test_partial_cache_matches_oracle_residency(tiny, tiny_oracle, ctxs):

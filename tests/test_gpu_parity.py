@@ -5,7 +5,7 @@ import pytest
 
 import lfsynth
 import oracle
-from lfcheck import check_eye, gpu_candidates, gpu_context, gpu_render, unstable_mask
+from lfcheck import check_reference, check_eye, gpu_candidates, gpu_context, gpu_render, unstable_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -101,12 +101,15 @@ def test_reference_render_matches_oracle(tiny, tiny_oracle, ctx32):
     out = torch.zeros(W * H * 3, dtype=torch.float32, device="cuda")
     lf.lf_render_reference(ctx32, [(p, R)], 90.0, (W, H), 3, 2.0, out)
     torch.cuda.synchronize()
-    got = out.view(-1, 3).cpu().numpy()
-    idx = np.arange(0, W * H, 7)
-    ref = oracle.render_reference(tiny_oracle, p, R, 90.0, W, H, idx, ss=3, disk_scale=2.0)
-    err = np.abs(got[idx] - ref).max(1)
-    print(f"reference ss=3: max err {err.max():.3g}, >1e-4: {(err > 1e-4).mean() * 100:.2f}%")
-    assert (err > 1e-4).mean() < 0.01 and err.max() < 2.0 / 255
+    got = out.view(-1, 3).cpu().numpy().astype(np.float64)
+    check_reference(tiny_oracle, got, p, R, 90.0, W, H, np.arange(0, W * H, 7), 3, 2.0, "reference ss=3")
+    # 4 x 4 sub-rays (the corrector's target), a ragged eye
+    W, H = 72, 40
+    out = torch.zeros(W * H * 3, dtype=torch.float32, device="cuda")
+    lf.lf_render_reference(ctx32, [(p, R)], 90.0, (W, H), 4, 2.0, out)
+    torch.cuda.synchronize()
+    got = out.view(-1, 3).cpu().numpy().astype(np.float64)
+    check_reference(tiny_oracle, got, p, R, 90.0, W, H, np.arange(0, W * H, 5), 4, 2.0, "reference ss=4")
 
 
 def test_eye_outside_capture_surface_is_rejected(tiny, ctx32):

@@ -5,8 +5,9 @@ Parity criteria as for the renderer: colours within 1e-4 on stable pixels,
 where a pixel is unstable when a +-1e-3 px shift of every sample's image
 position moves the oracle's prefiltered colour by more than 1e-2 (one of its
 rays crosses a silhouette or the mesh domain edge); unstable pixels stay
-below 1 % (a prefiltered pixel gathers 16 rays, each of which may sit on an
-edge). The denominators (sum of rho sigma over the samples that count) agree
+below 0.1 % of the sample (at most 2 on small samples), as for the renderer,
+although a prefiltered pixel gathers 16 rays, each of which may sit on an
+edge. The denominators (sum of rho sigma over the samples that count) agree
 to FP32 rounding on stable pixels.
 """
 import numpy as np
@@ -14,7 +15,7 @@ import pytest
 
 import lfsynth
 import oracle
-from lfcheck import gpu_context, torch_mod
+from lfcheck import MAX_UNSTABLE, gpu_context, torch_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +52,7 @@ def check_views(ov, ctx, views, radius, dp, po, basis, idx, npx, label, ext=None
         werr = np.abs(gws[q][idx] - ref["wsum"])
         print(f"{label} view {i}: {len(idx)} px, max err stable {err[~bad].max():.3g}, all {err.max():.3g}, "
               f"unstable {bad.mean() * 100:.2f}%, max |dW| stable {werr[~bad].max():.3g}")
-        assert bad.mean() < 0.01
+        assert bad.sum() <= max(2, MAX_UNSTABLE * len(idx))
         assert err[~bad].max() <= 1e-4
         assert werr[~bad].max() <= 1e-5 * max(1.0, np.abs(ref["wsum"]).max())
 

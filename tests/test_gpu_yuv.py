@@ -8,7 +8,7 @@ import pytest
 
 import lfsynth
 import oracle
-from lfcheck import check_eye, gpu_context, gpu_render
+from lfcheck import MAX_UNSTABLE, check_eye, gpu_context, gpu_render
 
 pytestmark = pytest.mark.gpu
 
@@ -69,9 +69,9 @@ def test_full_size_yuv420_sampled_parity():
     ctx.close()
     rng = np.random.default_rng(9)
     for (pos, rot), (rgb, _, _) in zip(eyes, outs):
-        idx = np.sort(rng.choice(1440 * 1600, 1500, replace=False))
+        idx = np.sort(rng.choice(1440 * 1600, 3000, replace=False))
         ref = oracle.render(oy, pos, rot, 100.0, 1440, 1600, idx)["rgb"]
         bad = unstable_mask(oy, pos, rot, 100.0, 1440, 1600, idx, ref)
         err = np.abs(rgb[idx] - ref).max(1)
-        print(f"full yuv420: max err stable {err[~bad].max():.3g}, unstable {bad.mean() * 100:.2f}%")
-        assert bad.mean() < 0.005 and err[~bad].max() <= 1e-4
+        print(f"full yuv420: max err stable {err[~bad].max():.3g}, unstable {int(bad.sum())} of {len(idx)}")
+        assert bad.sum() <= max(2, MAX_UNSTABLE * len(idx)) and err[~bad].max() <= 1e-4

@@ -9,6 +9,8 @@ blanks exactly the pixels whose taps reach it), by sufficiency and
 minimality of the visible-tile set (a render restricted to it equals the full
 render, and dropping any one of its tiles changes some pixel's weight sum),
 and by the empty cache."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -78,3 +80,32 @@ def test_camera_centre_needs_every_tile_of_its_view_only(tiny):
     assert np.array_equal(blank[seen], want[seen])
     same = ~blank.reshape(-1)
     assert np.array_equal(r["rgb"][same], full["rgb"][same]) and np.array_equal(r["count"][same], full["count"][same])
+
+
+def test_band_classified_visible_tiles_bracket_the_visible_set(tiny, tiny_oracle):
+    """must (tiles shown only through well-conditioned decisions, for the
+    centre rays and their +-1e-3 px shifts) lies within the plain visible set
+    of every one of those ray sets, and each of them within may; with no
+    margin and no shift the bracket is tight up to the ill-conditioned
+    decisions, which are rare (a few pairs)."""
+    pos, rot, hfov = tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg
+    must, may = oracle.visible_tiles_band(tiny_oracle, pos, rot, hfov, 256, 256, page=32)
+    assert must.sum() > 0 and (must <= may).all()
+    for d in ((0.0, 0.0), (1e-3, 0.0), (0.0, -1e-3)):
+        idx = None
+        o, e = oracle.eye_rays(pos, rot, hfov, 256, 256, oracle.pixel_centres(256, 256, idx) + np.array(d))
+        vis = np.zeros_like(must)
+        oracle.lib().orc_visible_tiles(ctypes.byref(tiny_oracle.s), o.shape[0], o.ctypes.data, e.ctypes.data, 32,
+                                       vis.ctypes.data)
+        assert (must <= vis).all() and (vis <= may).all()
+    tight_must, tight_may = oracle.visible_tiles_band(tiny_oracle, pos, rot, hfov, 256, 256, page=32, margin=0.0,
+                                                      jitter=0.0)
+    plain = oracle.visible_tiles(tiny_oracle, pos, rot, hfov, 256, 256, page=32)
+    assert (tight_must <= plain).all() and (plain <= tight_may).all()
+    assert int(tight_may.sum() - tight_must.sum()) <= max(2, plain.sum() // 200)
+    # the margin makes the taps near a texel boundary undecided: with 0.49
+    # texels almost every tap is, and may reaches tiles next to the visible ones
+    wide_must, wide_may = oracle.visible_tiles_band(tiny_oracle, pos, rot, hfov, 256, 256, page=32, margin=0.49,
+                                                    jitter=0.0)
+    assert (wide_must <= plain).all() and (plain <= wide_may).all()
+    assert wide_must.sum() < plain.sum() < wide_may.sum()
