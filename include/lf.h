@@ -178,6 +178,26 @@ int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, co
               float *out_rgb, float *out_wsum, uint8_t *out_count, void *hip_stream);
 
 /*
+ * lf_render for callers that cannot allocate device memory: code under HIP
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, results and asynchrony as lf_render (bit for bit the same
+ * image), but the per-launch scratch (per eye-view records, per-tile
+ * candidate lists and counts) lives in a fixed device array of 16 MiB that
+ * the library holds on each GPU until the process ends, instead of in the
+ * context's buffer. The call allocates nothing and records no timing events
+ * (lf_profile does not see it). Nothing in the scratch needs clearing: the
+ * set-up and culling kernels write every entry the render reads.
+ * Limit: each launch of at most 16 eyes must fit in 16 MiB (a stereo pair of
+ * 2160 x 2160 eyes needs about 5 MiB at the default 16 x 16 tiles); a call
+ * with a larger launch returns LF_EINVAL before launching anything.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on
+ * one GPU (different streams, or host threads, without ordering) race and
+ * must not be made. The current device must be the context's device.
+ */
+int lf_render_noalloc(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                      float *out_rgb, float *out_wsum, uint8_t *out_count, void *hip_stream);
+
+/*
  * Views taking part in renders. enabled: host uint8 [n_views], non-zero =
  * enabled, or NULL to enable every view (the state after lf_load_views). A
  * disabled view is left out of every later query (render, batch, reference,

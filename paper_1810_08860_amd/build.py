@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblf.so")
 HOSTCHECK_SO = os.path.join(HERE, "liblf_hostcheck.so")
 
-SOURCES = ["lf_kernels.hip", "lf_corrector.hip", "lf_probe.hip", "lf_api.cpp", "lf_corrector_api.cpp", "lf_disks.cpp"]
+SOURCES = ["lf_kernels.hip", "lf_corrector.hip", "lf_probe.hip", "lf_noalloc.hip", "lf_api.cpp", "lf_corrector_api.cpp",
+           "lf_disks.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

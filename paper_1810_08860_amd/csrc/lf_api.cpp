@@ -295,15 +295,26 @@ ViewBases view_bases(const lf_ctx *c) {
     return vb;
 }
 
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device scratch of one launch chunk: eye-view records, tile lists, tile counts.
+size_t chunk_scratch_bytes(const lf_ctx *c, const EyeChunk &ch) {
+    return al256(sizeof(EyeView) * (size_t)ch.n_eyes * c->n) + al256(sizeof(uint16_t) * (size_t)kListCap * ch.total_tiles) +
+           al256(sizeof(int32_t) * (size_t)ch.total_tiles);
+}
+
 // Prep + cull for one chunk of eyes; fills the table/list pointers of `a`.
-int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t s) {
+// The chunk's scratch is the context's buffer (grown on demand), or the
+// caller's region `fixed` (large enough: checked by the caller).
+int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t s, void *fixed = nullptr) {
     const size_t ev_bytes = sizeof(EyeView) * (size_t)ch.n_eyes * c->n;
     const size_t list_bytes = sizeof(uint16_t) * (size_t)kListCap * ch.total_tiles;
-    const size_t cnt_bytes = sizeof(int32_t) * (size_t)ch.total_tiles;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    int rc = ensure_scratch(c, al(ev_bytes) + al(list_bytes) + al(cnt_bytes));
-    if (rc) return rc;
-    char *p = (char *)c->scratch;
+    auto al = al256;
+    if (!fixed) {
+        int rc = ensure_scratch(c, chunk_scratch_bytes(c, ch));
+        if (rc) return rc;
+    }
+    char *p = fixed ? (char *)fixed : (char *)c->scratch;
     EyeView *ev = (EyeView *)p;
     uint16_t *tl = (uint16_t *)(p + al(ev_bytes));
     int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
@@ -581,14 +592,14 @@ int lf_query(const lf_ctx *c, int32_t *n_views, int32_t *img_w, int32_t *mesh_m,
 static int render_impl(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
                        float *out_rgb, float *out_wsum, uint8_t *out_count, int mode, double R, float sub_x,
                        float sub_y, float scale, int accumulate, hipStream_t s,
-                       unsigned long long *stats = nullptr) {
+                       unsigned long long *stats = nullptr, void *fixed = nullptr) {
     int64_t pix_off = 0;
     for (int32_t k0 = 0; k0 < n_eyes; k0 += kMaxEyesPerLaunch) {
         const int32_t nk = std::min(kMaxEyesPerLaunch, n_eyes - k0);
         EyeChunk ch;
         fill_chunk(c, ch, eyes + k0, nk, hfov_deg, res + 2 * k0, pix_off, c->tune.tile_w, c->tune.tile_h);
         RenderArgs a = base_args(c, R);
-        int rc = prep_and_cull(c, ch, a, R, s);
+        int rc = prep_and_cull(c, ch, a, R, s, fixed);
         if (rc) return rc;
         a.out_rgb = out_rgb;
         a.out_wsum = out_wsum;
@@ -614,6 +625,46 @@ int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, co
     return render_impl(c, eyes, n_eyes, hfov_deg, res, out_rgb, out_wsum, out_count, MODE_RENDER, c->R, 0.5f, 0.5f,
                        1.0f, 0, (hipStream_t)hip_stream);
 }
+
+}  // extern "C"
+
+namespace lf {
+
+int ctx_device(const lf_ctx *c) { return c->device; }
+
+int render_fixed_scratch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                         float *out_rgb, float *out_wsum, uint8_t *out_count, void *scratch, size_t scratch_bytes,
+                         hipStream_t s) {
+    if (!c) return fail(LF_EINVAL, "NULL context");
+    if (!out_rgb) return fail(LF_EINVAL, "out_rgb must not be NULL");
+    int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
+    if (rc) return rc;
+    // every launch chunk must fit before anything is launched
+    int64_t pix_off = 0;
+    for (int32_t k0 = 0; k0 < n_eyes; k0 += kMaxEyesPerLaunch) {
+        const int32_t nk = std::min(kMaxEyesPerLaunch, n_eyes - k0);
+        EyeChunk ch;
+        fill_chunk(c, ch, eyes + k0, nk, hfov_deg, res + 2 * k0, pix_off, c->tune.tile_w, c->tune.tile_h);
+        const size_t need = chunk_scratch_bytes(c, ch);
+        if (need > scratch_bytes)
+            return fail(LF_EINVAL,
+                        "eyes %d..%d need %zu bytes of scratch (eye-view records and tile lists); the fixed scratch "
+                        "holds %zu bytes: render fewer or smaller eyes per call",
+                        k0, k0 + nk - 1, need, scratch_bytes);
+        for (int32_t k = 0; k < nk; ++k) pix_off += (int64_t)res[2 * (k0 + k)] * res[2 * (k0 + k) + 1];
+    }
+    // kernel launches only (no per-kernel timing events)
+    const bool prof = c->profiling;
+    c->profiling = false;
+    rc = render_impl(c, eyes, n_eyes, hfov_deg, res, out_rgb, out_wsum, out_count, MODE_RENDER, c->R, 0.5f, 0.5f,
+                     1.0f, 0, s, nullptr, scratch);
+    c->profiling = prof;
+    return rc;
+}
+
+}  // namespace lf
+
+extern "C" {
 
 int lf_render_reference(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
                         int32_t ss, double disk_scale, float *out_rgb, void *hip_stream) {

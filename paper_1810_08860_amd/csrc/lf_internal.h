@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lf.h"
+
 namespace lf {
 
 constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
@@ -145,6 +147,17 @@ struct RenderArgs {
 
 // Record an error message for lf_last_error and return code (lf_api.cpp).
 int fail_msg(int code, const char *msg);
+
+// The device a context's data lives on (current when it was loaded).
+int ctx_device(const lf_ctx *c);
+
+// lf_render with the per-launch scratch (eye-view records, tile lists and
+// counts) in the caller's device region [scratch, scratch + scratch_bytes)
+// instead of the context's buffer: no device allocation. Every launch chunk
+// is checked against scratch_bytes before the first launch (LF_EINVAL).
+int render_fixed_scratch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
+                         float *out_rgb, float *out_wsum, uint8_t *out_count, void *scratch, size_t scratch_bytes,
+                         hipStream_t s);
 
 // Launchers (lf_kernels.hip). All are asynchronous on `s` and return the
 // launch status.

@@ -65,6 +65,7 @@ def lib():
         L.lf_disk_extents.argtypes = [i32, vp, vp, f64, vp]
         L.lf_set_tune.argtypes = [vp, ctypes.POINTER(lf_tune)]
         L.lf_render.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
+        L.lf_render_noalloc.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp, vp, vp]
         L.lf_render_reference.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, i32, f64, vp, vp]
         L.lf_prefilter.argtypes = [vp, vp, i32, f64, vp, vp, vp, i32, i32, vp, vp, vp]
         L.lf_set_view_mask.argtypes = [vp, vp]
@@ -95,6 +96,7 @@ def lib():
         L.lf_free.argtypes = [vp]
         L.lf_free.restype = None
         for name in ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render",
+                     "lf_render_noalloc",
                      "lf_render_reference",
                      "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
                      "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
@@ -228,6 +230,15 @@ def lf_render(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, out_cou
     r = _res(res, len(e))
     _check(lib().lf_render(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb), _ptr(out_wsum),
                            _ptr(out_count), _stream(stream)))
+
+
+def lf_render_noalloc(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, out_count=None, stream=None):
+    """lf_render with its scratch in the library's fixed device array (no
+    device allocation; calls on one GPU must not overlap)."""
+    e = make_eyes(eyes)
+    r = _res(res, len(e))
+    _check(lib().lf_render_noalloc(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb),
+                                   _ptr(out_wsum), _ptr(out_count), _stream(stream)))
 
 
 def lf_render_reference(ctx: Context, eyes, hfov_deg, res, ss, disk_scale, out_rgb, stream=None):
@@ -456,7 +467,8 @@ def lf_last_error() -> str:
 
 
 # names of every symbol include/lf.h declares (checked by the ABI test)
-EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_reference",
+EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_noalloc",
+           "lf_render_reference",
            "lf_prefilter", "lf_set_view_mask", "lf_two_level_mask", "lf_cache_config", "lf_cache_update",
            "lf_cache_resident", "lf_cache_page_misses", "lf_stream_copy",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
