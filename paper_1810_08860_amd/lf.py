@@ -9,7 +9,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblf.so")
+# LF_LIB may name another build of the same sources (the sanitizer test loads
+# a build whose host code carries AddressSanitizer and UBSan checks)
+LIB_PATH = os.environ.get("LF_LIB") or os.path.join(_HERE, "liblf.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
 LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420, LF_IMG_YUV420_RGTC, LF_IMG_PAGED_RGBA8 = 0, 1, 2, 3, 4, 5

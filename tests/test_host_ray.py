@@ -11,7 +11,7 @@ import lfsynth
 import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SO = os.path.join(ROOT, "paper_1810_08860_amd", "liblf_hostcheck.so")
+SO = os.environ.get("LF_HOSTCHECK_LIB") or os.path.join(ROOT, "paper_1810_08860_amd", "liblf_hostcheck.so")
 
 
 def _lib():
