@@ -134,9 +134,14 @@ typedef struct {
 
 /* Launch shape: screen tile of tile_w x tile_h pixels (both multiples of 8,
  * tile_w * tile_h <= 256); one workgroup renders one tile, one wavefront one
- * 8 x 8 pixel block of it. */
+ * 8 x 8 pixel block of it. cap: capacity of a tile's candidate-view list
+ * (1..64; 0 = 64): the culling lists the views whose disk may reach the tile,
+ * and a tile with more than cap of them is rendered by the exact scan over
+ * every view instead (the same views in the same order, so every cap gives
+ * the same image bit for bit; a smaller cap sends more tiles to the scan). */
 typedef struct {
     int32_t tile_w, tile_h;
+    int32_t cap;
 } lf_tune;
 
 /*
@@ -161,7 +166,8 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out);
  * frame (parallel optical axes). out[0] is the left eye. */
 int lf_stereo_eyes(const double head_pos[3], const double head_rot[9], double ipd_m, lf_eye out[2]);
 
-/* Set the launch shape used by lf_render (NULL restores the default 16x16, 32). */
+/* Set the launch shape used by lf_render (NULL restores the default: 16 x 16
+ * tiles, candidate lists of 64). */
 int lf_set_tune(lf_ctx *c, const lf_tune *t);
 
 /*
@@ -355,10 +361,10 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
 
 /*
  * Autotuner of the batched path: times lf_render_batch on the given batch for
- * tiles {8x8, 16x16, 32x8} (median of reps runs each, after a capture and
- * warm-up run), stores the fastest in the context and returns it in *best (may
- * be NULL); ms[3] (may be NULL) receives the medians in that order.
- * Synchronous.
+ * tiles {8x8, 16x16, 32x8} x candidate caps {8, 16, 32, 64} (median of reps
+ * runs each, after a capture and warm-up run), stores the fastest in the
+ * context and returns it in *best (may be NULL); ms[12] (may be NULL)
+ * receives the medians, shape-major in that order. Synchronous.
  */
 int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, const int32_t *res,
                       float *out_rgb, int32_t reps, lf_tune *best, float *ms, void *hip_stream);
@@ -426,6 +432,16 @@ int lf_corrector_create(const float *params, lf_corrector **out);
 int lf_corrector_set_params(lf_corrector *c, const float *params);
 /* Copy the current FP32 parameters to host memory; *step (may be NULL) = optimiser steps taken. Synchronous. */
 int lf_corrector_get_params(lf_corrector *c, float *params, int64_t *step);
+/* Optimiser state for checkpoints: the FP32 master parameters, Adam's first
+ * and second moments (20,835 floats each, host) and the number of steps
+ * taken. get: synchronous copy out. set: replaces all of it (after the device
+ * is idle), so training resumes exactly where the saved run was: the same
+ * later steps on the same batches give the same parameters bit for bit.
+ * LF_EINVAL for NULL pointers, a negative step, a value that is not finite or
+ * a negative second moment. */
+int lf_corrector_get_state(lf_corrector *c, float *params, float *adam_m, float *adam_v, int64_t *step);
+int lf_corrector_set_state(lf_corrector *c, const float *params, const float *adam_m, const float *adam_v,
+                           int64_t step);
 /* Corrected images (device out_rgb [P][3]); out_fallback (device [P] u8, 1 =
  * kept the render) and out_resid (device [P][3] FP32) may be NULL. A
  * threshold of 0 returns the render exactly. Asynchronous on hip_stream.

@@ -10,6 +10,7 @@ PSNR. Every forward, backward and optimiser step runs in the library's kernels.
 """
 from __future__ import annotations
 
+import json
 import math
 from dataclasses import dataclass
 
@@ -60,18 +61,59 @@ def make_frames(ctx_rt, ctx_ref, eyes, hfov, W, H, ss=4, disk_scale=2.0):
     return frames
 
 
-def train(corr, frames, steps, batch=16, crop=96, lr=2e-3, lr_end=2e-4, seed=0, log_every=100):
-    """Adam on random crops of the frames with a cosine learning-rate decay.
-    Returns [(step, loss)] at every log_every steps and at the end."""
+class TrainState:
+    """Where a training run stands: the crop sampler's generator and the next
+    step of the schedule (the optimiser state lives in the corrector)."""
+
+    def __init__(self, seed: int = 0, total: int = 0):
+        self.rng = np.random.default_rng(seed)
+        self.it = 0
+        self.total = total
+
+
+def save_checkpoint(corr, state: TrainState, path: str):
+    """Everything a resumed run needs to continue bit for bit: the FP32 master
+    parameters, Adam's moments and step count (from the library), the crop
+    sampler's generator state and the schedule position. A plain .npz (no
+    pickled objects)."""
+    st = lf.lf_corrector_get_state(corr)
+    np.savez(path, params=st["params"], adam_m=st["adam_m"], adam_v=st["adam_v"],
+             step=np.int64(st["step"]), it=np.int64(state.it), total=np.int64(state.total),
+             rng=np.array(json.dumps(state.rng.bit_generator.state)))
+
+
+def load_checkpoint(corr, path: str) -> TrainState:
+    """Restore a checkpoint written by save_checkpoint into corr; returns the
+    training state to pass to train()."""
+    with np.load(path, allow_pickle=False) as z:
+        lf.lf_corrector_set_state(corr, z["params"], z["adam_m"], z["adam_v"], int(z["step"]))
+        state = TrainState(total=int(z["total"]))
+        state.it = int(z["it"])
+        state.rng.bit_generator.state = json.loads(str(z["rng"]))
+    return state
+
+
+def train(corr, frames, steps, batch=16, crop=96, lr=2e-3, lr_end=2e-4, seed=0, log_every=100, state=None):
+    """Adam on random crops of the frames with a cosine learning-rate decay
+    over `steps` steps. With a TrainState (fresh, or from load_checkpoint) the
+    run takes up to `steps` further steps of that schedule from where the
+    state stands (its total fixes the schedule) and leaves the state at the
+    step reached. Returns [(step, loss)] at every log_every steps and at the
+    end."""
     import torch
-    rng = np.random.default_rng(seed)
+    if state is None:
+        state = TrainState(seed, steps)
+    if state.total == 0:
+        state.total = steps
+    rng = state.rng
     H, W = frames[0].rgb.shape[:2]
     c_rgb = torch.empty((batch, crop, crop, 3), dtype=torch.float32, device="cuda")
     c_ws = torch.empty((batch, crop, crop), dtype=torch.float32, device="cuda")
     c_cnt = torch.empty((batch, crop, crop), dtype=torch.uint8, device="cuda")
     c_ref = torch.empty((batch, crop, crop, 3), dtype=torch.float32, device="cuda")
     log = []
-    for it in range(steps):
+    last = min(state.total, state.it + steps)
+    for it in range(state.it, last):
         for b in range(batch):
             f = frames[rng.integers(len(frames))]
             y = int(rng.integers(0, H - crop + 1))
@@ -80,13 +122,14 @@ def train(corr, frames, steps, batch=16, crop=96, lr=2e-3, lr_end=2e-4, seed=0, 
             c_ws[b].copy_(f.wsum[y:y + crop, x:x + crop])
             c_cnt[b].copy_(f.count[y:y + crop, x:x + crop])
             c_ref[b].copy_(f.ref[y:y + crop, x:x + crop])
-        t = it / max(steps - 1, 1)
+        t = it / max(state.total - 1, 1)
         lr_t = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * t))
-        want = (it % log_every == 0) or it == steps - 1
+        want = (it % log_every == 0) or it == last - 1
         loss, _ = lf.lf_corrector_train_step(corr, c_rgb, c_ws, c_cnt, c_ref, batch, crop, crop, lr_t,
                                              want_loss=want)
         if want:
             log.append((it, loss))
+        state.it = it + 1
     return log
 
 

@@ -124,7 +124,7 @@ struct lf_ctx {
     // per-render scratch: eye-view table and tile lists, grown on demand
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
-    lf_tune tune{16, 16};
+    lf_tune tune{16, 16, kListCap};
     // optional per-kernel timing (lf_profile): event pairs around each launch
     struct Timed {
         int kind;
@@ -152,7 +152,7 @@ struct lf_ctx {
         // persistent render kernel; each replay points them at fresh events
         hipEvent_t ph_a = nullptr, ph_b = nullptr;
         hipGraphNode_t node_a = nullptr, node_b = nullptr;
-        lf_tune tune{16, 16};
+        lf_tune tune{16, 16, kListCap};
         bool tuned = false;
     } batch;
 };
@@ -278,6 +278,7 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.page_miss = c->cache.miss_dev;
     a.ext_inv_scale = (float)(c->R / R);
     a.scale = 1.0f;
+    a.list_cap = c->tune.cap;
     return a;
 }
 
@@ -567,15 +568,26 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     return LF_OK;
 }
 
+// A launch shape with its cap resolved (0 = kListCap); false if invalid.
+static bool tune_ok(const lf_tune &t, lf_tune &out) {
+    if (t.tile_w <= 0 || t.tile_h <= 0 || t.tile_w % 8 || t.tile_h % 8 || t.tile_w * t.tile_h > 256) return false;
+    if (t.cap < 0 || t.cap > kListCap) return false;
+    out = t;
+    if (out.cap == 0) out.cap = kListCap;
+    return true;
+}
+
 int lf_set_tune(lf_ctx *c, const lf_tune *t) {
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (!t) {
-        c->tune = lf_tune{16, 16};
+        c->tune = lf_tune{16, 16, kListCap};
         return LF_OK;
     }
-    if (t->tile_w <= 0 || t->tile_h <= 0 || t->tile_w % 8 || t->tile_h % 8 || t->tile_w * t->tile_h > 256)
-        return fail(LF_EINVAL, "tile must be multiples of 8 with at most 256 pixels (got %dx%d)", t->tile_w, t->tile_h);
-    c->tune = *t;
+    lf_tune r;
+    if (!tune_ok(*t, r))
+        return fail(LF_EINVAL, "tile must be multiples of 8 with at most 256 pixels and cap in [0, %d] (got %dx%d, %d)",
+                    kListCap, t->tile_w, t->tile_h, t->cap);
+    c->tune = r;
     return LF_OK;
 }
 
@@ -599,6 +611,7 @@ static int render_impl(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfo
         EyeChunk ch;
         fill_chunk(c, ch, eyes + k0, nk, hfov_deg, res + 2 * k0, pix_off, c->tune.tile_w, c->tune.tile_h);
         RenderArgs a = base_args(c, R);
+        a.list_cap = c->tune.cap;
         int rc = prep_and_cull(c, ch, a, R, s, fixed);
         if (rc) return rc;
         a.out_rgb = out_rgb;
@@ -1052,9 +1065,10 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     if (!out_rgb) return fail(LF_EINVAL, "out_rgb must not be NULL");
     int rc = check_eyes(c, eyes, n_eyes, hfov_deg, res);
     if (rc) return rc;
-    const lf_tune t = tune ? *tune : c->batch.tune;
-    if (t.tile_w <= 0 || t.tile_h <= 0 || t.tile_w % 8 || t.tile_h % 8 || t.tile_w * t.tile_h > 256)
-        return fail(LF_EINVAL, "invalid tune %dx%d", t.tile_w, t.tile_h);
+    lf_tune t;
+    if (!tune_ok(tune ? *tune : c->batch.tune, t))
+        return fail(LF_EINVAL, "invalid tune %dx%d, cap %d", tune ? tune->tile_w : 0, tune ? tune->tile_h : 0,
+                    tune ? tune->cap : 0);
     hipStream_t s = (hipStream_t)hip_stream;
     lf_ctx::Batch &B = c->batch;
 
@@ -1128,6 +1142,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     a.out_rgb = out_rgb;
     a.out_wsum = out_wsum;
     a.out_count = out_count;
+    a.list_cap = t.cap;
     BatchArgs b;
     b.eyes = B.eyes_dev;
     b.n_eyes = n_eyes;
@@ -1145,8 +1160,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     std::string key;
     {
         char buf[256];
-        snprintf(buf, sizeof buf, "%d|%.17g|%p|%p|%p|%p|%d|%d|%d|", n_eyes, hfov_deg, (void *)out_rgb,
-                 (void *)out_wsum, (void *)out_count, B.buf, t.tile_w, t.tile_h, c->profiling ? 1 : 0);
+        snprintf(buf, sizeof buf, "%d|%.17g|%p|%p|%p|%p|%d|%d|%d|%d|", n_eyes, hfov_deg, (void *)out_rgb,
+                 (void *)out_wsum, (void *)out_count, B.buf, t.tile_w, t.tile_h, t.cap, c->profiling ? 1 : 0);
         key = buf;
         for (int32_t k = 0; k < n_eyes; ++k) key += std::to_string(res[2 * k]) + "x" + std::to_string(res[2 * k + 1]) + ",";
     }
@@ -1225,6 +1240,7 @@ int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov
     if (!c) return fail(LF_EINVAL, "NULL context");
     if (reps < 1 || reps > 100) return fail(LF_EINVAL, "reps must be in [1,100]");
     static const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
+    static const int caps[4] = {8, 16, 32, kListCap};
     hipStream_t s = (hipStream_t)hip_stream;
     hipEvent_t ea, eb;
     LF_HIP(hipEventCreate(&ea), "hipEventCreate");
@@ -1234,8 +1250,8 @@ int lf_autotune_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov
     float best_ms = INFINITY;
     lf_tune bt = c->batch.tune;
     int rc = LF_OK;
-    for (int i = 0; i < 3 && rc == LF_OK; ++i) {
-        lf_tune t{shapes[i][0], shapes[i][1]};
+    for (int i = 0; i < 12 && rc == LF_OK; ++i) {
+        lf_tune t{shapes[i / 4][0], shapes[i / 4][1], caps[i % 4]};
         rc = lf_render_batch(c, eyes, n_eyes, hfov_deg, res, out_rgb, nullptr, nullptr, &t, hip_stream);  // capture + warm
         std::vector<float> times;
         for (int r = 0; r < reps && rc == LF_OK; ++r) {

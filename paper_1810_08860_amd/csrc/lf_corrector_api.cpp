@@ -214,6 +214,33 @@ int lf_corrector_get_params(lf_corrector *c, float *params, int64_t *step) {
     return LF_OK;
 }
 
+int lf_corrector_get_state(lf_corrector *c, float *params, float *adam_m, float *adam_v, int64_t *step) {
+    if (!c || !params || !adam_m || !adam_v || !step) return cfail(LF_EINVAL, "NULL argument");
+    CF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    CF_HIP(hipMemcpy(params, c->prm, sizeof(float) * kCorrParams, hipMemcpyDeviceToHost), "get params");
+    CF_HIP(hipMemcpy(adam_m, c->m1, sizeof(float) * kCorrParams, hipMemcpyDeviceToHost), "get first moments");
+    CF_HIP(hipMemcpy(adam_v, c->m2, sizeof(float) * kCorrParams, hipMemcpyDeviceToHost), "get second moments");
+    *step = c->step;
+    return LF_OK;
+}
+
+int lf_corrector_set_state(lf_corrector *c, const float *params, const float *adam_m, const float *adam_v,
+                           int64_t step) {
+    if (!c || !params || !adam_m || !adam_v) return cfail(LF_EINVAL, "NULL argument");
+    if (step < 0) return cfail(LF_EINVAL, "step must be >= 0 (got %lld)", (long long)step);
+    for (int64_t k = 0; k < kCorrParams; ++k)
+        if (!std::isfinite(params[k]) || !std::isfinite(adam_m[k]) || !(adam_v[k] >= 0.0f) || !std::isfinite(adam_v[k]))
+            return cfail(LF_EINVAL, "state entry %lld is not finite (or a second moment is negative)", (long long)k);
+    // renders and training steps already queued on any stream may still read the state
+    CF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    CF_HIP(hipMemcpy(c->prm, params, sizeof(float) * kCorrParams, hipMemcpyHostToDevice), "set params");
+    CF_HIP(hipMemcpy(c->m1, adam_m, sizeof(float) * kCorrParams, hipMemcpyHostToDevice), "set first moments");
+    CF_HIP(hipMemcpy(c->m2, adam_v, sizeof(float) * kCorrParams, hipMemcpyHostToDevice), "set second moments");
+    c->step = step;
+    c->packed = false;
+    return LF_OK;
+}
+
 int lf_corrector_apply(lf_corrector *c, const float *rgb, const float *wsum, const uint8_t *count, int32_t n_images,
                        int32_t W, int32_t H, float fallback_thresh, float *out_rgb, uint8_t *out_fallback,
                        float *out_resid, void *hip_stream) {

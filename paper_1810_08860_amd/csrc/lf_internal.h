@@ -117,6 +117,7 @@ struct RenderArgs {
     int32_t n_views;
     const uint16_t *tile_list;  // [tiles][kListCap]
     const int32_t *tile_count;  // [tiles]
+    int32_t list_cap;           // a tile with more candidates than this takes the scan over every view
     int32_t NB;                 // inverse-depth blocks per side of a view's mesh
     int32_t M, img_w, img_h;
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)

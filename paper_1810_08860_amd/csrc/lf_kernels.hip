@@ -616,7 +616,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
     const int64_t pix = E.pix_off + (int64_t)py * E.W + px;
 
     const int cnt = uniform_load(a.tile_count + tile);
-    const bool overflow = cnt > kListCap;
+    const bool overflow = cnt > a.list_cap;
     const int total = overflow ? a.n_views : cnt;
     const EyeView *eve = a.ev + (int64_t)e * a.n_views;
     bool inside = inside_img;

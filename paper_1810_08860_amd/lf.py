@@ -38,7 +38,7 @@ class lf_eye(ctypes.Structure):
 
 
 class lf_tune(ctypes.Structure):
-    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("cap", ctypes.c_int32)]
 
 
 class LFError(RuntimeError):
@@ -90,6 +90,8 @@ def lib():
         L.lf_corrector_create.argtypes = [vp, ctypes.POINTER(vp)]
         L.lf_corrector_set_params.argtypes = [vp, vp]
         L.lf_corrector_get_params.argtypes = [vp, vp, vp]
+        L.lf_corrector_get_state.argtypes = [vp, vp, vp, vp, vp]
+        L.lf_corrector_set_state.argtypes = [vp, vp, vp, vp, ctypes.c_int64]
         L.lf_corrector_apply.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp, vp]
         L.lf_corrector_train_step.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
         L.lf_corrector_free.argtypes = [vp]
@@ -103,7 +105,7 @@ def lib():
                      "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
                      "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
                      "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply",
-                     "lf_corrector_train_step"):
+                     "lf_corrector_train_step", "lf_corrector_get_state", "lf_corrector_set_state"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -211,10 +213,10 @@ def lf_stereo_eyes(head_pos, head_rot, ipd_m):
     return out
 
 
-def lf_set_tune(ctx: Context, tile_w=None, tile_h=None):
+def lf_set_tune(ctx: Context, tile_w=None, tile_h=None, cap=0):
     if tile_w is None:
         return _check(lib().lf_set_tune(ctx.handle, None))
-    t = lf_tune(int(tile_w), int(tile_h))
+    t = lf_tune(int(tile_w), int(tile_h), int(cap))
     return _check(lib().lf_set_tune(ctx.handle, ctypes.byref(t)))
 
 
@@ -348,18 +350,21 @@ def lf_render_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, out_wsum=None, o
                                  _ptr(out_wsum), _ptr(out_count), t, _stream(stream)))
 
 
-TUNE_GRID = [(8, 8), (16, 16), (32, 8)]
+TUNE_SHAPES = [(8, 8), (16, 16), (32, 8)]
+TUNE_CAPS = [8, 16, 32, 64]
+# the autotuner's points (tile_w, tile_h, cap), shape-major
+TUNE_GRID = [(w, h, c) for (w, h) in TUNE_SHAPES for c in TUNE_CAPS]
 
 
 def lf_autotune_batch(ctx: Context, eyes, hfov_deg, res, out_rgb, reps=5, stream=None):
-    """Returns ((tile_w, tile_h) chosen, {tile shape: median ms})."""
+    """Returns ((tile_w, tile_h, cap) chosen, {(tile_w, tile_h, cap): median ms})."""
     e = make_eyes(eyes)
     r = _res(res, len(e))
     best = lf_tune()
     ms = np.zeros(len(TUNE_GRID), np.float32)
     _check(lib().lf_autotune_batch(ctx.handle, e, len(e), float(hfov_deg), r.ctypes.data, _ptr(out_rgb), int(reps),
                                    ctypes.byref(best), ms.ctypes.data, _stream(stream)))
-    return (best.tile_w, best.tile_h), dict(zip(TUNE_GRID, ms.tolist()))
+    return (best.tile_w, best.tile_h, best.cap), dict(zip(TUNE_GRID, ms.tolist()))
 
 
 def lf_batch_frame_times(ctx: Context, n_eyes):
@@ -411,6 +416,22 @@ def lf_corrector_get_params(c: Corrector):
     step = ctypes.c_int64()
     _check(lib().lf_corrector_get_params(c.handle, out.ctypes.data, ctypes.byref(step)))
     return out, step.value
+
+
+def lf_corrector_get_state(c: Corrector) -> dict:
+    """FP32 master parameters, Adam moments and step count (host copies)."""
+    out = {k: np.zeros(CORRECTOR_PARAMS, np.float32) for k in ("params", "adam_m", "adam_v")}
+    step = ctypes.c_int64()
+    _check(lib().lf_corrector_get_state(c.handle, out["params"].ctypes.data, out["adam_m"].ctypes.data,
+                                        out["adam_v"].ctypes.data, ctypes.byref(step)))
+    out["step"] = int(step.value)
+    return out
+
+
+def lf_corrector_set_state(c: Corrector, params, adam_m, adam_v, step):
+    arrs = [np.ascontiguousarray(a, np.float32).reshape(CORRECTOR_PARAMS) for a in (params, adam_m, adam_v)]
+    _check(lib().lf_corrector_set_state(c.handle, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                                        int(step)))
 
 
 def lf_corrector_apply(c: Corrector, rgb, wsum, count, n_images, W, H, thresh, out_rgb, out_fallback=None,
@@ -475,5 +496,5 @@ EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", 
            "lf_cache_resident", "lf_cache_page_misses", "lf_stream_copy",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
-           "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_apply", "lf_corrector_train_step",
-           "lf_corrector_free", "lf_last_error", "lf_free")
+           "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_get_state", "lf_corrector_set_state",
+           "lf_corrector_apply", "lf_corrector_train_step", "lf_corrector_free", "lf_last_error", "lf_free")

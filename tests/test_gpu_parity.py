@@ -54,17 +54,20 @@ def test_ragged_sizes_and_several_eyes(tiny, tiny_oracle, ctx32):
 
 
 def test_launch_shapes_give_identical_images(tiny, ctx32):
-    """The tile shape changes the schedule, never the result: every pixel
-    blends the same exact candidate set in the same order."""
+    """The tile shape and candidate cap change the schedule, never the
+    result: every pixel blends the same exact candidate set in the same order."""
     from paper_1810_08860_amd import lf
     p, R = tiny.head_pos[0], tiny.head_rot[0]
     res = [(200, 120)]
     base = gpu_render(ctx32, [(p, R)], 90.0, res)[0]
-    for tw, th in ((8, 8), (32, 8), (16, 8), (8, 32), (8, 16)):
-        lf.lf_set_tune(ctx32, tw, th)
+    for tw, th, cap in ((8, 8, 0), (32, 8, 0), (16, 8, 0), (8, 32, 0), (8, 16, 0), (16, 16, 8), (16, 16, 1),
+                        (32, 8, 16), (8, 8, 32)):
+        # a candidate cap below a tile's candidate count sends that tile to the
+        # exact scan over every view: the same views in the same order
+        lf.lf_set_tune(ctx32, tw, th, cap)
         got = gpu_render(ctx32, [(p, R)], 90.0, res)[0]
         for a, b in zip(base, got):
-            assert np.array_equal(a, b), (tw, th)
+            assert np.array_equal(a, b), (tw, th, cap)
     lf.lf_set_tune(ctx32)
 
 
