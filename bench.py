@@ -136,8 +136,8 @@ def time_variant(lf, torch, ctx, eyes_all, steps, warmup, profile=False):
     out = torch.empty(npx * 3, dtype=torch.float32, device="cuda")
     res = np.array([[EYE_W, EYE_H], [EYE_W, EYE_H]], np.int32)
     P = len(eyes_all)
-    for k in range(warmup):
-        lf.lf_render(ctx, eyes_all[k % P], HFOV, res, out)
+    for k in range(warmup):  # warm-up poses from the end of the list, timed poses from the start
+        lf.lf_render(ctx, eyes_all[P - 1 - k % P], HFOV, res, out)
     torch.cuda.synchronize()
     if profile:
         lf.lf_profile(ctx, True)
@@ -157,6 +157,7 @@ def time_variant(lf, torch, ctx, eyes_all, steps, warmup, profile=False):
     frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
     total_s = t1 - t0
     return {
+        "frames": steps,
         "mpix_s": npx * steps / total_s / 1e6,
         "ms_per_stereo_frame": 1e3 * total_s / steps,
         "p50_ms": float(np.percentile(frame_ms, 50)),
@@ -241,47 +242,145 @@ def cpu_baseline(lf, torch, views, head_pos, head_rot, ctx_plain, seconds):
     }
 
 
-def time_batched(lf, torch, ctx, w, steps, warmup, per_batch, profile=False):
-    """Stereo frames rendered per_batch at a time with lf_render_batch."""
+MIN_LAUNCHES = 10
+
+
+def batch_poses(w, first, per_batch):
+    """Eye table of one batched launch: per_batch consecutive stereo poses from
+    pose `first` on (wrapping around the pose list)."""
+    from paper_1810_08860_amd import lf
     P = len(w.head_pos)
-    nb = max(1, steps // per_batch)
+    eyes = []
+    for k in range(per_batch):
+        q = (first + k) % P
+        eyes.extend(lf.lf_stereo_eyes(w.head_pos[q], w.head_rot[q], IPD))
+    return lf.make_eyes([(np.array(e.pos), np.array(e.rot)) for e in eyes])
+
+
+def batched_error_table(lf, torch, ov, ctx, w, per_batch, n_poses=32, px_per_eye=4096, seed=7):
+    """Error of the batched FP16 path itself against the FP64 oracle: poses
+    0..n_poses-1 rendered by lf_render_batch in launches of per_batch poses
+    (exactly as timed), px_per_eye random pixels per eye. Per stereo frame:
+    max abs error on stable pixels (the oracle moves by at most 1e-2 under a
+    +-1e-3 px shift of the ray) and over all sampled pixels, PSNR over the
+    sampled pixels, unstable count. Part of the oracle leg (FP64 CPU work)."""
+    import oracle
+    npx = EYE_W * EYE_H
     res = np.array([[EYE_W, EYE_H]] * (2 * per_batch), np.int32)
-    batches = []
-    for b in range(max(nb, 1)):
-        eyes = []
+    out = torch.empty(2 * per_batch * npx * 3, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed)
+    rows, t_oracle = [], 0.0
+    for b in range(-(-n_poses // per_batch)):
+        lf.lf_render_batch(ctx, batch_poses(w, b * per_batch, per_batch), HFOV, res, out)
+        torch.cuda.synchronize()
+        host = out.view(2 * per_batch, npx, 3)
         for k in range(per_batch):
-            q = (b * per_batch + k) % P
-            eyes.extend(lf.lf_stereo_eyes(w.head_pos[q], w.head_rot[q], IPD))
-        batches.append(lf.make_eyes([(np.array(e.pos), np.array(e.rot)) for e in eyes]))
+            q = b * per_batch + k
+            if q >= n_poses:
+                break
+            eyes = oracle.stereo_eyes(w.head_pos[q], w.head_rot[q], IPD)
+            st, al, sq, un, n = 0.0, 0.0, 0.0, 0, 0
+            for e in range(2):
+                idx = np.sort(rng.choice(npx, px_per_eye, replace=False))
+                got = host[2 * k + e][torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+                t0 = time.perf_counter()
+                ref = oracle.render(ov, eyes[e][0], eyes[e][1], HFOV, EYE_W, EYE_H, idx)["rgb"]
+                span = np.zeros(len(idx))
+                for d in ((1e-3, 0.0), (-1e-3, 0.0), (0.0, 1e-3), (0.0, -1e-3)):
+                    rj = oracle.render(ov, eyes[e][0], eyes[e][1], HFOV, EYE_W, EYE_H, idx, jitter=d)["rgb"]
+                    span = np.maximum(span, np.abs(rj - ref).max(1))
+                t_oracle += time.perf_counter() - t0
+                err = np.abs(got - ref).max(1)
+                unst = span > 1e-2
+                st = max(st, float(err[~unst].max()))
+                al = max(al, float(err.max()))
+                sq += float(((got - ref) ** 2).sum())
+                un += int(unst.sum())
+                n += len(idx)
+            rows.append({"pose": q, "max_abs_stable": st, "max_abs_all": al,
+                         "psnr_db": 10 * np.log10(1.0 / max(sq / (3 * n), 1e-30)), "unstable": un, "pixels": n})
+    return {
+        "path": "fp16_batched (RGBA16F images, FP16 geometry, FP32 arithmetic, lf_render_batch)",
+        "sample": f"{px_per_eye} random pixels per eye x 2 eyes x {n_poses} poses (0..{n_poses - 1}), "
+                  f"launches of {per_batch} poses; stable = oracle moves <= 1e-2 under a +-1e-3 px ray shift",
+        "bound": 2.0 / 255,
+        "max_abs_stable": max(r["max_abs_stable"] for r in rows),
+        "max_abs_all": max(r["max_abs_all"] for r in rows),
+        "psnr_db_min": min(r["psnr_db"] for r in rows),
+        "psnr_db_mean": float(np.mean([r["psnr_db"] for r in rows])),
+        "unstable_frac": sum(r["unstable"] for r in rows) / sum(r["pixels"] for r in rows),
+        "within_bound": all(r["max_abs_stable"] <= 2.0 / 255 for r in rows),
+        "oracle_s": t_oracle,
+        "per_frame": rows,
+    }
+
+
+def time_batched(lf, torch, ctx, w, steps, warmup, per_batch, profile=False):
+    """Stereo frames rendered per_batch at a time with lf_render_batch: at
+    least MIN_LAUNCHES launches and at least `steps` frames, each launch with
+    its own poses (poses 0, 1, ... in order); the warm-up launches take poses
+    from the end of the list, so no timed launch repeats a warm-up pose. Each
+    launch is bracketed by HIP events on the render stream (p50 / p99 per
+    launch); the value is the pixels of all timed launches over the wall
+    time of the timed region."""
+    P = len(w.head_pos)
+    nb = max(MIN_LAUNCHES, -(-steps // per_batch))
+    nw = max(1, -(-warmup // per_batch))
+    if (nb + nw) * per_batch > P:
+        raise SystemExit(f"{nb + nw} launches of {per_batch} poses need more than the {P} poses")
+    res = np.array([[EYE_W, EYE_H]] * (2 * per_batch), np.int32)
+    timed = [batch_poses(w, b * per_batch, per_batch) for b in range(nb)]
+    warm = [batch_poses(w, P - (k + 1) * per_batch, per_batch) for k in range(nw)]
     npx = 2 * per_batch * EYE_W * EYE_H
     out = torch.empty(npx * 3, dtype=torch.float32, device="cuda")
     if profile:
         lf.lf_profile(ctx, True)  # graph captured with timing nodes from the start
         lf.lf_profile(ctx, False)
         lf.lf_profile(ctx, True)
-    for k in range(max(1, warmup // per_batch)):
-        lf.lf_render_batch(ctx, batches[k % nb], HFOV, res, out)
+    for k in range(nw):
+        lf.lf_render_batch(ctx, warm[k], HFOV, res, out)
     torch.cuda.synchronize()
     if profile:
         lf.lf_profile_read(ctx)  # drop warm-up timings
         lf.lf_profile(ctx, True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nb)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b in range(nb):
-        lf.lf_render_batch(ctx, batches[b], HFOV, res, out)
+        ev[b][0].record()
+        lf.lf_render_batch(ctx, timed[b], HFOV, res, out)
+        ev[b][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = lf.lf_profile_read(ctx) if profile else None
     if profile:
         lf.lf_profile(ctx, False)
+    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
     frames = nb * per_batch
     return {
         "mpix_s": npx * nb / (t1 - t0) / 1e6,
         "ms_per_stereo_frame": 1e3 * (t1 - t0) / frames,
         "frames": frames,
+        "launches": nb,
         "frames_per_launch": per_batch,
+        "launch_ms_p50": float(np.percentile(launch_ms, 50)),
+        "launch_ms_p99": float(np.percentile(launch_ms, 99)),
+        "p50_ms": float(np.percentile(launch_ms, 50)) / per_batch,
+        "p99_ms": float(np.percentile(launch_ms, 99)) / per_batch,
+        "timed_poses": [0, frames],
         "prof": prof,
     }
+
+
+def timed_work(lf, ctx, w, first, frames):
+    """Work counters (lf_render_stats) summed over stereo poses [first, first + frames)."""
+    acc = {k: 0 for k in lf.STAT_NAMES}
+    res = np.array([[EYE_W, EYE_H]] * 2, np.int32)
+    for q in range(first, first + frames):
+        s = lf.lf_render_stats(ctx, lf.lf_stereo_eyes(w.head_pos[q], w.head_rot[q], IPD), HFOV, res)
+        for k in acc:
+            acc[k] += s[k]
+    return acc
 
 
 MIXED_SIZES = [(1080, 1200), (1440, 1600), (2160, 2160)]
@@ -510,8 +609,8 @@ def mixed_batch(lf, torch, ctx, seed, n_poses=64, reps=10):
         "poses": n_poses,
         "pixels_per_batch": npx,
         "eye_sizes": {f"{w}x{h}": int(sum(1 for s in sizes if s == (w, h))) for w, h in MIXED_SIZES},
-        "tune": {"tile": f"{best[0]}x{best[1]}", "seconds": tune_s,
-                 "median_ms": {f"{a}x{b}": v for (a, b), v in table.items()}},
+        "tune": {"tile": f"{best[0]}x{best[1]}", "cap": best[2], "seconds": tune_s,
+                 "median_ms": {f"{a}x{b} cap {c}": v for (a, b, c), v in table.items()}},
         "batch_ms_median": float(np.median(batch_ms)),
         "mpix_s": npx / (np.median(batch_ms) * 1e-3) / 1e6,
         "frame_span_ms_p50": float(np.percentile(spans, 50)),
@@ -605,20 +704,17 @@ def main():
             r = time_variant(lf, torch, ctx, eyes_all, args.steps, args.warmup, profile=prof)
             del r["out"]
         if prof or key[2] == "oval":
-            # work counters of the same frames (outside the timed region)
-            acc = {k: 0 for k in lf.STAT_NAMES}
-            n_stat = min(64, len(eyes_all))
-            for k in range(n_stat):
-                s = lf.lf_render_stats(ctx, eyes_all[k], HFOV, np.array([[EYE_W, EYE_H]] * 2, np.int32))
-                for kk in acc:
-                    acc[kk] += s[kk]
+            # work counters of exactly the timed frames (outside the timed region)
+            n_stat = r.get("frames", min(args.steps, len(eyes_all)))
+            acc = timed_work(lf, ctx, w, 0, n_stat)
             r["stats_per_frame"] = {k: v / n_stat for k, v in acc.items()}
+            r["stats_frames"] = n_stat
         results[name] = r
         log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.4f} ms/stereo frame")
     if not args.no_mixed and ("rgba16f", "f16", "circle") in ctxs:
         log("[bench] mixed-size batch ...")
         mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f16", "circle")], seed=4242)
-        log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']}, "
+        log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']} cap {mixed['tune']['cap']}, "
             f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
     two = None
@@ -686,6 +782,14 @@ def main():
         log("[bench] cpu baseline (FP64 oracle) ...")
         cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctxs[("rgba32f", "f32", "circle")],
                            args.cpu_seconds)
+        if ("rgba16f", "f16", "circle") in ctxs and "fp16_batched" in results:
+            import oracle
+            log("[bench] error table of the batched FP16 path against the oracle (32 poses) ...")
+            cpu["fp16_batched_vs_oracle"] = batched_error_table(
+                lf, torch, oracle.OracleViews.from_views(V), ctxs[("rgba16f", "f16", "circle")], w, args.per_batch)
+            t = cpu["fp16_batched_vs_oracle"]
+            log(f"[bench] fp16_batched vs oracle: max abs stable {t['max_abs_stable']:.3g} (bound {2 / 255:.3g}), "
+                f"all {t['max_abs_all']:.3g}, PSNR min {t['psnr_db_min']:.1f} dB, unstable {t['unstable_frac']:.2%}")
     for c in ctxs.values():
         c.close()
 
@@ -710,9 +814,13 @@ def main():
             "stereo_frames_per_launch": m.get("frames_per_launch", 1),
         },
         "ms_per_stereo_frame": m["ms_per_stereo_frame"],
-        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms", "stats_per_frame")
-                         if kk in v} for k, v in results.items()},
+        "frames_timed": m.get("frames"),
+        "variants": {k: {kk: v[kk] for kk in ("mpix_s", "ms_per_stereo_frame", "p50_ms", "p99_ms", "frames",
+                                             "launches", "launch_ms_p50", "launch_ms_p99", "stats_per_frame",
+                                             "stats_frames") if kk in v} for k, v in results.items()},
         "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
+        "fp16_batched_vs_oracle": ({k: v for k, v in cpu["fp16_batched_vs_oracle"].items() if k != "per_frame"}
+                                   if cpu and "fp16_batched_vs_oracle" in cpu else None),
         "mixed_batch": mixed,
         "corrector": corr,
         "prefilter": pref,
