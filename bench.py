@@ -10,9 +10,11 @@ culling, fused reproject + gather + blend), with the light field already
 resident in HBM.
 
 Prints ONE JSON line. `value` is eye-view Mpix/s of the FP16/batched path
-(FP16 images and geometry, FP32 arithmetic, 16 stereo frames per persistent
+(FP16 images, FP32 geometry, FP32 arithmetic, 16 stereo frames per persistent
 graph-captured launch); the plain FP32 path (FP32 images and geometry, one
-launch sequence per stereo frame) is timed beside it, as are a mixed-size
+launch sequence per stereo frame) is timed beside it, and so are the batched
+path with FP16 geometry too and with RGBA8 images (the oracle leg gives each
+batched form's error table on 32 poses), a mixed-size
 batch (64 stereo poses at 1080x1200 / 1440x1600 / 2160x2160 per eye, autotuned
 tile shape) and the FP64 oracle on the host cores. The per-frame path is also
 timed with the images in the YUV420 form of the paper's tile cache (1.5 bytes
@@ -61,7 +63,7 @@ def log(*a):
 
 
 RENDER_SOURCES = ("lf_kernels.hip", "lf_ray.h", "lf_internal.h")
-RENDER_KERNEL = "k_render_persistent<1, 1, 0>"
+RENDER_KERNEL = "k_render_persistent<1, 0, 0>"
 
 
 def kernel_source_hash() -> str:
@@ -100,7 +102,7 @@ def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_byt
     rf, rw = pick(fetch_csv, "FETCH_SIZE", RENDER_KERNEL), pick(write_csv, "WRITE_SIZE", RENDER_KERNEL)
     fs, wsc = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
     t = {
-        "kernel": f"{RENDER_KERNEL} (FP16 images and geometry, 16 stereo frames of 2 x {EYE_W} x {EYE_H} per launch)",
+        "kernel": f"{RENDER_KERNEL} (FP16 images, FP32 geometry, 16 stereo frames of 2 x {EYE_W} x {EYE_H} per launch)",
         "kernel_hash": kernel_source_hash(),
         "calibration": {"copy_bytes": copy_bytes, "fetch_kib_read": cf, "write_kib_read": cw,
                         "fetch_scale": fs, "write_scale": wsc},
@@ -257,7 +259,7 @@ def batch_poses(w, first, per_batch):
     return lf.make_eyes([(np.array(e.pos), np.array(e.rot)) for e in eyes])
 
 
-def batched_error_table(lf, torch, ov, ctx, w, per_batch, n_poses=32, px_per_eye=4096, seed=7):
+def batched_error_table(lf, torch, ov, ctx, w, per_batch, path, n_poses=32, px_per_eye=4096, seed=7):
     """Error of the batched FP16 path itself against the FP64 oracle: poses
     0..n_poses-1 rendered by lf_render_batch in launches of per_batch poses
     (exactly as timed), px_per_eye random pixels per eye. Per stereo frame:
@@ -300,7 +302,7 @@ def batched_error_table(lf, torch, ov, ctx, w, per_batch, n_poses=32, px_per_eye
             rows.append({"pose": q, "max_abs_stable": st, "max_abs_all": al,
                          "psnr_db": 10 * np.log10(1.0 / max(sq / (3 * n), 1e-30)), "unstable": un, "pixels": n})
     return {
-        "path": "fp16_batched (RGBA16F images, FP16 geometry, FP32 arithmetic, lf_render_batch)",
+        "path": path,
         "sample": f"{px_per_eye} random pixels per eye x 2 eyes x {n_poses} poses (0..{n_poses - 1}), "
                   f"launches of {per_batch} poses; stable = oracle moves <= 1e-2 under a +-1e-3 px ray shift",
         "bound": 2.0 / 255,
@@ -502,7 +504,7 @@ def two_level_leg(lf, torch, V, eyes_all, steps=200, avail_frac=0.5):
     ext = np.concatenate([np.full((V.n, 4), V.disk_radius),
                           np.full((len(coarse), 4), 1.5 * lfsynth.mean_nn(V.centres[coarse]))])
     ctx = lf.lf_load_views(V.centres[idx], V.rot[idx], V.rgba8[idx], V.zdepth[idx], V.src_fov_deg, V.disk_radius,
-                           img_fmt="rgba16f", geo_fmt="f16", disk_ext=ext)
+                           img_fmt="rgba16f", geo_fmt="f32", disk_ext=ext)
     avail = (np.random.default_rng(5).uniform(size=V.n) < avail_frac).astype(np.uint8)
     mask = lf.lf_two_level_mask(ctx, V.n, avail)
     lf.lf_set_view_mask(ctx, mask)
@@ -528,7 +530,7 @@ def streaming_leg(lf, torch, V, head_pos, head_rot, frames=270, budget=128, cach
     ext = np.concatenate([np.full((V.n, 4), V.disk_radius),
                           np.full((len(coarse), 4), 1.5 * lfsynth.mean_nn(V.centres[coarse]))])
     ctx = lf.lf_load_views(V.centres[idx], V.rot[idx], V.rgba8[idx], V.zdepth[idx], V.src_fov_deg, V.disk_radius,
-                           img_fmt="paged_rgba8", geo_fmt="f16", disk_ext=ext)
+                           img_fmt="paged_rgba8", geo_fmt="f32", disk_ext=ext)
     pages = int(cache_gb * (1 << 30)) // (64 * 64 * 4)
     lf.lf_cache_config(ctx, pages, first_resident=V.n)
     res = np.array([[EYE_W, EYE_H], [EYE_W, EYE_H]], np.int32)
@@ -634,7 +636,8 @@ def main():
     ap.add_argument("--no-two-level", action="store_true", help="skip the two-level progressive leg")
     ap.add_argument("--no-streaming", action="store_true", help="skip the tile streaming leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
-    ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,yuv420_rgtc,fp16_batched,fp16_batched_oval")
+    ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,yuv420_rgtc,fp16_batched,fp16geo_batched,"
+                                           "rgba8_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
@@ -682,8 +685,10 @@ def main():
     storage = {"plain": ("rgba32f", "f32", "circle"), "fp16": ("rgba16f", "f16", "circle"),
                "rgba8": ("rgba8", "f16", "circle"), "yuv420": ("yuv420", "f16", "circle"),
                "yuv420_rgtc": ("yuv420_rgtc", "f16", "circle"),
-               "fp16_batched": ("rgba16f", "f16", "circle"),
-               "fp16_batched_oval": ("rgba16f", "f16", "oval")}
+               "fp16_batched": ("rgba16f", "f32", "circle"),
+               "fp16geo_batched": ("rgba16f", "f16", "circle"),
+               "rgba8_batched": ("rgba8", "f32", "circle"),
+               "fp16_batched_oval": ("rgba16f", "f32", "oval")}
     chosen = [v for v in args.variants.split(",") if v]
     main_name = "fp16_batched" if "fp16_batched" in chosen else chosen[0]
     results, ctxs = {}, {}
@@ -711,9 +716,9 @@ def main():
             r["stats_frames"] = n_stat
         results[name] = r
         log(f"[bench] {name}: {r['mpix_s']:.0f} Mpix/s, {r['ms_per_stereo_frame']:.4f} ms/stereo frame")
-    if not args.no_mixed and ("rgba16f", "f16", "circle") in ctxs:
+    if not args.no_mixed and ("rgba16f", "f32", "circle") in ctxs:
         log("[bench] mixed-size batch ...")
-        mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f16", "circle")], seed=4242)
+        mixed = mixed_batch(lf, torch, ctxs[("rgba16f", "f32", "circle")], seed=4242)
         log(f"[bench] mixed: {mixed['mpix_s']:.0f} Mpix/s, tune {mixed['tune']['tile']} cap {mixed['tune']['cap']}, "
             f"p50 {mixed['frame_span_ms_p50']:.3f} ms, p99 {mixed['frame_span_ms_p99']:.3f} ms")
 
@@ -739,9 +744,9 @@ def main():
         log(f"[bench] prefilter: {pref['ms_per_view']:.2f} ms per view, {pref['mrays_s']:.0f} Mrays/s")
 
     corr = None
-    if not args.no_corrector and ("rgba16f", "f16", "circle") in ctxs and ("rgba32f", "f32", "circle") in ctxs:
+    if not args.no_corrector and ("rgba16f", "f32", "circle") in ctxs and ("rgba32f", "f32", "circle") in ctxs:
         log("[bench] corrector ...")
-        corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f16", "circle")], ctxs[("rgba32f", "f32", "circle")],
+        corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f32", "circle")], ctxs[("rgba32f", "f32", "circle")],
                              steps=args.corrector_steps)
         log(f"[bench] corrector: PSNR {corr['psnr_plain_db']:.2f} -> {corr['psnr_corrected_db']:.2f} dB, "
             f"{corr['ms_per_stereo_frame']:.3f} ms / stereo frame, {corr['achieved_tflops']:.0f} TFLOP/s")
@@ -782,13 +787,18 @@ def main():
         log("[bench] cpu baseline (FP64 oracle) ...")
         cpu = cpu_baseline(lf, torch, V, w.head_pos, w.head_rot, ctxs[("rgba32f", "f32", "circle")],
                            args.cpu_seconds)
-        if ("rgba16f", "f16", "circle") in ctxs and "fp16_batched" in results:
-            import oracle
-            log("[bench] error table of the batched FP16 path against the oracle (32 poses) ...")
-            cpu["fp16_batched_vs_oracle"] = batched_error_table(
-                lf, torch, oracle.OracleViews.from_views(V), ctxs[("rgba16f", "f16", "circle")], w, args.per_batch)
-            t = cpu["fp16_batched_vs_oracle"]
-            log(f"[bench] fp16_batched vs oracle: max abs stable {t['max_abs_stable']:.3g} (bound {2 / 255:.3g}), "
+        import oracle
+        ov = oracle.OracleViews.from_views(V)
+        for name, what in (("fp16_batched", "RGBA16F images, FP32 geometry"),
+                           ("fp16geo_batched", "RGBA16F images, FP16 geometry"),
+                           ("rgba8_batched", "RGBA8 images, FP32 geometry")):
+            if name not in results:
+                continue
+            log(f"[bench] error table of {name} against the oracle (32 poses) ...")
+            t = batched_error_table(lf, torch, ov, ctxs[storage[name]], w, args.per_batch,
+                                    f"{name} ({what}, FP32 arithmetic, lf_render_batch)")
+            cpu[f"{name}_vs_oracle"] = t
+            log(f"[bench] {name} vs oracle: max abs stable {t['max_abs_stable']:.3g} (bound {2 / 255:.3g}), "
                 f"all {t['max_abs_all']:.3g}, PSNR min {t['psnr_db_min']:.1f} dB, unstable {t['unstable_frac']:.2%}")
     for c in ctxs.values():
         c.close()
@@ -819,8 +829,9 @@ def main():
                                              "launches", "launch_ms_p50", "launch_ms_p99", "stats_per_frame",
                                              "stats_frames") if kk in v} for k, v in results.items()},
         "speedup_vs_plain_fp32": (m["mpix_s"] / results["plain"]["mpix_s"]) if "plain" in results else None,
-        "fp16_batched_vs_oracle": ({k: v for k, v in cpu["fp16_batched_vs_oracle"].items() if k != "per_frame"}
-                                   if cpu and "fp16_batched_vs_oracle" in cpu else None),
+        "batched_vs_oracle": ({k[:-len("_vs_oracle")]: {kk: vv for kk, vv in v.items() if kk != "per_frame"}
+                               for k, v in cpu.items() if k.endswith("_vs_oracle") and isinstance(v, dict)}
+                              if cpu else None),
         "mixed_batch": mixed,
         "corrector": corr,
         "prefilter": pref,

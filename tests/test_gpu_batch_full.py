@@ -2,8 +2,8 @@
 
 * The headline batch: 16 stereo poses of 2 x 1440 x 1600 eyes from the full
   light field (1024 views of 1024^2, 256^2 depth meshes) with FP16 images and
-  geometry, in one persistent graph-captured launch, equals the 32 per-eye
-  lf_render images bit for bit (colour, weight sum, view count).
+  FP32 geometry, in one persistent graph-captured launch, equals the 32
+  per-eye lf_render images bit for bit (colour, weight sum, view count).
 * A mixed-size batch with 2160 x 2160 eyes, large enough that every
   workgroup of the persistent grid renders hundreds of tiles (eye switches,
   the one-ahead tile fetch and the queue stealing all run many times), equals
@@ -32,7 +32,7 @@ def full():
 
 @pytest.fixture(scope="module")
 def ctx16(full):
-    c = gpu_context(full.views, "rgba16f", "f16")
+    c = gpu_context(full.views, "rgba16f", "f32")
     yield c
     c.close()
 
