@@ -393,8 +393,11 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
     """Train the residual corrector on pairs the method generates (real-time
     FP16 render vs the offline reference: 4x4 sub-pixel rays, disks of twice
-    the radius), 20k crops by default; PSNR on held-out poses; inference time
-    on a stereo frame."""
+    the radius) from three seeded scenes: the bench's scene (seed 0) and
+    scenes 1 and 2, generated the same way (12 textured spheres in a box,
+    1024 views of 1024^2); 8 eyes each, 20k random crops by default. PSNR
+    and max error on held-out poses of scene 0 and on a held-out scene
+    (seed 3); inference time on a stereo frame."""
     import lfsynth
     from paper_1810_08860_amd import corrector
 
@@ -405,16 +408,32 @@ def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
             out += [(np.array(e.pos), np.array(e.rot).reshape(3, 3)) for e in lf.lf_stereo_eyes(p[k], R[k], IPD)]
         return out
 
+    def scene_frames(seed, pose_seed, n_poses):
+        V = lfsynth.make_views(1024, 1024, 256, 12, seed=seed)
+        rt = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
+                              img_fmt="rgba16f", geo_fmt="f32")
+        ref = lf.lf_load_views(V.centres, V.rot, V.rgba8, V.zdepth, V.src_fov_deg, V.disk_radius,
+                               img_fmt="rgba32f", geo_fmt="f32")
+        fr = corrector.make_frames(rt, ref, eyes(pose_seed, n_poses), HFOV, EYE_W, EYE_H)
+        rt.close()
+        ref.close()
+        return fr
+
     t0 = time.perf_counter()
-    train_frames = corrector.make_frames(ctx_rt, ctx_ref, eyes(500, 12), HFOV, EYE_W, EYE_H)
-    test_frames = corrector.make_frames(ctx_rt, ctx_ref, eyes(900, 2), HFOV, EYE_W, EYE_H)
+    train_frames = corrector.make_frames(ctx_rt, ctx_ref, eyes(500, 4), HFOV, EYE_W, EYE_H)
+    held_poses = corrector.make_frames(ctx_rt, ctx_ref, eyes(900, 2), HFOV, EYE_W, EYE_H)
+    for seed in (1, 2):
+        train_frames += scene_frames(seed, 500 + seed, 4)
+    held_scene = scene_frames(3, 950, 2)
     t_pairs = time.perf_counter() - t0
     corr = lf.lf_corrector_create(corrector.init_params(0))
     t0 = time.perf_counter()
     log = corrector.train(corr, train_frames, steps=steps, batch=batch, crop=crop, seed=1, log_every=250)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    ev = corrector.evaluate(corr, test_frames)
+    ev = corrector.evaluate(corr, held_poses)
+    ev_scene = corrector.evaluate(corr, held_scene)
+    test_frames = held_poses
     # inference timing on one stereo frame (both eyes in one call)
     f0, f1 = test_frames[0], test_frames[1]
     rgb = torch.stack([f0.rgb, f1.rgb]).contiguous()
@@ -437,8 +456,14 @@ def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
     return {
         "training_crops": steps * batch,
         "crop": crop,
+        "train_scenes": [0, 1, 2],
         "train_eyes": len(train_frames),
         "held_out_eyes": len(test_frames),
+        "held_out_scene": {"seed": 3, "eyes": len(held_scene), "psnr_plain_db": ev_scene["psnr_plain"],
+                           "psnr_corrected_db": ev_scene["psnr_corrected"], "psnr_gain_db": ev_scene["psnr_gain_db"],
+                           "max_err_plain": ev_scene["max_err_plain"],
+                           "max_err_corrected": ev_scene["max_err_corrected"],
+                           "fallback_frac": ev_scene["fallback_frac"]},
         "pair_generation_s": t_pairs,
         "train_s": t_train,
         "loss_first_last": [log[0][1], log[-1][1]],
@@ -748,6 +773,8 @@ def main():
         log("[bench] corrector ...")
         corr = corrector_leg(lf, torch, ctxs[("rgba16f", "f32", "circle")], ctxs[("rgba32f", "f32", "circle")],
                              steps=args.corrector_steps)
+        log(f"[bench] corrector, held-out scene: PSNR {corr['held_out_scene']['psnr_plain_db']:.2f} -> "
+            f"{corr['held_out_scene']['psnr_corrected_db']:.2f} dB")
         log(f"[bench] corrector: PSNR {corr['psnr_plain_db']:.2f} -> {corr['psnr_corrected_db']:.2f} dB, "
             f"{corr['ms_per_stereo_frame']:.3f} ms / stereo frame, {corr['achieved_tflops']:.0f} TFLOP/s")
 
