@@ -136,9 +136,14 @@ typedef struct {
  * tile_w * tile_h <= 256); one workgroup renders one tile, one wavefront one
  * 8 x 8 pixel block of it. cap: capacity of a tile's candidate-view list
  * (1..64; 0 = 64): the culling lists the views whose disk may reach the tile,
- * and a tile with more than cap of them is rendered by the exact scan over
- * every view instead (the same views in the same order, so every cap gives
- * the same image bit for bit; a smaller cap sends more tiles to the scan). */
+ * each with an upper bound of the inverse depth its rays can meet (where
+ * their mesh walks start), and a tile with more than cap of them is rendered
+ * by the exact scan over every view instead, whose walks start from the
+ * inverse-depth blocks (the same views in the same order, and a mesh cell's
+ * root does not depend on where a walk entered the cell, so shapes and caps
+ * give the same image: bit for bit in the tests; a root within rounding of a
+ * cell edge may come from either cell). A smaller cap sends more tiles to the
+ * scan. */
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t cap;
@@ -194,7 +199,8 @@ int lf_render(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_deg, co
  * (lf_profile does not see it). Nothing in the scratch needs clearing: the
  * set-up and culling kernels write every entry the render reads.
  * Limit: each launch of at most 16 eyes must fit in 16 MiB (a stereo pair of
- * 2160 x 2160 eyes needs about 5 MiB at the default 16 x 16 tiles); a call
+ * 2160 x 2160 eyes over 1024 views needs about 9.2 MiB at the default
+ * 16 x 16 tiles); a call
  * with a larger launch returns LF_EINVAL before launching anything.
  * Every call on one GPU shares that GPU's array: calls whose work overlaps on
  * one GPU (different streams, or host threads, without ordering) race and

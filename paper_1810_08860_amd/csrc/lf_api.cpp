@@ -92,6 +92,7 @@ struct lf_ctx {
     double *vt = nullptr;    // device [n][12]: centre, frame
     float2 *wr = nullptr;    // device [n]: inverse-depth range
     float2 *blk = nullptr;   // device [n][NB][NB]: inverse-depth range per block of cells
+    uint16_t *win = nullptr;  // device [n][M-1][M-1]: per cell, FP16 bound over the kWin x kWin cells from it
     float4 *ext_inv = nullptr;  // device [n]: oval disks' inverse extents (null: circles of radius R)
     float *vrad = nullptr;      // device [n]: oval disks' largest extent (culling bound)
     uint8_t *vmask = nullptr;   // device [n]: views taking part in renders (lf_set_view_mask)
@@ -220,10 +221,6 @@ void fill_chunk(const lf_ctx *c, EyeChunk &ch, const lf_eye *eyes, int32_t n, do
     ch.n_eyes = n;
     ch.tile_w = tw;
     ch.tile_h = th;
-    ch.M = c->M;
-    ch.NB = num_blocks(c->M);
-    ch.sM = (float)(c->M / (2.0 * c->tan_s));
-    ch.cM = (float)(0.5 * (c->M - 1));
     const double tx = std::tan(0.5 * hfov_deg * M_PI / 180.0);
     int32_t tiles = 0, supers = 0;
     for (int32_t k = 0; k < n; ++k) {
@@ -267,7 +264,6 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.cW = (float)(0.5 * (c->img_w - 1));
     a.sH = (float)(c->img_h / (2.0 * c->tan_s));
     a.cH = (float)(0.5 * (c->img_h - 1));
-    a.R = (float)R;
     a.invR = (float)(1.0 / R);
     // R is the context's radius times the call's disk scale; oval extents scale alike
     a.ext_inv = c->ext_inv;
@@ -298,9 +294,21 @@ ViewBases view_bases(const lf_ctx *c) {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Mesh grid and per-cell bounds for the culling kernels.
+CullGeo cull_geo(const lf_ctx *c) {
+    CullGeo g;
+    g.M = c->M;
+    g.NB = num_blocks(c->M);
+    g.sM = (float)(c->M / (2.0 * c->tan_s));
+    g.cM = (float)(0.5 * (c->M - 1));
+    g.win = c->win;
+    g.win_per_view = (int64_t)(c->M - 1) * (c->M - 1);
+    return g;
+}
+
 // Device scratch of one launch chunk: eye-view records, tile lists, tile counts.
 size_t chunk_scratch_bytes(const lf_ctx *c, const EyeChunk &ch) {
-    return al256(sizeof(EyeView) * (size_t)ch.n_eyes * c->n) + al256(sizeof(uint16_t) * (size_t)kListCap * ch.total_tiles) +
+    return al256(sizeof(EyeView) * (size_t)ch.n_eyes * c->n) + al256(sizeof(uint32_t) * (size_t)kListCap * ch.total_tiles) +
            al256(sizeof(int32_t) * (size_t)ch.total_tiles);
 }
 
@@ -309,7 +317,7 @@ size_t chunk_scratch_bytes(const lf_ctx *c, const EyeChunk &ch) {
 // caller's region `fixed` (large enough: checked by the caller).
 int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t s, void *fixed = nullptr) {
     const size_t ev_bytes = sizeof(EyeView) * (size_t)ch.n_eyes * c->n;
-    const size_t list_bytes = sizeof(uint16_t) * (size_t)kListCap * ch.total_tiles;
+    const size_t list_bytes = sizeof(uint32_t) * (size_t)kListCap * ch.total_tiles;
     auto al = al256;
     if (!fixed) {
         int rc = ensure_scratch(c, chunk_scratch_bytes(c, ch));
@@ -317,12 +325,12 @@ int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t 
     }
     char *p = fixed ? (char *)fixed : (char *)c->scratch;
     EyeView *ev = (EyeView *)p;
-    uint16_t *tl = (uint16_t *)(p + al(ev_bytes));
+    uint32_t *tl = (uint32_t *)(p + al(ev_bytes));
     int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
     // conservative disk bounds for the tile test; the exact per-ray test decides in k_render
     const DiskBound db{c->vrad, R, R / c->R, c->vmask};
     LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, view_bases(c), ev, s); }), "k_prep launch");
-    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, ev, c->n, tl, tc, s); }), "k_cull launch");
+    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, cull_geo(c), ev, c->n, tl, tc, s); }), "k_cull launch");
     a.ev = ev;
     a.tile_list = tl;
     a.tile_count = tc;
@@ -558,9 +566,14 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         if (z_owned) (void)hipFree(z_dev);
         return bail(hip_fail(e, "hipMalloc(block bounds)"));
     }
+    if ((e = hipMalloc(&c->win, sizeof(uint16_t) * n_cells)) != hipSuccess) {
+        if (z_owned) (void)hipFree(z_dev);
+        return bail(hip_fail(e, "hipMalloc(cell bounds)"));
+    }
     e = launch_geo_cells(z_dev, c->geo, d->geo_fmt, n, M, 0);
     if (e == hipSuccess) e = launch_geo_range(c->geo, d->geo_fmt, n, M, c->wr, 0);
     if (e == hipSuccess) e = launch_geo_blocks(c->geo, d->geo_fmt, n, M, c->blk, 0);
+    if (e == hipSuccess) e = launch_geo_win(c->geo, d->geo_fmt, n, M, c->win, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (z_owned) (void)hipFree(z_dev);
     if (e != hipSuccess) return bail(hip_fail(e, "geometry conversion"));
@@ -1107,7 +1120,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     // device buffers: eye table, eye-view records, tile lists, counts, queue, stamps
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t ev_b = al(sizeof(EyeView) * (size_t)n_eyes * c->n);
-    const size_t tl_b = al(sizeof(uint16_t) * (size_t)kListCap * tiles);
+    const size_t tl_b = al(sizeof(uint32_t) * (size_t)kListCap * tiles);
     const size_t tc_b = al(sizeof(int32_t) * (size_t)tiles);
     const size_t q_b = al(sizeof(unsigned int) * kQueueStride * kXcds), ft_b = al(sizeof(unsigned long long) * 2 * (size_t)n_eyes);
     const size_t need = ev_b + tl_b + tc_b + q_b + ft_b;
@@ -1137,7 +1150,7 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     char *p = (char *)B.buf;
     RenderArgs a = base_args(c, c->R);
     a.ev = (const EyeView *)p;
-    a.tile_list = (const uint16_t *)(p + ev_b);
+    a.tile_list = (const uint32_t *)(p + ev_b);
     a.tile_count = (const int32_t *)(p + ev_b + tl_b);
     a.out_rgb = out_rgb;
     a.out_wsum = out_wsum;
@@ -1179,8 +1192,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
             LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
         }
         LF_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, view_bases(c), c->img_fmt, c->geo_fmt, grid, B.cap_stream,
-                                    nullptr, nullptr);
+        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, view_bases(c), cull_geo(c), c->img_fmt, c->geo_fmt,
+                                    grid, B.cap_stream, nullptr, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(B.cap_stream, &g);
         if (e != hipSuccess) {
@@ -1381,6 +1394,7 @@ void lf_free(lf_ctx *c) {
     if (c->vt) (void)hipFree(c->vt);
     if (c->wr) (void)hipFree(c->wr);
     if (c->blk) (void)hipFree(c->blk);
+    if (c->win) (void)hipFree(c->win);
     if (c->ext_inv) (void)hipFree(c->ext_inv);
     if (c->vrad) (void)hipFree(c->vrad);
     if (c->vmask) (void)hipFree(c->vmask);

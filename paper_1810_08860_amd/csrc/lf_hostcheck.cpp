@@ -3,6 +3,7 @@
 // evaluated ray by ray on the host. Test support only; not part of liblf.so.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -14,15 +15,19 @@ extern "C" {
 
 // For each ray k and view i: cand[k*n+i] (disk test passed), hit[k*n+i] (mesh
 // hit), and the normalised image-plane position (Xs, Ys) of the hit.
-// geo_fmt 0 = FP32 cells, 1 = FP16 cells. Returns 0.
-int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
-              double R, int32_t geo_fmt, int64_t n_rays, const double *o, const double *e, int32_t *cand,
-              int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
+// geo_fmt 0 = FP32 cells, 1 = FP16 cells. walk 0: the two-level march over
+// the inverse-depth blocks; walk 1: the single walk from the start bound that
+// the culling gives a listed view (the largest per-cell bound over the cell
+// box of the ray, as a one-ray tile). Returns 0.
+static int trace(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
+                 double R, int32_t geo_fmt, int32_t walk, int64_t n_rays, const double *o, const double *e,
+                 int32_t *cand, int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
     const int Mc = M - 1, NB = num_blocks(M);
     const size_t per = (size_t)Mc * Mc;
     std::vector<float4> c32(geo_fmt == 0 ? per * n : 0);
     std::vector<uint2> c16(geo_fmt == 1 ? per * n : 0);
     std::vector<float2> wr(n), blk((size_t)n * NB * NB);
+    std::vector<uint16_t> cmax(per * n);
     for (int v = 0; v < n; ++v) {
         const float *zv = z + (size_t)v * M * M;
         for (int k = 0; k < Mc; ++k)
@@ -32,15 +37,29 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
                 const size_t idx = (size_t)v * per + (size_t)k * Mc + j;
                 if (geo_fmt == 0) {
                     c32[idx] = make_float4(w00, w10, w01, w11);
+                    cmax[idx] = half_up_bits(fmaxf(fmaxf(w00, w10), fmaxf(w01, w11)));
                 } else {
                     __half2 a = __floats2half2_rn(w00, w10), b = __floats2half2_rn(w01, w11);
                     uint2 q;
                     std::memcpy(&q.x, &a, 4);
                     std::memcpy(&q.y, &b, 4);
                     c16[idx] = q;
+                    const float4 d = load_cell<1>(&c16[idx], 0u);
+                    cmax[idx] = half_up_bits(fmaxf(fmaxf(d.x, d.y), fmaxf(d.z, d.w)));
                 }
             }
     }
+    // the window table: per cell, the largest cell bound over the kWin x kWin cells from it
+    std::vector<uint16_t> win(per * n);
+    for (int v = 0; v < n; ++v)
+        for (int k = 0; k < Mc; ++k)
+            for (int j = 0; j < Mc; ++j) {
+                uint16_t m = 0;
+                for (int kk = k; kk < std::min(k + kWin, Mc); ++kk)
+                    for (int jj = j; jj < std::min(j + kWin, Mc); ++jj)
+                        m = std::max(m, cmax[(size_t)v * per + (size_t)kk * Mc + jj]);
+                win[(size_t)v * per + (size_t)k * Mc + j] = m;
+            }
     for (int v = 0; v < n; ++v) {
         float lo = INFINITY, hi = -INFINITY;
         for (int b = 0; b < NB * NB; ++b) {
@@ -62,7 +81,7 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
     }
     const double ts = std::tan(0.5 * src_fov_deg * M_PI / 180.0);
     const float sM = (float)(M / (2.0 * ts)), cM = (float)(0.5 * (M - 1));
-    const float Rf = (float)R, invR = (float)(1.0 / R);
+    const float invR = (float)(1.0 / R);
     for (int64_t k = 0; k < n_rays; ++k) {
         for (int v = 0; v < n; ++v) {
             const double *c = centres + 3 * v, *Rv = rot + 9 * v;
@@ -83,7 +102,7 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
             ev.view = v;
             const size_t out = (size_t)k * n + v;
             RayView rv;
-            cand[out] = disk_test(ev, 0.0f, 0.0f, Rf, invR, rv) ? 1 : 0;
+            cand[out] = disk_test(ev, 0.0f, 0.0f, invR, rv) ? 1 : 0;
             hit[out] = 0;
             Xs[out] = Ys[out] = NAN;
             cells_visited[out] = 0;
@@ -93,9 +112,24 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
             const float2 *b = blk.data() + (size_t)v * NB * NB;
             const void *cv = geo_fmt == 0 ? (const void *)(c32.data() + (size_t)v * per)
                                           : (const void *)(c16.data() + (size_t)v * per);
-            const bool h = geo_fmt == 0
-                               ? march<0>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc)
-                               : march<1>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc);
+            bool h;
+            if (walk == 0) {
+                h = geo_fmt == 0 ? march<0>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc)
+                                 : march<1>(cv, b, M, NB, sM, cM, ev.wmin, ev.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc);
+            } else {
+                int4 bx = make_int4(-1, -1, -1, -1);
+                if (!tile_cell_box(ev, 0.0f, 0.0f, 0.0f, 0.0f, M, sM, cM, bx.x, bx.y, bx.z, bx.w)) bx.x = -1;
+                uint32_t top = 0;
+                int nx, ny;
+                if (box_windows(bx, nx, ny, top))
+                    for (int ty = 0; ty < ny; ++ty)
+                        for (int tx = 0; tx < nx; ++tx)
+                            top = std::max(top, (uint32_t)win[(size_t)v * per + box_window_index(bx, tx, ty, Mc)]);
+                const float wt = half_bits_to_float(top);
+                h = geo_fmt == 0
+                        ? march_top<0>(cv, M, sM, cM, ev.wmin, ev.wmax, wt, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc)
+                        : march_top<1>(cv, M, sM, cM, ev.wmin, ev.wmax, wt, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh, nc);
+            }
             cells_visited[out] = nc;
             if (!h) continue;
             hit[out] = 1;
@@ -104,6 +138,37 @@ int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const
         }
     }
     return 0;
+}
+
+int lfh_trace(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
+              double R, int32_t geo_fmt, int64_t n_rays, const double *o, const double *e, int32_t *cand,
+              int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
+    return trace(n, M, z, centres, rot, src_fov_deg, R, geo_fmt, 0, n_rays, o, e, cand, hit, Xs, Ys, cells_visited);
+}
+
+int lfh_trace_top(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
+                  double R, int32_t geo_fmt, int64_t n_rays, const double *o, const double *e, int32_t *cand,
+                  int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
+    return trace(n, M, z, centres, rot, src_fov_deg, R, geo_fmt, 1, n_rays, o, e, cand, hit, Xs, Ys, cells_visited);
+}
+
+// The cell box of tile_cell_box for one (eye-view frame, rectangle): m, o as
+// in an eye-view record, w range [wmin, wmax]; box = (j0, j1, k0, k1).
+// Returns 1 with a box, 0 without one.
+int lfh_tile_box(const float *m, const float *o, float wmin, float wmax, float X0, float X1, float Y0, float Y1,
+                 int32_t M, float sM, float cM, int32_t *box) {
+    EyeView ev;
+    std::memset(&ev, 0, sizeof ev);
+    std::memcpy(ev.m, m, sizeof ev.m);
+    std::memcpy(ev.o, o, sizeof ev.o);
+    ev.wmin = wmin;
+    ev.wmax = wmax;
+    return tile_cell_box(ev, X0, X1, Y0, Y1, M, sM, cM, box[0], box[1], box[2], box[3]) ? 1 : 0;
+}
+
+// FP16 round-up of the per-cell bounds, for n values.
+void lfh_half_up(int64_t n, const float *x, uint16_t *bits) {
+    for (int64_t k = 0; k < n; ++k) bits[k] = half_up_bits(x[k]);
 }
 
 }  // extern "C"

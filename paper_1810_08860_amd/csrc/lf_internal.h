@@ -12,6 +12,7 @@ namespace lf {
 constexpr int kMaxEyesPerLaunch = 16;  // eye parameters travel in kernel arguments
 constexpr int kListCap = 64;           // per-tile candidate list capacity (exact beyond: full scan)
 constexpr int kBlk = 16;               // mesh cells per side of an inverse-depth bounds block
+constexpr int kWin = 4;                // mesh cells per side of a window of the start-bound table
 constexpr int kXcds = 8;               // XCDs of an MI355X (one L2 each)
 constexpr int kQueueStride = 32;       // batch queue counters: one per XCD, 128 bytes apart
 constexpr int kSuper = 4;              // screen tiles per side of a culling super-tile
@@ -53,9 +54,6 @@ struct EyeChunk {
     int32_t total_supers;
     int32_t pad;
     int32_t tile_w, tile_h;
-    // mesh grid of the light field (for the culling of prefilter eyes)
-    int32_t M, NB;
-    float sM, cM;
     EyeParam e[kMaxEyesPerLaunch];
 };
 
@@ -82,10 +80,16 @@ struct ViewBases {
     int64_t geo_bytes, img_bytes, img2_bytes, blk_per_view;
 };
 
-// Mesh grid of the light field as the culling of prefilter eyes needs it.
+// Mesh grid of the light field as the culling kernels need it: the grid
+// transform, the inverse-depth blocks (prefilter eyes) and the window table
+// from which each listed view of a tile gets the bound its rays' mesh walks
+// start from: per mesh cell (j, k), an upper bound of the inverse depth over
+// the cells [j, j + kWin) x [k, k + kWin) (FP16 bits, rounded up).
 struct CullGeo {
     int32_t M, NB;
     float sM, cM;
+    const uint16_t *win;   // [n][M-1][M-1]
+    int64_t win_per_view;  // (M-1)^2
 };
 
 // Bound of every disk for culling: the radius of view v's disk is
@@ -115,14 +119,17 @@ enum { DISK_CIRCLE = 0, DISK_OVAL = 1 };
 struct RenderArgs {
     const EyeView *ev;          // [n_eyes][n_views]
     int32_t n_views;
-    const uint16_t *tile_list;  // [tiles][kListCap]
+    // [tiles][kListCap]: view index (low 16 bits) and the FP16 bits of an upper
+    // bound of the view's mesh inverse depth over every cell a ray of the tile
+    // can reach (high 16 bits; +inf: no bound)
+    const uint32_t *tile_list;
     const int32_t *tile_count;  // [tiles]
     int32_t list_cap;           // a tile with more candidates than this takes the scan over every view
     int32_t NB;                 // inverse-depth blocks per side of a view's mesh
     int32_t M, img_w, img_h;
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
     float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
-    float R, invR;              // circular disks
+    float invR;                 // circular disks: 1 / radius
     const float4 *ext_inv;      // oval disks (null: circles): [n] 1/e+u, 1/e-u, 1/e+v, 1/e-v
     float ext_inv_scale;        // multiplies ext_inv (1 / disk scale)
     float *out_rgb;
@@ -171,17 +178,19 @@ hipError_t launch_convert_rgtc(const uint8_t *y, const uint8_t *uv, void *yb, vo
 hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);
+// per mesh cell: the largest corner inverse depth of the kWin x kWin cells from it, FP16 rounded up
+hipError_t launch_geo_win(const void *cells, int geo_fmt, int32_t n, int32_t M, uint16_t *win, hipStream_t s);
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
                        const ViewBases &vb, EyeView *ev, hipStream_t s);
-hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_t *tile_list, int32_t *tile_count,
-                       hipStream_t s);
+hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint32_t *tile_list,
+                       int32_t *tile_count, hipStream_t s);
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
                          hipStream_t s);
 // reset + prep + cull + persistent render of a batch (a.ev / tile lists are the batch's buffers)
 // ev_a / ev_b (may be null) are recorded just before / after the persistent render kernel
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, const ViewBases &vb, int img_fmt, int geo_fmt, int grid, hipStream_t s,
-                        hipEvent_t ev_a, hipEvent_t ev_b);
+                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, int img_fmt, int geo_fmt, int grid,
+                        hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 // occupancy of the persistent render kernel (oval: the oval-disk form)
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu);
 // RGBA8 [n][H][W] device images -> kPage x kPage tiles, [n][tiles_y][tiles_x][kPage][kPage]

@@ -221,6 +221,28 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
     }
 }
 
+// Per mesh cell (j, k) of each view: the largest inverse depth over the
+// corners of the cells [j, j + kWin) x [k, k + kWin) (cut at the grid's
+// edge), from the stored values, as FP16 bits rounded up.
+template <int GEO>
+__global__ __launch_bounds__(256) void k_geo_win(const void *__restrict__ cells, int32_t n, int32_t M,
+                                                 uint16_t *__restrict__ win) {
+    const int Mc = M - 1;
+    const int64_t per = (int64_t)Mc * Mc, total = per * n;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = c / per;
+        const int r = (int)(c % per), k = r / Mc, j = r % Mc;
+        const void *view = static_cast<const char *>(cells) + v * per * (GEO == 0 ? 16 : 8);
+        float m = 0.0f;
+        for (int kk = k; kk < min(k + kWin, Mc); ++kk)
+            for (int jj = j; jj < min(j + kWin, Mc); ++jj) {
+                const float4 q = load_cell<GEO>(view, (uint32_t)(kk * Mc + jj));
+                m = fmaxf(m, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
+            }
+        win[c] = half_up_bits(m);
+    }
+}
+
 // Per (eye, view) frame change, computed in FP64 and stored FP32.
 // Can any ray of a plain eye's image rectangle [-tx, tx] x [-ty, ty] cross
 // the disk of radius R (view frame: ray direction m (X, Y, 1), eye at o)? The
@@ -450,13 +472,41 @@ __device__ __forceinline__ int find_eye_super(const EyeChunk &ch, int super) {
 // shape.
 struct CullSmem {
     uint16_t slist[kSuperCap];
-    uint16_t tlst[4][kListCap];
+    uint32_t tlst[4][kListCap];  // view, then view | start bound bits << 16
+    int4 tbox[4][kListCap];      // the listed view's cell box (tile_cell_box); x < 0: no box
     int wcnt[4];
 };
 
+// Start bounds of the listed views of one tile, by one wavefront: eight lanes
+// per listed view (eight views per pass), as 2 rows x 4 columns over the
+// windows that cover the view's cell box (box_windows), then the maximum over
+// the eight lanes.
+// FP16 bits of positive values compare like the values. Entry q of lst
+// becomes view | bound << 16.
+__device__ __forceinline__ void list_bounds(const CullGeo &g, uint32_t *lst, const int4 *box, int m, int lane) {
+    const int Mc = g.M - 1, grp = lane >> 3, sub = lane & 7;
+    for (int base = 0; base < m; base += 8) {
+        const int q = base + grp;
+        uint32_t mx = 0;
+        uint32_t v = 0;
+        if (q < m) {
+            v = lst[q];
+            const int4 b = box[q];
+            const uint16_t *cw = g.win + (int64_t)v * g.win_per_view;
+            int nx, ny;
+            if (box_windows(b, nx, ny, mx))
+                for (int ty = sub >> 2; ty < ny; ty += 2)
+                    for (int tx = sub & 3; tx < nx; tx += 4) mx = max(mx, (uint32_t)cw[box_window_index(b, tx, ty, Mc)]);
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+        if (q < m && sub == 0) lst[q] = v | (mx << 16);
+    }
+}
+
 __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int tile_w, int tile_h,
                                            const EyeView *__restrict__ eve, int32_t n, const CullGeo &g,
-                                           uint16_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
+                                           uint32_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
                                            CullSmem &sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -514,7 +564,13 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
                 const uint64_t mask = __ballot(keep);
                 if (keep) {
                     const int slot = count + __popcll(mask & below);
-                    if (slot < kListCap) sm.tlst[wave][slot] = (uint16_t)v;
+                    if (slot < kListCap) {
+                        int4 bx = make_int4(-1, -1, -1, -1);
+                        if (!tile_cell_box(eve[v], X0, X1, Y0, Y1, g.M, g.sM, g.cM, bx.x, bx.y, bx.z, bx.w))
+                            bx.x = -1;
+                        sm.tlst[wave][slot] = (uint32_t)v;
+                        sm.tbox[wave][slot] = bx;
+                    }
                 }
                 count += __popcll(mask);
             }
@@ -523,6 +579,12 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
         if (active) {
             const int tile = E.tile_off + ty * E.tiles_x + tx;
             const int m = min(count, kListCap);
+            // each listed view's start bound: the largest cell bound in its box
+            // (lists longer than kListCap are never read: those tiles scan every view)
+            if (count <= kListCap) {
+                list_bounds(g, sm.tlst[wave], sm.tbox[wave], m, lane);
+                __threadfence_block();  // the entries written by other lanes are visible below
+            }
             for (int q = lane; q < m; q += 64) tile_list[(int64_t)tile * kListCap + q] = sm.tlst[wave][q];
             if (lane == 0) tile_count[tile] = count;
         }
@@ -530,13 +592,12 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
     }
 }
 
-__global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const EyeView *__restrict__ ev, int32_t n,
-                                              uint16_t *__restrict__ tile_list,
+__global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const CullGeo g, const EyeView *__restrict__ ev,
+                                              int32_t n, uint32_t *__restrict__ tile_list,
                                               int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_super(ch, super);
-    const CullGeo g{ch.M, ch.NB, ch.sM, ch.cM};
     cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, g, tile_list,
                tile_count, sm);
 }
@@ -554,14 +615,14 @@ __device__ __forceinline__ int find_eye_sorted(const EyeParam *__restrict__ eyes
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const EyeView *__restrict__ ev, int32_t n,
-                                                    uint16_t *__restrict__ tile_list,
+__global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const CullGeo g,
+                                                    const EyeView *__restrict__ ev, int32_t n,
+                                                    uint32_t *__restrict__ tile_list,
                                                     int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_sorted(b.eyes, b.n_eyes, super, true);
     const EyeParam E = b.eyes[e];
-    const CullGeo g{0, 0, 0.0f, 0.0f};  // batch eyes are plain eyes (src_view = -1)
     cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, g, tile_list, tile_count,
                sm);
 }
@@ -629,17 +690,18 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
         X = fmaf(-E.par_u, w, X);
         Y = fmaf(-E.par_v, w, Y);
     }
-    // the list's 16-bit entries, read in pairs (the list of a tile starts 4-byte aligned)
-    const uint32_t *tl = reinterpret_cast<const uint32_t *>(a.tile_list + (int64_t)tile * kListCap);
+    const uint32_t *tl = a.tile_list + (int64_t)tile * kListCap;
 
     float accr = 0.0f, accg = 0.0f, accb = 0.0f, ws = 0.0f;
     int nc = 0, nh = 0, n_tests = 0, n_cells = 0, n_miss = 0;
     if (inside) {
         for (int c = 0; c < total; ++c) {
             int vid = c;
+            uint32_t top_bits = 0;
             if (!overflow) {
-                const uint32_t pair = uniform_load(tl + (c >> 1));
-                vid = (c & 1) ? (int)(pair >> 16) : (int)(pair & 0xffffu);
+                const uint32_t entry = uniform_load(tl + c);
+                vid = (int)(entry & 0xffffu);
+                top_bits = entry >> 16;
             }
             const EyeView v = uniform_load(eve + vid);
             if (overflow && !(v.rk > 0.0f)) continue;  // a disabled view (listed tiles never hold one)
@@ -647,17 +709,22 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             ++n_tests;
             const bool cand = DISK == DISK_OVAL
                                   ? disk_test_oval(v, X, Y, uniform_load(a.ext_inv + v.view), a.ext_inv_scale, rv)
-                                  : disk_test(v, X, Y, a.R, a.invR, rv);
+                                  : disk_test(v, X, Y, a.invR, rv);
             if (!cand) continue;
             if (MODE == MODE_STATS) ++nc;
             if (MODE == MODE_DEBUG) {
                 if (nc < a.dbg_cap) a.dbg_cand[pix * a.dbg_cap + nc] = v.view;
                 ++nc;
             }
+            // listed views: one walk from the tile's start bound; a tile that
+            // scans every view walks the inverse-depth blocks instead
             float wh;
-            if (!march<GEO>(v.cells, v.blk, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy, wh,
-                            n_cells))
-                continue;
+            const bool hit =
+                overflow ? march<GEO>(v.cells, v.blk, a.M, a.NB, a.sM, a.cM, v.wmin, v.wmax, rv.Vx, rv.Vy, rv.Dx, rv.Dy,
+                                      wh, n_cells)
+                         : march_top<GEO>(v.cells, a.M, a.sM, a.cM, v.wmin, v.wmax, half_bits_to_float(top_bits), rv.Vx,
+                                          rv.Vy, rv.Dx, rv.Dy, wh, n_cells);
+            if (!hit) continue;
             if (MODE == MODE_DEBUG) {
                 if (nh < a.dbg_cap) a.dbg_contrib[pix * a.dbg_cap + nh] = v.view;
                 ++nh;
@@ -999,15 +1066,24 @@ hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t 
     return hipGetLastError();
 }
 
+hipError_t launch_geo_win(const void *cells, int geo_fmt, int32_t n, int32_t M, uint16_t *win, hipStream_t s) {
+    const int g = grid_for((int64_t)n * (M - 1) * (M - 1), 256);
+    if (geo_fmt == 0)
+        hipLaunchKernelGGL(k_geo_win<0>, dim3(g), dim3(256), 0, s, cells, n, M, win);
+    else
+        hipLaunchKernelGGL(k_geo_win<1>, dim3(g), dim3(256), 0, s, cells, n, M, win);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
                        const ViewBases &vb, EyeView *ev, hipStream_t s) {
     hipLaunchKernelGGL(k_prep, dim3((n + 255) / 256, ch.n_eyes), dim3(256), 0, s, ch, vt, wr, n, db, vb, ev);
     return hipGetLastError();
 }
 
-hipError_t launch_cull(const EyeChunk &ch, const EyeView *ev, int32_t n, uint16_t *tile_list, int32_t *tile_count,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, ev, n, tile_list, tile_count);
+hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint32_t *tile_list,
+                       int32_t *tile_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, g, ev, n, tile_list, tile_count);
     return hipGetLastError();
 }
 
@@ -1077,13 +1153,13 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
 }
 
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, const ViewBases &vb, int img_fmt, int geo_fmt, int grid, hipStream_t s,
-                        hipEvent_t ev_a, hipEvent_t ev_b) {
+                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, int img_fmt, int geo_fmt, int grid,
+                        hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
     hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n, db, vb,
                        const_cast<EyeView *>(a.ev));
-    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, a.ev, n,
-                       const_cast<uint16_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
+    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, g, a.ev, n,
+                       const_cast<uint32_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
     if (ev_a) {
         hipError_t e = hipEventRecordWithFlags(ev_a, s, hipEventRecordExternal);
         if (e != hipSuccess) return e;

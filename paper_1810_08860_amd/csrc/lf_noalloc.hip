@@ -19,7 +19,7 @@
 namespace {
 
 // 16 MiB: a stereo pair of 2160 x 2160 eyes (36,450 tiles of 16 x 16 at
-// 132 bytes each, plus 2 x 1024 eye-view records of 96 bytes) needs 5 MiB.
+// 260 bytes each, plus 2 x 1024 eye-view records of 96 bytes) needs 9.2 MiB.
 constexpr size_t kScratchBytes = (size_t)16 << 20;
 constexpr int kMaxDevices = 64;
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "lf_internal.h"
 
@@ -130,11 +131,10 @@ LF_HD float disk_coords(const EyeView &v, float X, float Y, RayView &rv) {
 // in the view's tangent plane). False for a back-facing disk or rho <= 0.
 // Evaluated without early exits (a back-facing view gives garbage that the
 // final test discards, NaN included).
-LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR, RayView &rv) {
+LF_HD bool disk_test(const EyeView &v, float X, float Y, float invR, RayView &rv) {
     const float ez = disk_coords(v, X, Y, rv);
-    const float r2 = fmaf(rv.Dx, rv.Dx, rv.Dy * rv.Dy);
-    rv.rho = fmaf(-fast_sqrt(r2), invR, 1.0f);
-    return ez > 0.0f && r2 < R * R && rv.rho > 0.0f;
+    rv.rho = fmaf(-fast_sqrt(fmaf(rv.Dx, rv.Dx, rv.Dy * rv.Dy)), invR, 1.0f);
+    return ez > 0.0f && rv.rho > 0.0f;
 }
 
 // Asymmetric oval disk (Sec. 4.4): the linear falloff runs in the radius
@@ -143,9 +143,8 @@ LF_HD bool disk_test(const EyeView &v, float X, float Y, float R, float invR, Ra
 LF_HD bool disk_test_oval(const EyeView &v, float X, float Y, float4 ie, float s, RayView &rv) {
     const float ez = disk_coords(v, X, Y, rv);
     const float su = rv.Dx * (rv.Dx >= 0.0f ? ie.x : ie.y) * s, sv = rv.Dy * (rv.Dy >= 0.0f ? ie.z : ie.w) * s;
-    const float q2 = fmaf(su, su, sv * sv);
-    rv.rho = 1.0f - fast_sqrt(q2);
-    return ez > 0.0f && q2 < 1.0f && rv.rho > 0.0f;
+    rv.rho = 1.0f - fast_sqrt(fmaf(su, su, sv * sv));
+    return ez > 0.0f && rv.rho > 0.0f;
 }
 
 LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
@@ -159,71 +158,205 @@ LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 constexpr float kTolW = 4e-6f;
 constexpr float kTolD = 1e-5f;
 
-// Largest root of (mesh inverse depth - w) on one cell's piece of the line.
-// The piece enters the cell at w0 with cell-local coordinates (fx0, fy0) and
-// leaves at w0 + T (T <= 0); fx, fy move by (bx, by) per unit of w and
+// Largest root of (mesh inverse depth - w) on one cell's piece of the line,
+// the part with w in [lo, hi]. In the cell's local coordinates the line is
+// (fx, fy) = (px + bx w, py + by w), with (px, py) its point at w = 0 and
 // dbb = bx - by. Triangle A (fx >= fy) interpolates (w00, w10, w11) and
-// triangle B (fx < fy) interpolates (w00, w11, w01); on each the difference
-// is linear in t = w - w0, so its root is g / (1 - beta) in closed form.
-LF_HD bool cell_root(const float4 &c, float fx0, float fy0, float w0, float T, float bx, float by, float dbb,
-                     float tol, float &t) {
-    const float d0 = fx0 - fy0;
+// triangle B (fx < fy) interpolates (w00, w11, w01); on each the mesh is
+// linear in w along the line, so the root is num / den in closed form. The
+// root depends on the cell and the line only, not on where a walk entered
+// the cell, so every walk that reaches the cell computes the same value.
+LF_HD bool cell_root(const float4 &c, float px, float py, float bx, float by, float dbb, float lo, float hi,
+                     float &w) {
+    const float d0 = px - py;
     const float a1 = c.y - c.x, a2 = c.w - c.y;
-    const float gA = fmaf(fy0, a2, fmaf(fx0, a1, c.x)) - w0;
-    const float tA = gA * fast_rcp(1.0f - fmaf(by, a2, bx * a1));
+    const float wA = fmaf(py, a2, fmaf(px, a1, c.x)) * fast_rcp(fmaf(-by, a2, fmaf(-bx, a1, 1.0f)));
     const float b1 = c.w - c.z, b2 = c.z - c.x;
-    const float gB = fmaf(fy0, b2, fmaf(fx0, b1, c.x)) - w0;
-    const float tB = gB * fast_rcp(1.0f - fmaf(by, b2, bx * b1));
-    const bool okA = tA <= tol && tA >= T - tol && fmaf(dbb, tA, d0) >= -kTolD;
-    const bool okB = tB <= tol && tB >= T - tol && fmaf(dbb, tB, d0) <= kTolD;
-    t = fmaxf(okA ? tA : -INFINITY, okB ? tB : -INFINITY);
+    const float wB = fmaf(py, b2, fmaf(px, b1, c.x)) * fast_rcp(fmaf(-by, b2, fmaf(-bx, b1, 1.0f)));
+    const bool okA = wA <= hi && wA >= lo && fmaf(dbb, wA, d0) >= -kTolD;
+    const bool okB = wB <= hi && wB >= lo && fmaf(dbb, wB, d0) <= kTolD;
+    w = fmaxf(okA ? wA : -INFINITY, okB ? wB : -INFINITY);
     return okA || okB;
 }
 
-// Walk the cells of one block, [j0, j1] x [k0, k1], along the line from
-// w = ws down to w = we (ws >= we), starting in the cell that holds the line
-// at ws. True with w_hit at the first (largest-w) root. wxe / wye hold the w
-// at which the line leaves the current cell through its x / y edge; a step
-// moves them by dwx = -|1/bx| / dwy = -|1/by| (0 for an axis the line does
-// not cross).
+// Walk the cells of the box [j0, j1] x [k0, k1] (at most max_steps of them)
+// along the line g = (ax + w bx, ay + w by) from w = ws down to w = we
+// (ws >= we), starting in the cell that holds the line at ws. True with w_hit
+// at the first (largest-w) root. wxe / wye hold the w at which the line
+// leaves the current cell through its x / y edge; a step moves them by
+// -|1/bx| / -|1/by| (the slopes are nonzero: grid_line). A root is accepted
+// within tol of the cell's piece of the line.
 template <int GEO>
 LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx, float ibx, float ay, float by,
-                      float iby, float dwx, float dwy, float tol, int j0, int j1, int k0, int k1, float ws, float we,
+                      float iby, float tol, int j0, int j1, int k0, int k1, float ws, float we, int max_steps,
                       float &w_hit, int &n_cells) {
     const int sx = bx > 0.0f ? -1 : 1, sy = by > 0.0f ? -1 : 1;  // cell steps as w decreases
-    const float fsx = (float)sx, fsy = (float)sy;
+    const float dwx = -fabsf(ibx), dwy = -fabsf(iby);
     const float dbb = bx - by;
     float w0 = ws;
-    const float gx = fmaf(w0, bx, ax), gy = fmaf(w0, by, ay);
-    int j = min(max((int)floorf(gx), j0), j1);
-    int k = min(max((int)floorf(gy), k0), k1);
-    float fj = (float)j, fk = (float)k;
-    float fx0 = sat01(gx - fj), fy0 = sat01(gy - fk);
-    float wxe = dwx != 0.0f ? ((bx > 0.0f ? fj : fj + 1.0f) - ax) * ibx : -INFINITY;
-    float wye = dwy != 0.0f ? ((by > 0.0f ? fk : fk + 1.0f) - ay) * iby : -INFINITY;
+    int j = min(max((int)floorf(fmaf(w0, bx, ax)), j0), j1);
+    int k = min(max((int)floorf(fmaf(w0, by, ay)), k0), k1);
+    // exit edge in local coordinates: 0 when the coordinate falls as w does, else 1
+    float wxe = ((bx > 0.0f ? 0.0f : 1.0f) - (ax - (float)j)) * ibx;
+    float wye = ((by > 0.0f ? 0.0f : 1.0f) - (ay - (float)k)) * iby;
     bool found = false, more = true;
-    for (int it = 0; it < 2 * kBlk + 2 && more; ++it) {
+    for (int it = 0; it < max_steps && more; ++it) {
         const bool xs = wxe >= wye, ys = wye >= wxe;  // exit edge(s): both at a corner
         const float wn = xs ? wxe : wye;
         const bool last = !(wn > we);
         const float w1 = last ? we : (wn < w0 ? wn : w0);
         const float4 c = load_cell<GEO>(cells, mul24(k, Mc) + j);
         ++n_cells;
-        float t;
-        found = cell_root(c, fx0, fy0, w0, w1 - w0, bx, by, dbb, tol, t);
-        w_hit = w0 + t;
+        found = cell_root(c, ax - (float)j, ay - (float)k, bx, by, dbb, w1 - tol, w0 + tol, w_hit);
         j += xs ? sx : 0;
-        fj += xs ? fsx : 0.0f;
         wxe += xs ? dwx : 0.0f;
         k += ys ? sy : 0;
-        fk += ys ? fsy : 0.0f;
         wye += ys ? dwy : 0.0f;
         more = !found && !last && j >= j0 && j <= j1 && k >= k0 && k <= k1;
-        fx0 = sat01(fmaf(w1, bx, ax) - fj);
-        fy0 = sat01(fmaf(w1, by, ay) - fk);
         w0 = w1;
     }
     return found;
+}
+
+// FP16 bit pattern of the smallest half-precision value >= x, for x > 0
+// (+inf above the FP16 range). Positive FP16 values order like their bit
+// patterns, so a maximum of such bounds is an integer maximum.
+LF_HD uint16_t half_up_bits(float x) {
+    const __half h = __float2half_rn(x);
+    uint16_t b;
+    memcpy(&b, &h, 2);
+    return (uint16_t)(__half2float(h) < x ? b + 1 : b);
+}
+LF_HD float half_bits_to_float(uint32_t b) {
+    const uint16_t q = (uint16_t)b;
+    __half h;
+    memcpy(&h, &q, 2);
+    return __half2float(h);
+}
+
+// Mesh cells of view v that a ray through the image-plane rectangle
+// [X0, X1] x [Y1, Y0] can reach over w in [v.wmin, v.wmax]: the box
+// [j0, j1] x [k0, k1] (clamped to the grid). For a fixed w the points
+// V + w D of the rectangle's rays form the central projection of the
+// rectangle followed by an affine map, a convex quad spanned by its corner
+// rays, and each ray's points are affine in w, so every reachable point lies
+// in the convex hull of the corner rays' points at the two ends of the range.
+// The box is widened by a quarter cell against FP32 rounding. False (no box)
+// when a corner ray does not cross the disk plane from behind (the
+// projection is unbounded); true with an empty box (j0 > j1) when the hull
+// misses the mesh domain.
+LF_HD bool tile_cell_box(const EyeView &v, float X0, float X1, float Y0, float Y1, int M, float sM, float cM,
+                         int &j0, int &j1, int &k0, int &k1) {
+    const float cx[4] = {X0, X1, X1, X0}, cy[4] = {Y0, Y0, Y1, Y1};
+    float gx0 = INFINITY, gx1 = -INFINITY, gy0 = INFINITY, gy1 = -INFINITY;
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float ez = fmaf(v.m[6], cx[q], fmaf(v.m[7], cy[q], v.m[8]));
+        ok = ok && ez > 0.0f;
+        const float iz = fast_rcp(ez);
+        const float Vx = fmaf(v.m[0], cx[q], fmaf(v.m[1], cy[q], v.m[2])) * iz;
+        const float Vy = fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5])) * iz;
+        const float Dx = fmaf(-v.o[2], Vx, v.o[0]), Dy = fmaf(-v.o[2], Vy, v.o[1]);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float w = e ? v.wmax : v.wmin;
+            const float gx = fmaf(fmaf(w, Dx, Vx), sM, cM), gy = fmaf(-fmaf(w, Dy, Vy), sM, cM);
+            gx0 = fminf(gx0, gx);
+            gx1 = fmaxf(gx1, gx);
+            gy0 = fminf(gy0, gy);
+            gy1 = fmaxf(gy1, gy);
+        }
+    }
+    if (!ok || !(gx0 <= gx1 && gy0 <= gy1)) return false;  // NaN included
+    gx0 -= 0.25f;
+    gx1 += 0.25f;
+    gy0 -= 0.25f;
+    gy1 += 0.25f;
+    const float lim = (float)(M - 1);
+    if (gx1 < 0.0f || gx0 > lim || gy1 < 0.0f || gy0 > lim) {
+        j0 = k0 = 1;
+        j1 = k1 = 0;
+        return true;
+    }
+    // cells 0 .. M-2; the domain edge g = M-1 belongs to the last cell
+    const float top = (float)(M - 2);
+    j0 = (int)floorf(fminf(fmaxf(gx0, 0.0f), top));
+    j1 = (int)floorf(fminf(fmaxf(gx1, 0.0f), top));
+    k0 = (int)floorf(fminf(fmaxf(gy0, 0.0f), top));
+    k1 = (int)floorf(fminf(fmaxf(gy1, 0.0f), top));
+    return true;
+}
+
+// Windows of the per-cell window table (the bound over kWin x kWin cells
+// from each cell) that cover a cell box b = (j0, j1, k0, k1): nx x ny windows
+// starting every kWin cells from (j0, k0), the last of each row and column
+// moved back to end on the box's edge (a box narrower than kWin takes one
+// window from its corner, which reaches past the box: still a bound). False
+// when nothing is to be read: then mx is the bound already, +inf without a
+// box (j0 < 0) and 0 (+0.0: no root can exist) for an empty box.
+LF_HD bool box_windows(const int4 &b, int &nx, int &ny, uint32_t &mx) {
+    if (b.x < 0) {
+        mx = 0x7c00u;
+        return false;
+    }
+    if (b.x > b.y || b.z > b.w) {
+        mx = 0u;
+        return false;
+    }
+    nx = (b.y - b.x + kWin) / kWin;
+    ny = (b.w - b.z + kWin) / kWin;
+    return true;
+}
+LF_HD uint32_t box_window_index(const int4 &b, int tx, int ty, int Mc) {
+    const int j = min(b.x + kWin * tx, max(b.y - (kWin - 1), b.x));
+    const int k = min(b.z + kWin * ty, max(b.w - (kWin - 1), b.z));
+    return (uint32_t)(k * Mc + j);
+}
+
+// The ray's line in view grid coordinates, g = (ax + w bx, ay + w by), with
+// 1 / bx and 1 / by, clipped to the mesh domain 0 <= g <= M-1 on both axes:
+// [wlo, whi] shrinks to the part of the line over the domain. False when
+// nothing is left. A slope below 1e-20 in magnitude is raised to 1e-20 (same
+// sign): over any inverse-depth range the line then stays in one column or
+// row of cells, and its interval over the domain is every w or none, as for
+// a line that does not move along the axis at all.
+struct GridLine {
+    float ax, bx, ibx, ay, by, iby;
+};
+LF_HD float min_slope(float b) { return fabsf(b) >= 1e-20f ? b : copysignf(1e-20f, b); }
+LF_HD bool grid_line(int M, float sM, float cM, float Vx, float Vy, float Dx, float Dy, float &wlo, float &whi,
+                     GridLine &L) {
+    const float lim = (float)(M - 1);
+    L.ax = fmaf(Vx, sM, cM);
+    L.bx = min_slope(Dx * sM);
+    L.ay = fmaf(-Vy, sM, cM);
+    L.by = min_slope(-Dy * sM);
+    L.ibx = fast_rcp(L.bx);
+    L.iby = fast_rcp(L.by);
+    // per axis the domain is w in [x1, x1 + lim / b] (either order)
+    const float x1 = -L.ax * L.ibx, xl = lim * L.ibx;
+    const float y1 = -L.ay * L.iby, yl = lim * L.iby;
+    wlo = fmaxf(wlo, fmaxf(x1 + fminf(xl, 0.0f), y1 + fminf(yl, 0.0f)));
+    whi = fminf(whi, fminf(x1 + fmaxf(xl, 0.0f), y1 + fmaxf(yl, 0.0f)));
+    return wlo <= whi;
+}
+
+// Largest w in [wlo, whi] at which the line (V + w D, w) meets the view's
+// mesh, when no root lies above w = wtop (an upper bound of the mesh's inverse
+// depth over every cell the line can reach, e.g. from tile_cell_box): one
+// walk over the cells from min(whi, wtop) down, without the block level.
+template <int GEO>
+LF_HD bool march_top(const void *__restrict__ cells, int M, float sM, float cM, float wlo, float whi, float wtop,
+                     float Vx, float Vy, float Dx, float Dy, float &w_hit, int &n_cells) {
+    GridLine L;
+    if (!grid_line(M, sM, cM, Vx, Vy, Dx, Dy, wlo, whi, L)) return false;
+    const float ws = fminf(whi, wtop);
+    if (!(ws >= wlo)) return false;
+    const int Mc = M - 1;
+    // a segment crosses at most 2 Mc - 1 cells of the Mc x Mc grid
+    return walk_cells<GEO>(cells, Mc, L.ax, L.bx, L.ibx, L.ay, L.by, L.iby, kTolW * fabsf(whi), 0, Mc - 1, 0,
+                           Mc - 1, ws, wlo, 2 * Mc + 2, w_hit, n_cells);
 }
 
 // Largest w in [wlo, whi] at which the line (V + w D, w) meets the view's
@@ -235,27 +368,12 @@ template <int GEO>
 LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk, int M, int NB, float sM,
                  float cM, float wlo, float whi, float Vx, float Vy, float Dx, float Dy, float &w_hit,
                  int &n_cells) {
-    const float lim = (float)(M - 1);
-    const float ax = fmaf(Vx, sM, cM), bx = Dx * sM;
-    const float ay = fmaf(-Vy, sM, cM), by = -Dy * sM;
-    const bool mx = fabsf(bx) > 1e-20f, my = fabsf(by) > 1e-20f;
-    const float ibx = mx ? fast_rcp(bx) : 0.0f, iby = my ? fast_rcp(by) : 0.0f;
-    // clip to the mesh domain 0 <= g <= M-1 on both axes (an axis the line does
-    // not move along either keeps every w or none)
-    {
-        const float x1 = -ax * ibx, x2 = (lim - ax) * ibx;
-        const float y1 = -ay * iby, y2 = (lim - ay) * iby;
-        const bool inx = ax >= 0.0f && ax <= lim, iny = ay >= 0.0f && ay <= lim;
-        wlo = fmaxf(wlo, fmaxf(mx ? fminf(x1, x2) : (inx ? -INFINITY : INFINITY),
-                               my ? fminf(y1, y2) : (iny ? -INFINITY : INFINITY)));
-        whi = fminf(whi, fminf(mx ? fmaxf(x1, x2) : (inx ? INFINITY : -INFINITY),
-                               my ? fmaxf(y1, y2) : (iny ? INFINITY : -INFINITY)));
-    }
-    if (!(wlo <= whi)) return false;
+    GridLine L;
+    if (!grid_line(M, sM, cM, Vx, Vy, Dx, Dy, wlo, whi, L)) return false;
+    const float ax = L.ax, bx = L.bx, ibx = L.ibx, ay = L.ay, by = L.by, iby = L.iby;
 
     const int Mc = M - 1;
     const int sbx = bx > 0.0f ? -1 : 1, sby = by > 0.0f ? -1 : 1;
-    const float dwx = -fabsf(ibx), dwy = -fabsf(iby);
     const float tol = kTolW * fabsf(whi);
     float w0 = whi;
     int bi = (int)((unsigned)min(max((int)floorf(fmaf(w0, bx, ax)), 0), Mc - 1) / kBlk);
@@ -265,16 +383,16 @@ LF_HD bool march(const void *__restrict__ cells, const float2 *__restrict__ blk,
         const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc) - 1;
         const int k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc) - 1;
         // inverse depth at which the line leaves the block
-        const float wxe = mx ? ((float)(bx > 0.0f ? j0 : j1 + 1) - ax) * ibx : -INFINITY;
-        const float wye = my ? ((float)(by > 0.0f ? k0 : k1 + 1) - ay) * iby : -INFINITY;
+        const float wxe = ((float)(bx > 0.0f ? j0 : j1 + 1) - ax) * ibx;
+        const float wye = ((float)(by > 0.0f ? k0 : k1 + 1) - ay) * iby;
         const float wn = fmaxf(wxe, wye);
         const bool last = !(wn > wlo);
         const float wb1 = last ? wlo : fminf(wn, w0);
         const float2 bb = at<float2>(blk, mul24(bk, NB) + bi);
         const float ws = fminf(w0, bb.y), we = fmaxf(wb1, bb.x);
         if (ws >= we)
-            found = walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, dwx, dwy, tol, j0, j1, k0, k1, ws, we, w_hit,
-                                    n_cells);
+            found = walk_cells<GEO>(cells, Mc, ax, bx, ibx, ay, by, iby, tol, j0, j1, k0, k1, ws, we, 2 * kBlk + 2,
+                                    w_hit, n_cells);
         bi += wxe == wn ? sbx : 0;
         bk += wye == wn ? sby : 0;
         more = !found && !last && bi >= 0 && bi < NB && bk >= 0 && bk < NB;
@@ -300,16 +418,25 @@ LF_HD bool mesh_point(const void *__restrict__ cells, int M, float sM, float cM,
     return true;
 }
 
+// Bilinear taps along one axis of n texels with clamp-to-edge, at position p
+// in texel units with texel i's centre at i: taps i0, i1 = i0 + 1 (cut at the
+// edge) and the weight f of i1. Clamping p into [0, n-1] first yields the
+// same sample as clamping each tap (outside, both taps are the edge texel).
+LF_HD void taps(float p, int n, int &i0, int &i1, float &f) {
+    const float q = fminf(fmaxf(p, 0.0f), (float)(n - 1));
+    i0 = (int)q;
+    f = q - (float)i0;
+    i1 = min(i0 + 1, n - 1);
+}
+
 // Bilinear sample at normalised image-plane point (Xs, Ys): texel centres at
 // half-integers, clamp-to-edge (result in texel units; see texel_scale).
 template <int IMG>
 LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float py) {
-    const float x0f = floorf(px), y0f = floorf(py);
-    const float fx = px - x0f, fy = py - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-    x0 = min(max(x0, 0), W - 1);
-    y0 = min(max(y0, 0), H - 1);
+    int x0, x1, y0, y1;
+    float fx, fy;
+    taps(px, W, x0, x1, fx);
+    taps(py, H, y0, y1, fy);
     const uint32_t r0 = mul24(y0, W), r1 = mul24(y1, W);
     const Rgb a = texel<IMG>(img, r0 + x0), b = texel<IMG>(img, r0 + x1);
     const Rgb c = texel<IMG>(img, r1 + x0), d = texel<IMG>(img, r1 + x1);
@@ -328,12 +455,10 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float p
 LF_HD Rgb bilinear_yuv(const void *__restrict__ yp, const void *__restrict__ uvp, int W, int H, float px, float py) {
     float lum;
     {
-        const float x0f = floorf(px), y0f = floorf(py);
-        const float fx = px - x0f, fy = py - y0f;
-        int x0 = (int)x0f, y0 = (int)y0f;
-        const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-        x0 = min(max(x0, 0), W - 1);
-        y0 = min(max(y0, 0), H - 1);
+        int x0, x1, y0, y1;
+        float fx, fy;
+        taps(px, W, x0, x1, fx);
+        taps(py, H, y0, y1, fy);
         const uint32_t r0 = mul24(y0, W), r1 = mul24(y1, W);
         const float a = at<uint8_t>(yp, r0 + x0), b = at<uint8_t>(yp, r0 + x1);
         const float c = at<uint8_t>(yp, r1 + x0), d = at<uint8_t>(yp, r1 + x1);
@@ -344,12 +469,10 @@ LF_HD Rgb bilinear_yuv(const void *__restrict__ yp, const void *__restrict__ uvp
     {
         const int Wc = W >> 1, Hc = H >> 1;
         const float cx = 0.5f * (px - 0.5f), cy = 0.5f * (py - 0.5f);
-        const float x0f = floorf(cx), y0f = floorf(cy);
-        const float fx = cx - x0f, fy = cy - y0f;
-        int x0 = (int)x0f, y0 = (int)y0f;
-        const int x1 = min(max(x0 + 1, 0), Wc - 1), y1 = min(max(y0 + 1, 0), Hc - 1);
-        x0 = min(max(x0, 0), Wc - 1);
-        y0 = min(max(y0, 0), Hc - 1);
+        int x0, x1, y0, y1;
+        float fx, fy;
+        taps(cx, Wc, x0, x1, fx);
+        taps(cy, Hc, y0, y1, fy);
         const uint32_t r0 = mul24(y0, Wc), r1 = mul24(y1, Wc);
         const uint32_t a = at<uint16_t>(uvp, r0 + x0), b = at<uint16_t>(uvp, r0 + x1);
         const uint32_t c = at<uint16_t>(uvp, r1 + x0), d = at<uint16_t>(uvp, r1 + x1);
@@ -370,12 +493,10 @@ LF_HD uint32_t paged_texel(const char *__restrict__ pool, int32_t page, int x, i
 }
 LF_HD bool bilinear_paged(const void *__restrict__ pt, const char *__restrict__ pool, int tiles_x, int W, int H,
                           float px, float py, Rgb &out) {
-    const float x0f = floorf(px), y0f = floorf(py);
-    const float fx = px - x0f, fy = py - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-    x0 = min(max(x0, 0), W - 1);
-    y0 = min(max(y0, 0), H - 1);
+    int x0, x1, y0, y1;
+    float fx, fy;
+    taps(px, W, x0, x1, fx);
+    taps(py, H, y0, y1, fy);
     const uint32_t r0 = mul24(y0 >> kPageShift, tiles_x), r1 = mul24(y1 >> kPageShift, tiles_x);
     const int32_t p00 = at<int32_t>(pt, r0 + (x0 >> kPageShift)), p10 = at<int32_t>(pt, r0 + (x1 >> kPageShift));
     const int32_t p01 = at<int32_t>(pt, r1 + (x0 >> kPageShift)), p11 = at<int32_t>(pt, r1 + (x1 >> kPageShift));
@@ -396,10 +517,10 @@ LF_HD bool bilinear_paged(const void *__restrict__ pt, const char *__restrict__ 
 
 // Visibility pass: mark the image tiles of the four taps of a sample.
 LF_HD void mark_taps(uint8_t *__restrict__ vis, int tiles_x, int W, int H, float px, float py) {
-    int x0 = (int)floorf(px), y0 = (int)floorf(py);
-    const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-    x0 = min(max(x0, 0), W - 1);
-    y0 = min(max(y0, 0), H - 1);
+    int x0, x1, y0, y1;
+    float fx, fy;
+    taps(px, W, x0, x1, fx);
+    taps(py, H, y0, y1, fy);
     const int r0 = (y0 >> kPageShift) * tiles_x, r1 = (y1 >> kPageShift) * tiles_x;
     vis[r0 + (x0 >> kPageShift)] = 1;
     vis[r0 + (x1 >> kPageShift)] = 1;
@@ -441,12 +562,10 @@ LF_HD void rgtc_chroma(const void *__restrict__ uvp, int Wb, int x, int y, float
 LF_HD Rgb bilinear_rgtc(const void *__restrict__ yp, const void *__restrict__ uvp, int W, int H, float px, float py) {
     float lum;
     {
-        const float x0f = floorf(px), y0f = floorf(py);
-        const float fx = px - x0f, fy = py - y0f;
-        int x0 = (int)x0f, y0 = (int)y0f;
-        const int x1 = min(max(x0 + 1, 0), W - 1), y1 = min(max(y0 + 1, 0), H - 1);
-        x0 = min(max(x0, 0), W - 1);
-        y0 = min(max(y0, 0), H - 1);
+        int x0, x1, y0, y1;
+        float fx, fy;
+        taps(px, W, x0, x1, fx);
+        taps(py, H, y0, y1, fy);
         const int Wb = W >> 2;
         const float a = rgtc_luma(yp, Wb, x0, y0), b = rgtc_luma(yp, Wb, x1, y0);
         const float c = rgtc_luma(yp, Wb, x0, y1), d = rgtc_luma(yp, Wb, x1, y1);
@@ -457,12 +576,10 @@ LF_HD Rgb bilinear_rgtc(const void *__restrict__ yp, const void *__restrict__ uv
     {
         const int Wc = W >> 1, Hc = H >> 1, Wb = W >> 3;
         const float cx = 0.5f * (px - 0.5f), cy = 0.5f * (py - 0.5f);
-        const float x0f = floorf(cx), y0f = floorf(cy);
-        const float fx = cx - x0f, fy = cy - y0f;
-        int x0 = (int)x0f, y0 = (int)y0f;
-        const int x1 = min(max(x0 + 1, 0), Wc - 1), y1 = min(max(y0 + 1, 0), Hc - 1);
-        x0 = min(max(x0, 0), Wc - 1);
-        y0 = min(max(y0, 0), Hc - 1);
+        int x0, x1, y0, y1;
+        float fx, fy;
+        taps(cx, Wc, x0, x1, fx);
+        taps(cy, Hc, y0, y1, fy);
         float ab, ar, bb, br, cb_, cr_, db, dr;
         rgtc_chroma(uvp, Wb, x0, y0, ab, ar);
         rgtc_chroma(uvp, Wb, x1, y0, bb, br);

@@ -1,6 +1,8 @@
-"""The kernels' per-ray arithmetic (exact disk test + two-level inverse-depth
-mesh walk, compiled for the host from the same header the kernels use)
-against the FP64 oracle's per-view records, ray by ray, on the CPU."""
+"""The kernels' per-ray arithmetic (exact disk test, the two-level
+inverse-depth mesh walk and the single walk from a culling start bound,
+compiled for the host from the same header the kernels use) against the
+FP64 oracle's per-view records, ray by ray, on the CPU; and the pieces of
+the start bound (cell box of a tile's rays, FP16 rounding up)."""
 import ctypes
 import os
 
@@ -19,14 +21,19 @@ def _lib():
         pytest.skip("liblf_hostcheck.so not built")
     import torch  # noqa: F401  (same HIP runtime as the rest of the process)
     L = ctypes.CDLL(SO)
-    L.lfh_trace.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                            ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
-                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                            ctypes.c_void_p]
+    for f in (L.lfh_trace, L.lfh_trace_top):
+        f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p]
+    L.lfh_tile_box.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_void_p]
+    L.lfh_half_up.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     return L
 
 
-def _trace(V, o, e, geo_fmt=0, R=None):
+def _trace(V, o, e, geo_fmt=0, R=None, top=False):
     L = _lib()
     n, M = V.n, V.mesh_m
     nr = len(o)
@@ -40,14 +47,14 @@ def _trace(V, o, e, geo_fmt=0, R=None):
     r = np.ascontiguousarray(V.rot.reshape(-1, 9))
     o = np.ascontiguousarray(o, np.float64)
     e = np.ascontiguousarray(e, np.float64)
-    L.lfh_trace(n, M, z.ctypes.data, c.ctypes.data, r.ctypes.data, V.src_fov_deg,
+    (L.lfh_trace_top if top else L.lfh_trace)(n, M, z.ctypes.data, c.ctypes.data, r.ctypes.data, V.src_fov_deg,
                 V.disk_radius if R is None else R, geo_fmt, nr, o.ctypes.data, e.ctypes.data, cand.ctypes.data,
                 hit.ctypes.data, Xs.ctypes.data, Ys.ctypes.data, cells.ctypes.data)
     return cand, hit, Xs, Ys, cells
 
 
-def _compare(V, ov, o, e, geo_fmt=0, xy_tol=2e-5):
-    cand, hit, Xs, Ys, cells = _trace(V, o, e, geo_fmt)
+def _compare(V, ov, o, e, geo_fmt=0, xy_tol=2e-5, top=False):
+    cand, hit, Xs, Ys, cells = _trace(V, o, e, geo_fmt, top=top)
     ts = np.tan(np.radians(V.src_fov_deg / 2))
     dom = 1 - 1 / V.mesh_m
     n_hits, bad_xy = 0, 0
@@ -107,3 +114,98 @@ def test_host_ray_math_fp16_geometry_close(tiny, tiny_oracle):
     d = np.maximum(np.abs(Xs[m] - X32[m]), np.abs(Ys[m] - Y32[m]))
     # 1 source pixel of the tiny views is 2 tan(60)/128 = 0.027 in X
     assert np.quantile(d, 0.99) < 0.027 * 0.05
+
+
+@pytest.mark.parametrize("top", [False, True], ids=["two_level", "start_bound"])
+def test_walk_forms_match_oracle_full_size_sample(top):
+    """The full-size field (1024 views, 256^2 depth) and stereo eyes of the
+    headline workload; both walks against the oracle ray by ray."""
+    V = lfsynth.make_views(1024, 32, 256, 12, seed=0)
+    ov = oracle.OracleViews.from_views(V)
+    p, R = lfsynth.poses(1000, 2, 0.25)
+    rng = np.random.default_rng(6)
+    total, bad_total = 0, 0
+    for k in range(2):
+        eye = oracle.stereo_eyes(p[k], R[k], 0.064)[k]
+        pxy = rng.uniform(0, [1440, 1600], (60, 2))
+        o, e = oracle.eye_rays(eye[0], eye[1], 100.0, 1440, 1600, pxy)
+        n_hits, bad, _ = _compare(V, ov, o, e, top=top)
+        total += n_hits
+        bad_total += bad
+    assert total > 500 and bad_total <= 0.002 * total, (total, bad_total)
+
+
+@pytest.mark.parametrize("geo_fmt", [0, 1])
+def test_start_bound_walk_finds_the_two_level_hits(tiny, geo_fmt):
+    """Same candidates and the same hits: a cell's root does not depend on
+    where the walk entered the cell, so the two walks agree bit for bit
+    wherever both reach the root's cell from above (all but rounding ties)."""
+    rng = np.random.default_rng(12)
+    pxy = rng.uniform(0, 256, (400, 2))
+    o, e = oracle.eye_rays(tiny.head_pos[0], tiny.head_rot[0], tiny.hfov_deg, 256, 256, pxy)
+    c0, h0, X0, Y0, n0 = _trace(tiny.views, o, e, geo_fmt=geo_fmt)
+    c1, h1, X1, Y1, n1 = _trace(tiny.views, o, e, geo_fmt=geo_fmt, top=True)
+    assert np.array_equal(c0, c1)
+    assert (h0 == h1).mean() > 0.999, (h0 != h1).sum()
+    m = (h0 == 1) & (h1 == 1)
+    assert m.sum() > 1500
+    d = np.maximum(np.abs(X0[m] - X1[m]), np.abs(Y0[m] - Y1[m]))
+    assert (d == 0).mean() > 0.999 and d.max() < 1e-5, ((d > 0).sum(), d.max())
+    assert n1[c1 == 1].mean() <= n0[c0 == 1].mean()
+    print("cells per candidate: two-level", n0[c0 == 1].mean(), "start bound", n1[c1 == 1].mean())
+
+
+def test_tile_cell_box_holds_every_ray_of_the_rectangle():
+    """Rays through random points of a rectangle, at random inverse depths of
+    the range, land (in FP64) inside the cell box computed from the corners."""
+    L = _lib()
+    rng = np.random.default_rng(21)
+    M = 256
+    sM, cM = np.float32(M / (2 * np.tan(np.radians(60)))), np.float32(0.5 * (M - 1))
+    checked = 0
+    for trial in range(300):
+        # a rotation close to the identity (the eye looks roughly along the view's axis)
+        a = rng.normal(size=3) * 0.3
+        K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+        Rm = np.eye(3) + np.sin(np.linalg.norm(a)) / np.linalg.norm(a) * K + \
+            (1 - np.cos(np.linalg.norm(a))) / np.linalg.norm(a) ** 2 * K @ K
+        m = Rm.astype(np.float32).reshape(9)
+        o = np.array([rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), rng.uniform(-0.6, -0.05)], np.float32)
+        wmin, wmax = np.float32(rng.uniform(0.1, 0.5)), np.float32(rng.uniform(0.6, 3.0))
+        X0 = np.float32(rng.uniform(-0.8, 0.7)); X1 = np.float32(X0 + rng.uniform(0.001, 0.1))
+        Y0 = np.float32(rng.uniform(-0.7, 0.8)); Y1 = np.float32(Y0 - rng.uniform(0.001, 0.1))
+        box = np.zeros(4, np.int32)
+        ok = L.lfh_tile_box(m.ctypes.data, o.ctypes.data, wmin, wmax, X0, X1, Y0, Y1, M, sM, cM, box.ctypes.data)
+        if not ok:
+            continue
+        if box[0] > box[1]:
+            continue  # the rectangle's rays miss the mesh domain
+        X = rng.uniform(X0, X1, 200); Y = rng.uniform(Y1, Y0, 200); w = rng.uniform(wmin, wmax, 200)
+        md = m.astype(np.float64).reshape(3, 3)
+        ex, ey, ez = md @ np.stack([X, Y, np.ones_like(X)])
+        Vx, Vy = ex / ez, ey / ez
+        Dx, Dy = o[0] - o[2] * Vx, o[1] - o[2] * Vy
+        gx = (Vx + w * Dx) * sM + cM
+        gy = cM - (Vy + w * Dy) * sM
+        inside = (gx >= 0) & (gx <= M - 1) & (gy >= 0) & (gy <= M - 1)
+        j = np.minimum(np.floor(gx), M - 2); k = np.minimum(np.floor(gy), M - 2)
+        assert ((j >= box[0]) & (j <= box[1]) & (k >= box[2]) & (k <= box[3]) | ~inside).all(), (trial, box)
+        checked += int(inside.sum())
+    assert checked > 10000, checked
+
+
+def test_half_up_bits_rounds_up_to_the_next_half():
+    L = _lib()
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.uniform(1e-3, 50.0, 20000), np.float16(rng.uniform(0.01, 10, 1000)).astype(np.float64),
+                        [65504.0, 65520.0, 1e6]]).astype(np.float32)
+    bits = np.zeros(len(x), np.uint16)
+    L.lfh_half_up(len(x), x.ctypes.data, bits.ctypes.data)
+    h = bits.view(np.float16).astype(np.float32)
+    assert (h >= x).all()
+    below = (bits - 1).view(np.float16).astype(np.float32)
+    assert (below < x).all()
+    # representable values are kept as they are; beyond the FP16 range: +inf
+    exact = np.float16(x).astype(np.float32) == x
+    assert (h[exact] == x[exact]).all()
+    assert np.isinf(h[-2:]).all()

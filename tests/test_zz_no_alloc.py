@@ -81,7 +81,7 @@ def test_noalloc_equals_render_on_two_calls_second_smaller(tiny, ctx):
 
 def test_noalloc_full_size_stereo_pair(tiny, ctx):
     """The largest per-eye size of the mixed batch (2160 x 2160), both eyes in
-    one launch (about 5 MiB of scratch)."""
+    one launch (about 9 MiB of scratch over the tiny field's 64 views)."""
     eyes, res = _eyes(34, [(2160, 2160)])
     _check_pair(ctx, eyes, tiny.hfov_deg, res)
 
@@ -89,7 +89,7 @@ def test_noalloc_full_size_stereo_pair(tiny, ctx):
 def test_noalloc_rejects_launches_beyond_its_scratch(tiny, ctx):
     import torch
     from paper_1810_08860_amd import lf
-    # 4 eyes of 4096 x 4096: 262,144 tiles of 132 bytes = 33 MiB in one launch
+    # 4 eyes of 4096 x 4096: 262,144 tiles of 260 bytes = 65 MiB in one launch
     eyes, res = _eyes(35, [(4096, 4096)] * 2)
     outs = _outputs(res, 5.0)
     rc = _noalloc_raw(ctx, eyes, tiny.hfov_deg, res, outs)
