@@ -359,11 +359,16 @@ __global__ void k_corr_pack(const float *__restrict__ prm, CorrLayout L, uint16_
 // image) over the tile grown by 4 pixels per side; each layer then computes
 // its output over a region one pixel smaller per side (22^2, 20^2, 18^2,
 // 16^2), entirely in LDS, with activations outside the image set to zero as
-// the per-layer zero padding requires. Every lane holds its B fragments of all
-// four layers in registers for the life of the workgroup (loaded once), so LDS
-// traffic is the A operand only. Regions are linearised row-major and cut into
-// 16-pixel MFMA row blocks; K-steps and packing match k_conv, so each layer
-// accumulates in the same order as the layer-by-layer path.
+// the per-layer zero padding requires. The weights are the MFMA's A operand:
+// every lane holds its fragments of layers 2 and 3 in registers for the life
+// of the workgroup, and fetches those of layers 1 and 4 (cached) at the start
+// of each use, so LDS traffic is the activations only. Regions are linearised
+// row-major and cut into 16-pixel MFMA row blocks, which a wave takes two at a
+// time; K-steps and packing match k_conv, so each layer accumulates in the
+// same order as the layer-by-layer path. The tile's own FP32 render values
+// stay in LDS (in the layer-1 input's space once layer 1 has read it) for the
+// final blend, so the next tile's inputs can be fetched into registers during
+// layers 2-4.
 constexpr int FT = 16;                                   // output tile side
 constexpr int FR0 = FT + 8, FR1 = FT + 6, FR2 = FT + 4, FR3 = FT + 2;
 constexpr int FPS = 40;                                  // hidden pixel stride: 32 channels + 8 pad
@@ -384,46 +389,95 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
 // channels. The weights are the MFMA's A operand and the activations its B
 // operand, so D[4 g + v][i] is channel 16 nb + 4 g + v of pixel 16 b + i:
 // each lane stores four consecutive channels of one pixel at once.
-template <int SOUT, bool IN8, int KS, int NBO, bool LAST>
+// PAIR: a wave takes two 16-pixel blocks at a time (blocks b and b + 4), four
+// independent accumulation chains. Each K-step's activations are read from
+// LDS one step ahead of the MFMAs that use them, and scheduling barriers keep
+// the compiler from hoisting further reads (registers: the weights of three
+// layers live in them for the whole kernel).
+template <int SOUT, bool IN8>
+__device__ __forceinline__ bf16x8 fused_a(const uint16_t *__restrict__ src, int x, int y, int s, int g) {
+    constexpr int SIN = SOUT + 2;
+    bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (IN8) {
+        const int t = 4 * s + g;  // four taps of 8 channels per K-step
+        if (t < 9) av = *reinterpret_cast<const bf16x8 *>(&src[((y + t / 3) * SIN + x + t % 3) * 8]);
+    } else {
+        av = *reinterpret_cast<const bf16x8 *>(&src[((y + s / 3) * SIN + x + s % 3) * FPS + 8 * g]);
+    }
+    return av;
+}
+
+template <int SOUT, int NBO, bool LAST>
+__device__ __forceinline__ void fused_store(const floatx4 (&acc)[NBO], int mm, uint16_t *__restrict__ dst,
+                                            float *__restrict__ res, const float *__restrict__ s_bias, int ox0,
+                                            int oy0, int H, int W, int g) {
+    constexpr int NOUT = SOUT * SOUT;
+    if (mm >= NOUT) return;
+    const int x = mm % SOUT, y = mm / SOUT;
+#pragma unroll
+    for (int nb = 0; nb < NBO; ++nb) {
+        const float4 bi = *reinterpret_cast<const float4 *>(&s_bias[16 * nb + 4 * g]);
+        const float v0 = acc[nb][0] + bi.x, v1 = acc[nb][1] + bi.y, v2 = acc[nb][2] + bi.z, v3 = acc[nb][3] + bi.w;
+        if (LAST) {
+            if (g == 0) *reinterpret_cast<float4 *>(&res[mm * 4]) = make_float4(v0, v1, v2, v3);
+        } else {
+            const int xx = ox0 + x, yy = oy0 + y;
+            uint2 o = make_uint2(0u, 0u);
+            if (xx >= 0 && xx < W && yy >= 0 && yy < H)
+                o = make_uint2(pack_bf16x2(fmaxf(v0, 0.0f), fmaxf(v1, 0.0f)), pack_bf16x2(fmaxf(v2, 0.0f), fmaxf(v3, 0.0f)));
+            *reinterpret_cast<uint2 *>(&dst[mm * FPS + 16 * nb + 4 * g]) = o;
+        }
+    }
+}
+
+template <int SOUT, bool IN8, int KS, int NBO, bool LAST, bool PAIR>
 __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, uint16_t *__restrict__ dst,
                                             float *__restrict__ res, const bf16x8 (&w)[KS][NBO],
                                             const float *__restrict__ s_bias, int ox0, int oy0, int H, int W) {
-    constexpr int SIN = SOUT + 2, NOUT = SOUT * SOUT, NBLK = (NOUT + 15) / 16;
+    constexpr int NOUT = SOUT * SOUT, NBLK = (NOUT + 15) / 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
-    for (int b = wave; b < NBLK; b += 4) {
-        const int mm = 16 * b + i;  // this lane's pixel
-        const int m = min(mm, NOUT - 1);
-        const int x = m % SOUT, y = m / SOUT;
-        floatx4 acc[NBO];
+    for (int b = wave; b < NBLK; b += PAIR ? 8 : 4) {
+        const int mm0 = 16 * b + i, mm1 = mm0 + 64;  // this lane's pixels (block b, block b + 4)
+        const int m0 = min(mm0, NOUT - 1);
+        const int x0 = m0 % SOUT, y0 = m0 / SOUT;
+        if (PAIR && b + 4 < NBLK) {
+            const int m1 = min(mm1, NOUT - 1);
+            const int x1 = m1 % SOUT, y1 = m1 / SOUT;
+            floatx4 acc0[NBO], acc1[NBO];
 #pragma unroll
-        for (int nb = 0; nb < NBO; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NBO; ++nb) acc0[nb] = acc1[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g), a1 = fused_a<SOUT, IN8>(src, x1, y1, 0, g);
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            if (IN8) {
-                const int t = 4 * s + g;  // four taps of 8 channels per K-step
-                if (t < 9)
-                    av = *reinterpret_cast<const bf16x8 *>(&src[((y + t / 3) * SIN + x + t % 3) * 8]);
-            } else {
-                av = *reinterpret_cast<const bf16x8 *>(&src[((y + s / 3) * SIN + x + s % 3) * FPS + 8 * g]);
+            for (int s = 0; s < KS; ++s) {
+                const bf16x8 c0 = a0, c1 = a1;
+                if (s + 1 < KS) {
+                    a0 = fused_a<SOUT, IN8>(src, x0, y0, s + 1, g);
+                    a1 = fused_a<SOUT, IN8>(src, x1, y1, s + 1, g);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NBO; ++nb) {
+                    acc0[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], c0, acc0[nb], 0, 0, 0);
+                    acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], c1, acc1[nb], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
+            fused_store<SOUT, NBO, LAST>(acc0, mm0, dst, res, s_bias, ox0, oy0, H, W, g);
+            fused_store<SOUT, NBO, LAST>(acc1, mm1, dst, res, s_bias, ox0, oy0, H, W, g);
+        } else {
+            floatx4 acc[NBO];
 #pragma unroll
-            for (int nb = 0; nb < NBO; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], av, acc[nb], 0, 0, 0);
-        }
-        if (mm >= NOUT) continue;
+            for (int nb = 0; nb < NBO; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g);
 #pragma unroll
-        for (int nb = 0; nb < NBO; ++nb) {
-            const float4 bi = *reinterpret_cast<const float4 *>(&s_bias[16 * nb + 4 * g]);
-            const float v0 = acc[nb][0] + bi.x, v1 = acc[nb][1] + bi.y, v2 = acc[nb][2] + bi.z, v3 = acc[nb][3] + bi.w;
-            if (LAST) {
-                if (g == 0) *reinterpret_cast<float4 *>(&res[mm * 4]) = make_float4(v0, v1, v2, v3);
-            } else {
-                const int xx = ox0 + x, yy = oy0 + y;
-                uint2 o = make_uint2(0u, 0u);
-                if (xx >= 0 && xx < W && yy >= 0 && yy < H)
-                    o = make_uint2(pack_bf16x2(fmaxf(v0, 0.0f), fmaxf(v1, 0.0f)), pack_bf16x2(fmaxf(v2, 0.0f), fmaxf(v3, 0.0f)));
-                *reinterpret_cast<uint2 *>(&dst[mm * FPS + 16 * nb + 4 * g]) = o;
+            for (int s = 0; s < KS; ++s) {
+                const bf16x8 c0 = a0;
+                if (s + 1 < KS) a0 = fused_a<SOUT, IN8>(src, x0, y0, s + 1, g);
+#pragma unroll
+                for (int nb = 0; nb < NBO; ++nb)
+                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], c0, acc[nb], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
+            fused_store<SOUT, NBO, LAST>(acc, mm0, dst, res, s_bias, ox0, oy0, H, W, g);
         }
     }
 }
@@ -441,6 +495,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ __attribute__((aligned(16))) uint16_t s_b[FR2 * FR2 * FPS];  // layer 2, then the residual
     __shared__ __attribute__((aligned(16))) float s_bias[4][32];
     float *s_res = reinterpret_cast<float *>(s_b);
+    // the tile's own render values (FP32 RGB of its 16 x 16 pixels), kept in
+    // s_in's space once layer 1 has read it, for the final blend
+    float *s_rgb = reinterpret_cast<float *>(s_in);
+    static_assert(sizeof(s_in) >= FT * FT * 3 * sizeof(float), "stash fits in the layer-1 input");
     const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, g = lane >> 4;
 
     // padded biases of the four layers
@@ -448,10 +506,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int l = tid >> 5, c = tid & 31;
         s_bias[l][c] = (l < 3 || c < 16) ? bbuf[L.layer[l].b_off + c] : 0.0f;
     }
-    // this lane's weight fragments of layers 2-4 (row 16 nb + i, columns
-    // 32 s + 8 g ..), held for the life of the workgroup; layer 1's are
-    // fetched per tile (cached), which leaves registers for the prefetch below
-    bf16x8 w2[9][2], w3[9][2], w4[9][1];
+    // this lane's weight fragments of layers 2-3 (row 16 nb + i, columns
+    // 32 s + 8 g ..), held for the life of the workgroup; layers 1 and 4's
+    // are fetched per tile (cached), which leaves registers for the prefetch
+    // below and for two blocks in flight per wave
+    bf16x8 w2[9][2], w3[9][2];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
         const int co = 16 * nb + i;
@@ -461,9 +520,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             w3[s][nb] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[2].wf_off + co * L.layer[2].kf + 32 * s + 8 * g]);
         }
     }
-#pragma unroll
-    for (int s = 0; s < 9; ++s)
-        w4[s][0] = *reinterpret_cast<const bf16x8 *>(&wbuf[L.layer[3].wf_off + i * L.layer[3].kf + 32 * s + 8 * g]);
 
     const int tx = (W + FT - 1) / FT, ty = (H + FT - 1) / FT;
     const int total = N * tx * ty;
@@ -523,15 +579,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int s = 0; s < 3; ++s)
                 w1[s][nb] = *reinterpret_cast<const bf16x8 *>(
                     &wbuf[wz + L.layer[0].wf_off + (16 * nb + i) * L.layer[0].kf + 32 * s + 8 * g]);
+        __syncthreads();
+        fused_layer<FR1, true, 3, 2, false, false>(s_in, s_a, nullptr, w1, s_bias[0], x0 - 3, y0 - 3, H, W);
+        __syncthreads();
+        // s_in is free: keep this tile's render values for the blend, then
+        // fetch the next tile's inputs into the registers that held them
+#pragma unroll
+        for (int k = 0; k < QN; ++k) {
+            const int q = tid + 256 * k;
+            const int cx = q % FR0 - 4, cy = q / FR0 - 4;
+            if (q < FR0 * FR0 && cx >= 0 && cx < FT && cy >= 0 && cy < FT) {
+                float *d = &s_rgb[(cy * FT + cx) * 3];
+                d[0] = pr[k];
+                d[1] = pg[k];
+                d[2] = pb[k];
+            }
+        }
         if (tile + (int)gridDim.x < total) fetch(tile + gridDim.x);
+        fused_layer<FR2, false, 9, 2, false, true>(s_a, s_b, nullptr, w2, s_bias[1], x0 - 2, y0 - 2, H, W);
         __syncthreads();
-        fused_layer<FR1, true, 3, 2, false>(s_in, s_a, nullptr, w1, s_bias[0], x0 - 3, y0 - 3, H, W);
+        fused_layer<FR3, false, 9, 2, false, true>(s_b, s_a, nullptr, w3, s_bias[2], x0 - 1, y0 - 1, H, W);
         __syncthreads();
-        fused_layer<FR2, false, 9, 2, false>(s_a, s_b, nullptr, w2, s_bias[1], x0 - 2, y0 - 2, H, W);
-        __syncthreads();
-        fused_layer<FR3, false, 9, 2, false>(s_b, s_a, nullptr, w3, s_bias[2], x0 - 1, y0 - 1, H, W);
-        __syncthreads();
-        fused_layer<FT, false, 9, 1, true>(s_a, nullptr, s_res, w4, s_bias[3], x0, y0, H, W);
+        {
+            int wz4 = 0;
+            asm volatile("" : "+s"(wz4));
+            bf16x8 w4[9][1];
+#pragma unroll
+            for (int s = 0; s < 9; ++s)
+                w4[s][0] = *reinterpret_cast<const bf16x8 *>(&wbuf[wz4 + L.layer[3].wf_off + i * L.layer[3].kf + 32 * s + 8 * g]);
+            fused_layer<FT, false, 9, 1, true, true>(s_a, nullptr, s_res, w4, s_bias[3], x0, y0, H, W);
+        }
         __syncthreads();
         // finish: out = render + residual, or the render where max |residual| > thresh
         {
@@ -540,7 +617,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 const int64_t p = img + (int64_t)yy * W + xx;
                 const float r0 = s_res[tid * 4], r1 = s_res[tid * 4 + 1], r2 = s_res[tid * 4 + 2];
                 const bool f = fmaxf(fabsf(r0), fmaxf(fabsf(r1), fabsf(r2))) > thresh;
-                const float c0 = rgb[3 * p], c1 = rgb[3 * p + 1], c2 = rgb[3 * p + 2];
+                const float c0 = s_rgb[tid * 3], c1 = s_rgb[tid * 3 + 1], c2 = s_rgb[tid * 3 + 2];
                 out[3 * p] = f ? c0 : c0 + r0;
                 out[3 * p + 1] = f ? c1 : c1 + r1;
                 out[3 * p + 2] = f ? c2 : c2 + r2;
