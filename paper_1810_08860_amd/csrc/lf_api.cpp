@@ -306,9 +306,11 @@ CullGeo cull_geo(const lf_ctx *c) {
     return g;
 }
 
-// Device scratch of one launch chunk: eye-view records, tile lists, tile counts.
+// Device scratch of one launch chunk: eye-view records, per-eye view lists and
+// counts, tile lists, tile counts.
 size_t chunk_scratch_bytes(const lf_ctx *c, const EyeChunk &ch) {
-    return al256(sizeof(EyeView) * (size_t)ch.n_eyes * c->n) + al256(sizeof(uint32_t) * (size_t)kListCap * ch.total_tiles) +
+    return al256(sizeof(EyeView) * (size_t)ch.n_eyes * c->n) + al256(sizeof(uint16_t) * (size_t)ch.n_eyes * c->n) +
+           al256(sizeof(int32_t) * (size_t)ch.n_eyes) + al256(sizeof(uint32_t) * (size_t)kListCap * ch.total_tiles) +
            al256(sizeof(int32_t) * (size_t)ch.total_tiles);
 }
 
@@ -325,12 +327,17 @@ int prep_and_cull(lf_ctx *c, EyeChunk &ch, RenderArgs &a, double R, hipStream_t 
     }
     char *p = fixed ? (char *)fixed : (char *)c->scratch;
     EyeView *ev = (EyeView *)p;
-    uint32_t *tl = (uint32_t *)(p + al(ev_bytes));
-    int32_t *tc = (int32_t *)(p + al(ev_bytes) + al(list_bytes));
+    p += al(ev_bytes);
+    uint16_t *el = (uint16_t *)p;
+    p += al(sizeof(uint16_t) * (size_t)ch.n_eyes * c->n);
+    int32_t *ec = (int32_t *)p;
+    p += al(sizeof(int32_t) * (size_t)ch.n_eyes);
+    uint32_t *tl = (uint32_t *)p;
+    int32_t *tc = (int32_t *)(p + al(list_bytes));
     // conservative disk bounds for the tile test; the exact per-ray test decides in k_render
     const DiskBound db{c->vrad, R, R / c->R, c->vmask};
     LF_HIP(timed_launch(c, 0, s, [&] { return launch_prep(ch, c->vt, c->wr, c->n, db, view_bases(c), ev, s); }), "k_prep launch");
-    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, cull_geo(c), ev, c->n, tl, tc, s); }), "k_cull launch");
+    LF_HIP(timed_launch(c, 1, s, [&] { return launch_cull(ch, cull_geo(c), ev, c->n, el, ec, tl, tc, s); }), "k_cull launch");
     a.ev = ev;
     a.tile_list = tl;
     a.tile_count = tc;
@@ -1120,10 +1127,11 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     // device buffers: eye table, eye-view records, tile lists, counts, queue, stamps
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t ev_b = al(sizeof(EyeView) * (size_t)n_eyes * c->n);
+    const size_t el_b = al(sizeof(uint16_t) * (size_t)n_eyes * c->n), ec_b = al(sizeof(int32_t) * (size_t)n_eyes);
     const size_t tl_b = al(sizeof(uint32_t) * (size_t)kListCap * tiles);
     const size_t tc_b = al(sizeof(int32_t) * (size_t)tiles);
     const size_t q_b = al(sizeof(unsigned int) * kQueueStride * kXcds), ft_b = al(sizeof(unsigned long long) * 2 * (size_t)n_eyes);
-    const size_t need = ev_b + tl_b + tc_b + q_b + ft_b;
+    const size_t need = ev_b + tl_b + tc_b + q_b + ft_b + el_b + ec_b;
     if (need > B.buf_bytes || n_eyes > B.eyes_cap) {
         if (B.copied) LF_HIP(hipEventSynchronize(B.copied), "hipEventSynchronize");
         LF_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -1166,6 +1174,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
     b.queue = (unsigned int *)(p + ev_b + tl_b + tc_b);
     for (int x = 0; x < kXcds; ++x) b.q_len[x] = q_len[x];
     b.frame_t = (unsigned long long *)(p + ev_b + tl_b + tc_b + q_b);
+    uint16_t *elist = (uint16_t *)(p + ev_b + tl_b + tc_b + q_b + ft_b);
+    int32_t *ecount = (int32_t *)(p + ev_b + tl_b + tc_b + q_b + ft_b + el_b);
     B.frame_t = b.frame_t;
     B.n_eyes = n_eyes;
 
@@ -1192,8 +1202,8 @@ int lf_render_batch(lf_ctx *c, const lf_eye *eyes, int32_t n_eyes, double hfov_d
             LF_HIP(hipEventCreate(&B.ph_b), "hipEventCreate");
         }
         LF_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, view_bases(c), cull_geo(c), c->img_fmt, c->geo_fmt,
-                                    grid, B.cap_stream, nullptr, nullptr);
+        hipError_t e = launch_batch(b, a, c->vt, c->wr, c->n, db, view_bases(c), cull_geo(c), elist, ecount, c->img_fmt,
+                                    c->geo_fmt, grid, B.cap_stream, nullptr, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(B.cap_stream, &g);
         if (e != hipSuccess) {

@@ -182,15 +182,16 @@ hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t 
 hipError_t launch_geo_win(const void *cells, int geo_fmt, int32_t n, int32_t M, uint16_t *win, hipStream_t s);
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
                        const ViewBases &vb, EyeView *ev, hipStream_t s);
-hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint32_t *tile_list,
-                       int32_t *tile_count, hipStream_t s);
+// per-eye lists of the views the eye-level cull keeps (elist [n_eyes][n], ecount [n_eyes]), then the tile lists
+hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint16_t *elist,
+                       int32_t *ecount, uint32_t *tile_list, int32_t *tile_count, hipStream_t s);
 hipError_t launch_render(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, int mode,
                          hipStream_t s);
 // reset + prep + cull + persistent render of a batch (a.ev / tile lists are the batch's buffers)
 // ev_a / ev_b (may be null) are recorded just before / after the persistent render kernel
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, int img_fmt, int geo_fmt, int grid,
-                        hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
+                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, uint16_t *elist, int32_t *ecount,
+                        int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 // occupancy of the persistent render kernel (oval: the oval-disk form)
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu);
 // RGBA8 [n][H][W] device images -> kPage x kPage tiles, [n][tiles_y][tiles_x][kPage][kPage]

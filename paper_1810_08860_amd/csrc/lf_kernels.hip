@@ -339,6 +339,32 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     return out;
 }
 
+// Per eye: the views its eye-level cull keeps (record rk > 0), ascending, so
+// the culling kernels test only those. One workgroup per eye; ballot and
+// prefix popcount per wave, the four wave counts prefixed across the group.
+__global__ __launch_bounds__(256) void k_eye_list(const EyeView *__restrict__ ev, int32_t n,
+                                                  uint16_t *__restrict__ elist, int32_t *__restrict__ ecount) {
+    __shared__ int wcnt[4];
+    const int e = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const EyeView *eve = ev + (int64_t)e * n;
+    uint16_t *out = elist + (int64_t)e * n;
+    int count = 0;
+    for (int base = 0; base < n; base += 256) {
+        const int v = base + (int)threadIdx.x;
+        const bool keep = v < n && eve[v].rk > 0.0f;
+        const uint64_t mask = __ballot(keep);
+        if (lane == 0) wcnt[wave] = __popcll(mask);
+        __syncthreads();
+        int off = count;
+        for (int w = 0; w < wave; ++w) off += wcnt[w];
+        if (keep) out[off + __popcll(mask & below)] = (uint16_t)v;
+        count += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ecount[e] = count;
+}
+
 __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *__restrict__ vt,
                                               const float2 *__restrict__ wr, int32_t n, const DiskBound db,
                                               const ViewBases vb, EyeView *__restrict__ ev) {
@@ -505,9 +531,9 @@ __device__ __forceinline__ void list_bounds(const CullGeo &g, uint32_t *lst, con
 }
 
 __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int tile_w, int tile_h,
-                                           const EyeView *__restrict__ eve, int32_t n, const CullGeo &g,
-                                           uint32_t *__restrict__ tile_list, int32_t *__restrict__ tile_count,
-                                           CullSmem &sm) {
+                                           const EyeView *__restrict__ eve, const uint16_t *__restrict__ elist,
+                                           int32_t ne, const CullGeo &g, uint32_t *__restrict__ tile_list,
+                                           int32_t *__restrict__ tile_count, CullSmem &sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int tx0 = (local % E.supers_x) * kSuper, ty0 = (local / E.supers_x) * kSuper;
@@ -523,9 +549,10 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
         float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
         const bool any = E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1);
         int scount = 0;
-        for (int base = 0; base < n; base += 256) {
-            const int v = base + (int)threadIdx.x;
-            const bool keep = any && v < n && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
+        for (int base = 0; base < ne; base += 256) {
+            const int q = base + (int)threadIdx.x;
+            const int v = q < ne ? (int)elist[q] : 0;
+            const bool keep = any && q < ne && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
             const uint64_t mask = __ballot(keep);
             if (lane == 0) sm.wcnt[wave] = __popcll(mask);
             __syncthreads();
@@ -544,7 +571,7 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
     const int scount = sm.wcnt[0];
     __syncthreads();
     const bool sover = scount > kSuperCap;
-    const int ns = sover ? n : scount;
+    const int ns = sover ? ne : scount;
 
     // phase 2: each wavefront tests the survivors against its tiles
     for (int t = wave; t < kSuper * kSuper; t += 4) {
@@ -559,7 +586,7 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
             const bool any = E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1);
             for (int b = 0; any && b < ns; b += 64) {
                 const int s = b + lane;
-                const int v = s < ns ? (sover ? s : (int)sm.slist[s]) : -1;
+                const int v = s < ns ? (int)(sover ? elist[s] : sm.slist[s]) : -1;
                 const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
                 const uint64_t mask = __ballot(keep);
                 if (keep) {
@@ -593,13 +620,14 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
 }
 
 __global__ __launch_bounds__(256) void k_cull(const EyeChunk ch, const CullGeo g, const EyeView *__restrict__ ev,
-                                              int32_t n, uint32_t *__restrict__ tile_list,
+                                              int32_t n, const uint16_t *__restrict__ elist,
+                                              const int32_t *__restrict__ ecount, uint32_t *__restrict__ tile_list,
                                               int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_super(ch, super);
-    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, n, g, tile_list,
-               tile_count, sm);
+    cull_super(ch.e[e], super - ch.e[e].super_off, ch.tile_w, ch.tile_h, ev + (int64_t)e * n, elist + (int64_t)e * n,
+               ecount[e], g, tile_list, tile_count, sm);
 }
 
 // Eye whose range [off(e), off(e+1)) holds item t, for a device eye table
@@ -617,14 +645,16 @@ __device__ __forceinline__ int find_eye_sorted(const EyeParam *__restrict__ eyes
 
 __global__ __launch_bounds__(256) void k_cull_batch(const BatchArgs b, const CullGeo g,
                                                     const EyeView *__restrict__ ev, int32_t n,
+                                                    const uint16_t *__restrict__ elist,
+                                                    const int32_t *__restrict__ ecount,
                                                     uint32_t *__restrict__ tile_list,
                                                     int32_t *__restrict__ tile_count) {
     __shared__ CullSmem sm;
     const int super = blockIdx.x;
     const int e = find_eye_sorted(b.eyes, b.n_eyes, super, true);
     const EyeParam E = b.eyes[e];
-    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, n, g, tile_list, tile_count,
-               sm);
+    cull_super(E, super - E.super_off, b.tile_w, b.tile_h, ev + (int64_t)e * n, elist + (int64_t)e * n, ecount[e],
+               g, tile_list, tile_count, sm);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1081,9 +1111,11 @@ hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, i
     return hipGetLastError();
 }
 
-hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint32_t *tile_list,
-                       int32_t *tile_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, g, ev, n, tile_list, tile_count);
+hipError_t launch_cull(const EyeChunk &ch, const CullGeo &g, const EyeView *ev, int32_t n, uint16_t *elist,
+                       int32_t *ecount, uint32_t *tile_list, int32_t *tile_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_eye_list, dim3(ch.n_eyes), dim3(256), 0, s, ev, n, elist, ecount);
+    hipLaunchKernelGGL(k_cull, dim3(ch.total_supers), dim3(256), 0, s, ch, g, ev, n, elist, ecount, tile_list,
+                       tile_count);
     return hipGetLastError();
 }
 
@@ -1153,12 +1185,13 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
 }
 
 hipError_t launch_batch(const BatchArgs &b, const RenderArgs &a, const double *vt, const float2 *wr, int32_t n,
-                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, int img_fmt, int geo_fmt, int grid,
-                        hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
+                        const DiskBound &db, const ViewBases &vb, const CullGeo &g, uint16_t *elist, int32_t *ecount,
+                        int img_fmt, int geo_fmt, int grid, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
     hipLaunchKernelGGL(k_batch_reset, dim3((b.n_eyes + 255) / 256), dim3(256), 0, s, b.queue, b.frame_t, b.n_eyes);
     hipLaunchKernelGGL(k_prep_batch, dim3((n + 255) / 256, b.n_eyes), dim3(256), 0, s, b, vt, wr, n, db, vb,
                        const_cast<EyeView *>(a.ev));
-    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, g, a.ev, n,
+    hipLaunchKernelGGL(k_eye_list, dim3(b.n_eyes), dim3(256), 0, s, a.ev, n, elist, ecount);
+    hipLaunchKernelGGL(k_cull_batch, dim3(b.total_supers), dim3(256), 0, s, b, g, a.ev, n, elist, ecount,
                        const_cast<uint32_t *>(a.tile_list), const_cast<int32_t *>(a.tile_count));
     if (ev_a) {
         hipError_t e = hipEventRecordWithFlags(ev_a, s, hipEventRecordExternal);
