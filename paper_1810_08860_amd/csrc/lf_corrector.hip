@@ -407,33 +407,48 @@ __device__ __forceinline__ bf16x8 fused_a(const uint16_t *__restrict__ src, int 
     return av;
 }
 
+// The accumulators already hold the bias (fused_bias). interior: the tile's
+// whole region lies inside the image, so no activation needs the zero of the
+// per-layer padding.
 template <int SOUT, int NBO, bool LAST>
 __device__ __forceinline__ void fused_store(const floatx4 (&acc)[NBO], int mm, uint16_t *__restrict__ dst,
-                                            float *__restrict__ res, const float *__restrict__ s_bias, int ox0,
-                                            int oy0, int H, int W, int g) {
+                                            float *__restrict__ res, bool interior, int ox0, int oy0, int H, int W,
+                                            int g) {
     constexpr int NOUT = SOUT * SOUT;
     if (mm >= NOUT) return;
     const int x = mm % SOUT, y = mm / SOUT;
+    const int xx = ox0 + x, yy = oy0 + y;
+    const bool in = interior || (xx >= 0 && xx < W && yy >= 0 && yy < H);
 #pragma unroll
     for (int nb = 0; nb < NBO; ++nb) {
-        const float4 bi = *reinterpret_cast<const float4 *>(&s_bias[16 * nb + 4 * g]);
-        const float v0 = acc[nb][0] + bi.x, v1 = acc[nb][1] + bi.y, v2 = acc[nb][2] + bi.z, v3 = acc[nb][3] + bi.w;
+        const float v0 = acc[nb][0], v1 = acc[nb][1], v2 = acc[nb][2], v3 = acc[nb][3];
         if (LAST) {
             if (g == 0) *reinterpret_cast<float4 *>(&res[mm * 4]) = make_float4(v0, v1, v2, v3);
         } else {
-            const int xx = ox0 + x, yy = oy0 + y;
             uint2 o = make_uint2(0u, 0u);
-            if (xx >= 0 && xx < W && yy >= 0 && yy < H)
+            if (in)
                 o = make_uint2(pack_bf16x2(fmaxf(v0, 0.0f), fmaxf(v1, 0.0f)), pack_bf16x2(fmaxf(v2, 0.0f), fmaxf(v3, 0.0f)));
             *reinterpret_cast<uint2 *>(&dst[mm * FPS + 16 * nb + 4 * g]) = o;
         }
     }
 }
 
+// Accumulator start values: the bias of this lane's four output channels
+// (channel 16 nb + 4 g + v sits in element v of block nb's D fragment).
+template <int NBO>
+__device__ __forceinline__ void fused_bias(floatx4 (&acc)[NBO], const float *__restrict__ s_bias, int g) {
+#pragma unroll
+    for (int nb = 0; nb < NBO; ++nb) {
+        const float4 bi = *reinterpret_cast<const float4 *>(&s_bias[16 * nb + 4 * g]);
+        acc[nb] = floatx4{bi.x, bi.y, bi.z, bi.w};
+    }
+}
+
 template <int SOUT, bool IN8, int KS, int NBO, bool LAST, bool PAIR>
 __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, uint16_t *__restrict__ dst,
                                             float *__restrict__ res, const bf16x8 (&w)[KS][NBO],
-                                            const float *__restrict__ s_bias, int ox0, int oy0, int H, int W) {
+                                            const float *__restrict__ s_bias, bool interior, int ox0, int oy0, int H,
+                                            int W) {
     constexpr int NOUT = SOUT * SOUT, NBLK = (NOUT + 15) / 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
     for (int b = wave; b < NBLK; b += PAIR ? 8 : 4) {
@@ -444,8 +459,8 @@ __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, ui
             const int m1 = min(mm1, NOUT - 1);
             const int x1 = m1 % SOUT, y1 = m1 / SOUT;
             floatx4 acc0[NBO], acc1[NBO];
-#pragma unroll
-            for (int nb = 0; nb < NBO; ++nb) acc0[nb] = acc1[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            fused_bias<NBO>(acc0, s_bias, g);
+            fused_bias<NBO>(acc1, s_bias, g);
             bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g), a1 = fused_a<SOUT, IN8>(src, x1, y1, 0, g);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
@@ -461,12 +476,11 @@ __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, ui
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            fused_store<SOUT, NBO, LAST>(acc0, mm0, dst, res, s_bias, ox0, oy0, H, W, g);
-            fused_store<SOUT, NBO, LAST>(acc1, mm1, dst, res, s_bias, ox0, oy0, H, W, g);
+            fused_store<SOUT, NBO, LAST>(acc0, mm0, dst, res, interior, ox0, oy0, H, W, g);
+            fused_store<SOUT, NBO, LAST>(acc1, mm1, dst, res, interior, ox0, oy0, H, W, g);
         } else {
             floatx4 acc[NBO];
-#pragma unroll
-            for (int nb = 0; nb < NBO; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            fused_bias<NBO>(acc, s_bias, g);
             bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
@@ -477,7 +491,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, ui
                     acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], c0, acc[nb], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            fused_store<SOUT, NBO, LAST>(acc, mm0, dst, res, s_bias, ox0, oy0, H, W, g);
+            fused_store<SOUT, NBO, LAST>(acc, mm0, dst, res, interior, ox0, oy0, H, W, g);
         }
     }
 }
@@ -580,7 +594,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 w1[s][nb] = *reinterpret_cast<const bf16x8 *>(
                     &wbuf[wz + L.layer[0].wf_off + (16 * nb + i) * L.layer[0].kf + 32 * s + 8 * g]);
         __syncthreads();
-        fused_layer<FR1, true, 3, 2, false, false>(s_in, s_a, nullptr, w1, s_bias[0], x0 - 3, y0 - 3, H, W);
+        // the layer-1 input region (4 pixels of margin) inside the image: no padding zeros anywhere
+        const bool interior = x0 >= 4 && y0 >= 4 && x0 + FT + 4 <= W && y0 + FT + 4 <= H;
+        fused_layer<FR1, true, 3, 2, false, false>(s_in, s_a, nullptr, w1, s_bias[0], interior, x0 - 3, y0 - 3, H, W);
         __syncthreads();
         // s_in is free: keep this tile's render values for the blend, then
         // fetch the next tile's inputs into the registers that held them
@@ -596,9 +612,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
         }
         if (tile + (int)gridDim.x < total) fetch(tile + gridDim.x);
-        fused_layer<FR2, false, 9, 2, false, true>(s_a, s_b, nullptr, w2, s_bias[1], x0 - 2, y0 - 2, H, W);
+        fused_layer<FR2, false, 9, 2, false, true>(s_a, s_b, nullptr, w2, s_bias[1], interior, x0 - 2, y0 - 2, H, W);
         __syncthreads();
-        fused_layer<FR3, false, 9, 2, false, true>(s_b, s_a, nullptr, w3, s_bias[2], x0 - 1, y0 - 1, H, W);
+        fused_layer<FR3, false, 9, 2, false, true>(s_b, s_a, nullptr, w3, s_bias[2], interior, x0 - 1, y0 - 1, H, W);
         __syncthreads();
         {
             int wz4 = 0;
@@ -607,7 +623,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int s = 0; s < 9; ++s)
                 w4[s][0] = *reinterpret_cast<const bf16x8 *>(&wbuf[wz4 + L.layer[3].wf_off + i * L.layer[3].kf + 32 * s + 8 * g]);
-            fused_layer<FT, false, 9, 1, true, true>(s_a, nullptr, s_res, w4, s_bias[3], x0, y0, H, W);
+            fused_layer<FT, false, 9, 1, true, true>(s_a, nullptr, s_res, w4, s_bias[3], interior, x0, y0, H, W);
         }
         __syncthreads();
         // finish: out = render + residual, or the render where max |residual| > thresh
