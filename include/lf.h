@@ -154,7 +154,8 @@ typedef struct {
  * images to img_fmt, turn each depth map into per-cell inverse-depth corners
  * (the vertex set of the view's mesh, Sec. 4.5) and record each view's
  * inverse-depth range. The caller may free every input on return.
- * Errors: LF_EINVAL for a null pointer, non-positive size, mesh_m < 2,
+ * Errors: LF_EINVAL for a null pointer, non-positive size, an image side
+ * below 2, mesh_m < 2,
  * img_w != img_h, FOV outside (0,180), a frame not orthonormal to 1e-6, a
  * depth that is not finite and positive, or R <= 0; LF_EINVAL also when an
  * image dimension reaches 2^24 or one view's share of any per-view array

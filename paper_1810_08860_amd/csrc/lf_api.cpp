@@ -258,6 +258,8 @@ RenderArgs base_args(const lf_ctx *c, double R) {
     a.M = c->M;
     a.img_w = c->img_w;
     a.img_h = c->img_h;
+    a.img_limx = (float)(c->img_w - 1);
+    a.img_limy = (float)(c->img_h - 1);
     a.sM = (float)(c->M / (2.0 * c->tan_s));
     a.cM = (float)(0.5 * (c->M - 1));
     a.sW = (float)(c->img_w / (2.0 * c->tan_s));
@@ -366,7 +368,7 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
     if (!d || !out) return fail(LF_EINVAL, "NULL argument");
     *out = nullptr;
     if (d->n_views <= 0 || d->n_views > 65535) return fail(LF_EINVAL, "n_views must be in [1, 65535] (got %d)", d->n_views);
-    if (d->img_w <= 0 || d->img_h <= 0) return fail(LF_EINVAL, "image size must be positive");
+    if (d->img_w < 2 || d->img_h < 2) return fail(LF_EINVAL, "image size must be at least 2 x 2");
     if (d->img_w != d->img_h) return fail(LF_EINVAL, "source views must be square (got %dx%d)", d->img_w, d->img_h);
     if (d->mesh_m < 2 || d->mesh_m > 8192) return fail(LF_EINVAL, "mesh_m must be in [2, 8192] (got %d)", d->mesh_m);
     if (!(d->src_fov_deg > 0.0 && d->src_fov_deg < 180.0)) return fail(LF_EINVAL, "src_fov_deg must be in (0,180)");

@@ -127,6 +127,7 @@ struct RenderArgs {
     int32_t list_cap;           // a tile with more candidates than this takes the scan over every view
     int32_t NB;                 // inverse-depth blocks per side of a view's mesh
     int32_t M, img_w, img_h;
+    float img_limx, img_limy;   // img_w - 1, img_h - 1 (clamp-to-edge limits of the texel coordinate)
     float sM, cM;               // grid coordinate g = X sM + cM (and cM - Y sM)
     float sW, cW, sH, cH;       // texel coordinate px = Xs sW + cW, py = cH - Ys sH
     float invR;                 // circular disks: 1 / radius

@@ -777,7 +777,7 @@ __device__ __forceinline__ void render_tile(const EyeParam &E, int e, int tile, 
             } else if constexpr (IMG == 4) {
                 col = bilinear_rgtc(v.img, v.img2, a.img_w, a.img_h, tpx, tpy);
             } else {
-                col = bilinear<IMG>(v.img, a.img_w, a.img_h, tpx, tpy);
+                col = bilinear<IMG>(v.img, a.img_w, a.img_h, a.img_limx, a.img_limy, tpx, tpy);
             }
             accr = fmaf(rv.rho, col.r, accr);
             accg = fmaf(rv.rho, col.g, accg);

@@ -429,17 +429,36 @@ LF_HD void taps(float p, int n, int &i0, int &i1, float &f) {
     i1 = min(i0 + 1, n - 1);
 }
 
+// The same taps for n >= 2 texels, with the second tap always i0 + 1: the
+// position clamped into [0, lim] (lim = n - 1 as a float), i0 = min(floor,
+// n - 2) and the weight f in [0, 1] of i0 + 1. The sample equals the one of
+// taps() (at the last texel the whole weight sits on i0 + 1 = n - 1), and
+// the four taps of a bilinear sample sit at fixed offsets from the first.
+LF_HD float clamp_to(float p, float lim) {  // p clamped into [0, lim] (p finite, lim >= 0)
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(p, 0.0f, lim);
+#else
+    return fminf(fmaxf(p, 0.0f), lim);
+#endif
+}
+LF_HD void taps_next(float p, int n, float lim, int &i0, float &f) {
+    const float q = clamp_to(p, lim);
+    i0 = min((int)q, n - 2);
+    f = q - (float)i0;
+}
+
 // Bilinear sample at normalised image-plane point (Xs, Ys): texel centres at
 // half-integers, clamp-to-edge (result in texel units; see texel_scale).
+// W, H >= 2; limx = W - 1, limy = H - 1.
 template <int IMG>
-LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float px, float py) {
-    int x0, x1, y0, y1;
+LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float limx, float limy, float px, float py) {
+    int x0, y0;
     float fx, fy;
-    taps(px, W, x0, x1, fx);
-    taps(py, H, y0, y1, fy);
-    const uint32_t r0 = mul24(y0, W), r1 = mul24(y1, W);
-    const Rgb a = texel<IMG>(img, r0 + x0), b = texel<IMG>(img, r0 + x1);
-    const Rgb c = texel<IMG>(img, r1 + x0), d = texel<IMG>(img, r1 + x1);
+    taps_next(px, W, limx, x0, fx);
+    taps_next(py, H, limy, y0, fy);
+    const uint32_t r0 = mul24(y0, W) + x0, r1 = r0 + W;
+    const Rgb a = texel<IMG>(img, r0), b = texel<IMG>(img, r0 + 1);
+    const Rgb c = texel<IMG>(img, r1), d = texel<IMG>(img, r1 + 1);
     // the four tap weights; FP16 taps then feed mixed-precision FMAs directly
     const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
     return {fmaf(w11, d.r, fmaf(w01, c.r, fmaf(w10, b.r, fmaf(w00, a.r, 0.0f)))),

@@ -45,6 +45,7 @@ def _desc(**kw):
 @pytest.mark.parametrize("field,value,msg", [
     ("n_views", 0, "n_views"),
     ("img_w", 0, "image size"),
+    ("img_w", 1, "image size"),
     ("img_w", 5, "square"),
     ("mesh_m", 1, "mesh_m"),
     ("src_fov_deg", 180.0, "src_fov"),
