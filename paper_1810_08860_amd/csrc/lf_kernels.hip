@@ -377,25 +377,19 @@ __global__ __launch_bounds__(256) void k_prep(const EyeChunk ch, const double *_
 // ---------------------------------------------------------------------------------------------
 // culling
 
-// Does any ray of the tile's pixel rectangle [X0,X1] x [Y1,Y0] cross the disk
-// of view v (inside the circle of radius R = v.rk)? Conservative: the tile's rays hit the disk plane
+// Does any ray of the tile's pixel rectangle [X0,X1] x [Y1,Y0] (corner rays C)
+// cross the disk of view v (inside the circle of radius R = v.rk)? Conservative: the tile's rays hit the disk plane
 // inside the convex quad spanned by the four corner rays (a central
 // projection of a rectangle), so the test is circle-vs-convex-quad; a tile
 // that straddles the plane's horizon is kept.
-__device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, float X0, float X1, float Y0, float Y1) {
+__device__ __forceinline__ bool tile_overlaps_disk(const EyeView &v, const TileCorners &C, float X0, float X1,
+                                                   float Y0, float Y1) {
     const float R = v.rk;
     if (!(R > 0.0f)) return false;  // a disabled view
     const float cx[4] = {X0, X1, X1, X0}, cy[4] = {Y0, Y0, Y1, Y1};
-    float dx[4], dy[4];
-    int npos = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float ez = fmaf(v.m[6], cx[q], fmaf(v.m[7], cy[q], v.m[8]));
-        npos += ez > 0.0f;
-        const float iz = 1.0f / ez;
-        dx[q] = fmaf(-v.o[2], fmaf(v.m[0], cx[q], fmaf(v.m[1], cy[q], v.m[2])) * iz, v.o[0]);
-        dy[q] = fmaf(-v.o[2], fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5])) * iz, v.o[1]);
-    }
+    const float(&dx)[4] = C.dx;
+    const float(&dy)[4] = C.dy;
+    const int npos = C.npos;
     if (npos == 0) return false;
     if (npos < 4) {
         // the tile straddles the disk plane's horizon: test the disk's bounding
@@ -552,7 +546,7 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
         for (int base = 0; base < ne; base += 256) {
             const int q = base + (int)threadIdx.x;
             const int v = q < ne ? (int)elist[q] : 0;
-            const bool keep = any && q < ne && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
+            const bool keep = any && q < ne && tile_overlaps_disk(eve[v], tile_corners(eve[v], X0, X1, Y0, Y1), X0, X1, Y0, Y1);
             const uint64_t mask = __ballot(keep);
             if (lane == 0) sm.wcnt[wave] = __popcll(mask);
             __syncthreads();
@@ -587,13 +581,15 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
             for (int b = 0; any && b < ns; b += 64) {
                 const int s = b + lane;
                 const int v = s < ns ? (int)(sover ? elist[s] : sm.slist[s]) : -1;
-                const bool keep = v >= 0 && tile_overlaps_disk(eve[v], X0, X1, Y0, Y1);
+                const EyeView &vr = eve[v >= 0 ? v : 0];
+                const TileCorners C = tile_corners(vr, X0, X1, Y0, Y1);
+                const bool keep = v >= 0 && tile_overlaps_disk(vr, C, X0, X1, Y0, Y1);
                 const uint64_t mask = __ballot(keep);
                 if (keep) {
                     const int slot = count + __popcll(mask & below);
                     if (slot < kListCap) {
                         int4 bx = make_int4(-1, -1, -1, -1);
-                        if (!tile_cell_box(eve[v], X0, X1, Y0, Y1, g.M, g.sM, g.cM, bx.x, bx.y, bx.z, bx.w))
+                        if (!tile_cell_box(vr, C, g.M, g.sM, g.cM, bx.x, bx.y, bx.z, bx.w))
                             bx.x = -1;
                         sm.tlst[wave][slot] = (uint32_t)v;
                         sm.tbox[wave][slot] = bx;

@@ -234,41 +234,58 @@ LF_HD float half_bits_to_float(uint32_t b) {
     return __half2float(h);
 }
 
-// Mesh cells of view v that a ray through the image-plane rectangle
-// [X0, X1] x [Y1, Y0] can reach over w in [v.wmin, v.wmax]: the box
-// [j0, j1] x [k0, k1] (clamped to the grid). For a fixed w the points
-// V + w D of the rectangle's rays form the central projection of the
-// rectangle followed by an affine map, a convex quad spanned by its corner
-// rays, and each ray's points are affine in w, so every reachable point lies
-// in the convex hull of the corner rays' points at the two ends of the range.
-// The box is widened by a quarter cell against FP32 rounding. False (no box)
-// when a corner ray does not cross the disk plane from behind (the
-// projection is unbounded); true with an empty box (j0 > j1) when the hull
-// misses the mesh domain.
-LF_HD bool tile_cell_box(const EyeView &v, float X0, float X1, float Y0, float Y1, int M, float sM, float cM,
-                         int &j0, int &j1, int &k0, int &k1) {
+// The four corner rays of the image-plane rectangle [X0, X1] x [Y1, Y0] in
+// view v's frame (corners (X0, Y0), (X1, Y0), (X1, Y1), (X0, Y1)): for each,
+// the vanishing point V and the disk-plane coordinates D, and npos = how many
+// of them cross the disk plane from behind (e'z > 0). Shared by the culling's
+// disk test and the cell box of a tile.
+struct TileCorners {
+    float vx[4], vy[4], dx[4], dy[4];
+    int npos;
+};
+LF_HD TileCorners tile_corners(const EyeView &v, float X0, float X1, float Y0, float Y1) {
     const float cx[4] = {X0, X1, X1, X0}, cy[4] = {Y0, Y0, Y1, Y1};
-    float gx0 = INFINITY, gx1 = -INFINITY, gy0 = INFINITY, gy1 = -INFINITY;
-    bool ok = true;
+    TileCorners C;
+    C.npos = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float ez = fmaf(v.m[6], cx[q], fmaf(v.m[7], cy[q], v.m[8]));
-        ok = ok && ez > 0.0f;
+        C.npos += ez > 0.0f;
         const float iz = fast_rcp(ez);
-        const float Vx = fmaf(v.m[0], cx[q], fmaf(v.m[1], cy[q], v.m[2])) * iz;
-        const float Vy = fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5])) * iz;
-        const float Dx = fmaf(-v.o[2], Vx, v.o[0]), Dy = fmaf(-v.o[2], Vy, v.o[1]);
+        C.vx[q] = fmaf(v.m[0], cx[q], fmaf(v.m[1], cy[q], v.m[2])) * iz;
+        C.vy[q] = fmaf(v.m[3], cx[q], fmaf(v.m[4], cy[q], v.m[5])) * iz;
+        C.dx[q] = fmaf(-v.o[2], C.vx[q], v.o[0]);
+        C.dy[q] = fmaf(-v.o[2], C.vy[q], v.o[1]);
+    }
+    return C;
+}
+
+// Mesh cells of view v that a ray through the rectangle of corners C can
+// reach over w in [v.wmin, v.wmax]: the box [j0, j1] x [k0, k1] (clamped to
+// the grid). For a fixed w the points V + w D of the rectangle's rays form
+// the central projection of the rectangle followed by an affine map, a convex
+// quad spanned by its corner rays, and each ray's points are affine in w, so
+// every reachable point lies in the convex hull of the corner rays' points at
+// the two ends of the range. The box is widened by a quarter cell against
+// FP32 rounding. False (no box) when a corner ray does not cross the disk
+// plane from behind (the projection is unbounded); true with an empty box
+// (j0 > j1) when the hull misses the mesh domain.
+LF_HD bool tile_cell_box(const EyeView &v, const TileCorners &C, int M, float sM, float cM, int &j0, int &j1,
+                         int &k0, int &k1) {
+    float gx0 = INFINITY, gx1 = -INFINITY, gy0 = INFINITY, gy1 = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const float w = e ? v.wmax : v.wmin;
-            const float gx = fmaf(fmaf(w, Dx, Vx), sM, cM), gy = fmaf(-fmaf(w, Dy, Vy), sM, cM);
+            const float gx = fmaf(fmaf(w, C.dx[q], C.vx[q]), sM, cM), gy = fmaf(-fmaf(w, C.dy[q], C.vy[q]), sM, cM);
             gx0 = fminf(gx0, gx);
             gx1 = fmaxf(gx1, gx);
             gy0 = fminf(gy0, gy);
             gy1 = fmaxf(gy1, gy);
         }
     }
-    if (!ok || !(gx0 <= gx1 && gy0 <= gy1)) return false;  // NaN included
+    if (C.npos < 4 || !(gx0 <= gx1 && gy0 <= gy1)) return false;  // NaN included
     gx0 -= 0.25f;
     gx1 += 0.25f;
     gy0 -= 0.25f;
@@ -286,6 +303,10 @@ LF_HD bool tile_cell_box(const EyeView &v, float X0, float X1, float Y0, float Y
     k0 = (int)floorf(fminf(fmaxf(gy0, 0.0f), top));
     k1 = (int)floorf(fminf(fmaxf(gy1, 0.0f), top));
     return true;
+}
+LF_HD bool tile_cell_box(const EyeView &v, float X0, float X1, float Y0, float Y1, int M, float sM, float cM,
+                         int &j0, int &j1, int &k0, int &k1) {
+    return tile_cell_box(v, tile_corners(v, X0, X1, Y0, Y1), M, sM, cM, j0, j1, k0, k1);
 }
 
 // Windows of the per-cell window table (the bound over kWin x kWin cells
