@@ -514,9 +514,19 @@ __device__ __forceinline__ void list_bounds(const CullGeo &g, uint32_t *lst, con
             const int4 b = box[q];
             const uint16_t *cw = g.win + (int64_t)v * g.win_per_view;
             int nx, ny;
-            if (box_windows(b, nx, ny, mx))
-                for (int ty = sub >> 2; ty < ny; ty += 2)
-                    for (int tx = sub & 3; tx < nx; tx += 4) mx = max(mx, (uint32_t)cw[box_window_index(b, tx, ty, Mc)]);
+            if (box_windows(b, nx, ny, mx)) {
+                // up to 4 x 4 windows: this lane's (at most two) loads issued together
+                const int tx = sub & 3, ty = sub >> 2;
+                const bool l0 = tx < nx && ty < ny, l1 = tx < nx && ty + 2 < ny;
+                const uint32_t a0 = l0 ? cw[box_window_index(b, tx, ty, Mc)] : 0u;
+                const uint32_t a1 = l1 ? cw[box_window_index(b, tx, ty + 2, Mc)] : 0u;
+                mx = max(a0, a1);
+                // larger boxes: the remaining windows
+                if (nx > 4 || ny > 4)
+                    for (int yy = ty; yy < ny; yy += 2)
+                        for (int xx = tx; xx < nx; xx += 4)
+                            if (xx >= 4 || yy >= 4) mx = max(mx, (uint32_t)cw[box_window_index(b, xx, yy, Mc)]);
+            }
         }
 #pragma unroll
         for (int off = 4; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
