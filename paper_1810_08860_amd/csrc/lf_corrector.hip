@@ -368,7 +368,8 @@ __global__ void k_corr_pack(const float *__restrict__ prm, CorrLayout L, uint16_
 // same order as the layer-by-layer path. The tile's own FP32 render values
 // stay in LDS (in the layer-1 input's space once layer 1 has read it) for the
 // final blend, so the next tile's inputs can be fetched into registers during
-// layers 2-4.
+// layers 2-4. Each XCD takes a contiguous range of tiles (shared halos stay in
+// its L2).
 constexpr int FT = 16;                                   // output tile side
 constexpr int FR0 = FT + 8, FR1 = FT + 6, FR2 = FT + 4, FR3 = FT + 2;
 constexpr int FPS = 40;                                  // hidden pixel stride: 32 channels + 8 pad
@@ -384,6 +385,15 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, b16x2));
 }
 
+// ReLU of two packed BF16 values: a BF16 value is negative exactly when its
+// bits read as a negative 16-bit integer, so one packed integer maximum with
+// zero does it (and rounding to BF16 keeps the sign, so this equals rounding
+// the ReLU of the FP32 values).
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2){0, 0}));
+}
+
 // One hidden layer (or the last): output region side SOUT from the input
 // region side SOUT + 2; IN8: 8-channel layer-1 input; NBO blocks of 16 output
 // channels. The weights are the MFMA's A operand and the activations its B
@@ -394,15 +404,40 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
 // LDS one step ahead of the MFMAs that use them, and scheduling barriers keep
 // the compiler from hoisting further reads (registers: the weights of three
 // layers live in them for the whole kernel).
+// Activation tiles are addressed through LDS (address space 3) pointers, so
+// index arithmetic stays 32-bit.
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
+
+// a * b for a, b below 2^24 as one 24-bit multiply. Written out because the
+// compiler otherwise folds a 32-bit multiply and the following add into a
+// 64-bit multiply-add whose unused high addend register can alias the
+// destination of an outstanding global load, which makes the wave wait for
+// every load in flight (the next tile's prefetch).
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(b), "v"(a));
+    return r;
+}
+
 template <int SOUT, bool IN8>
-__device__ __forceinline__ bf16x8 fused_a(const uint16_t *__restrict__ src, int x, int y, int s, int g) {
+__device__ __forceinline__ uint32_t fused_base(int x, int y, int g) {
+    constexpr int SIN = SOUT + 2;
+    // element index of this lane's first K-step operand; 24-bit products
+    return IN8 ? mul24((uint32_t)(y * SIN + x), 8u) : mul24((uint32_t)(y * SIN + x), (uint32_t)FPS) + 8u * g;
+}
+
+template <int SOUT, bool IN8>
+__device__ __forceinline__ bf16x8 fused_a(const lds_u16 *__restrict__ src, uint32_t base, int s, int g) {
     constexpr int SIN = SOUT + 2;
     bf16x8 av = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
     if (IN8) {
-        const int t = 4 * s + g;  // four taps of 8 channels per K-step
-        if (t < 9) av = *reinterpret_cast<const bf16x8 *>(&src[((y + t / 3) * SIN + x + t % 3) * 8]);
+        // four taps of 8 channels per K-step; the padding taps 9-11 carry zero
+        // weights, so they read tap 8's (finite) activations instead of a branch
+        const int t = min(4 * s + g, 8);
+        av = *reinterpret_cast<const lds_bf16x8 *>(&src[base + ((t / 3) * SIN + t % 3) * 8]);
     } else {
-        av = *reinterpret_cast<const bf16x8 *>(&src[((y + s / 3) * SIN + x + s % 3) * FPS + 8 * g]);
+        av = *reinterpret_cast<const lds_bf16x8 *>(&src[base + ((s / 3) * SIN + s % 3) * FPS]);
     }
     return av;
 }
@@ -419,16 +454,22 @@ __device__ __forceinline__ void fused_store(const floatx4 (&acc)[NBO], int mm, u
     const int x = mm % SOUT, y = mm / SOUT;
     const int xx = ox0 + x, yy = oy0 + y;
     const bool in = interior || (xx >= 0 && xx < W && yy >= 0 && yy < H);
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+    typedef __attribute__((address_space(3))) u32x2 lds_u32x2;
+    const uint32_t o0 = mul24((uint32_t)mm, (uint32_t)FPS) + 4u * g;
 #pragma unroll
     for (int nb = 0; nb < NBO; ++nb) {
         const float v0 = acc[nb][0], v1 = acc[nb][1], v2 = acc[nb][2], v3 = acc[nb][3];
         if (LAST) {
-            if (g == 0) *reinterpret_cast<float4 *>(&res[mm * 4]) = make_float4(v0, v1, v2, v3);
+            if (g == 0)
+                *reinterpret_cast<lds_f32x4 *>(&((__attribute__((address_space(3))) float *)res)[4u * mm]) =
+                    f32x4{v0, v1, v2, v3};
         } else {
-            uint2 o = make_uint2(0u, 0u);
-            if (in)
-                o = make_uint2(pack_bf16x2(fmaxf(v0, 0.0f), fmaxf(v1, 0.0f)), pack_bf16x2(fmaxf(v2, 0.0f), fmaxf(v3, 0.0f)));
-            *reinterpret_cast<uint2 *>(&dst[mm * FPS + 16 * nb + 4 * g]) = o;
+            u32x2 o = u32x2{0u, 0u};
+            if (in) o = u32x2{relu_bf16x2(pack_bf16x2(v0, v1)), relu_bf16x2(pack_bf16x2(v2, v3))};
+            *reinterpret_cast<lds_u32x2 *>(&((lds_u16 *)dst)[o0 + 16 * nb]) = o;
         }
     }
 }
@@ -451,23 +492,24 @@ __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, ui
                                             int W) {
     constexpr int NOUT = SOUT * SOUT, NBLK = (NOUT + 15) / 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    const lds_u16 *s3 = (const lds_u16 *)src;
     for (int b = wave; b < NBLK; b += PAIR ? 8 : 4) {
         const int mm0 = 16 * b + i, mm1 = mm0 + 64;  // this lane's pixels (block b, block b + 4)
         const int m0 = min(mm0, NOUT - 1);
-        const int x0 = m0 % SOUT, y0 = m0 / SOUT;
+        const uint32_t q0 = fused_base<SOUT, IN8>(m0 % SOUT, m0 / SOUT, g);
         if (PAIR && b + 4 < NBLK) {
             const int m1 = min(mm1, NOUT - 1);
-            const int x1 = m1 % SOUT, y1 = m1 / SOUT;
+            const uint32_t q1 = fused_base<SOUT, IN8>(m1 % SOUT, m1 / SOUT, g);
             floatx4 acc0[NBO], acc1[NBO];
             fused_bias<NBO>(acc0, s_bias, g);
             fused_bias<NBO>(acc1, s_bias, g);
-            bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g), a1 = fused_a<SOUT, IN8>(src, x1, y1, 0, g);
+            bf16x8 a0 = fused_a<SOUT, IN8>(s3, q0, 0, g), a1 = fused_a<SOUT, IN8>(s3, q1, 0, g);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const bf16x8 c0 = a0, c1 = a1;
                 if (s + 1 < KS) {
-                    a0 = fused_a<SOUT, IN8>(src, x0, y0, s + 1, g);
-                    a1 = fused_a<SOUT, IN8>(src, x1, y1, s + 1, g);
+                    a0 = fused_a<SOUT, IN8>(s3, q0, s + 1, g);
+                    a1 = fused_a<SOUT, IN8>(s3, q1, s + 1, g);
                 }
 #pragma unroll
                 for (int nb = 0; nb < NBO; ++nb) {
@@ -481,11 +523,11 @@ __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, ui
         } else {
             floatx4 acc[NBO];
             fused_bias<NBO>(acc, s_bias, g);
-            bf16x8 a0 = fused_a<SOUT, IN8>(src, x0, y0, 0, g);
+            bf16x8 a0 = fused_a<SOUT, IN8>(s3, q0, 0, g);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const bf16x8 c0 = a0;
-                if (s + 1 < KS) a0 = fused_a<SOUT, IN8>(src, x0, y0, s + 1, g);
+                if (s + 1 < KS) a0 = fused_a<SOUT, IN8>(s3, q0, s + 1, g);
 #pragma unroll
                 for (int nb = 0; nb < NBO; ++nb)
                     acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[s][nb], c0, acc[nb], 0, 0, 0);
@@ -564,8 +606,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
         }
     };
-    if (blockIdx.x < total) fetch(blockIdx.x);
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    // Workgroup b runs on XCD b mod 8 (when the grid is a multiple of 8): each
+    // XCD takes one contiguous eighth of the tiles, so neighbouring tiles, whose
+    // inputs overlap by the 4-pixel halo, meet in the same L2.
+    const bool by_xcd = gridDim.x % 8 == 0;
+    const int stride = by_xcd ? gridDim.x / 8 : gridDim.x;
+    const int t_lo = by_xcd ? (int)((int64_t)total * (blockIdx.x % 8) / 8) : 0;
+    const int t_hi = by_xcd ? (int)((int64_t)total * (blockIdx.x % 8 + 1) / 8) : total;
+    const int t_first = t_lo + (by_xcd ? blockIdx.x / 8 : blockIdx.x);
+    if (t_first < t_hi) fetch(t_first);
+    for (int tile = t_first; tile < t_hi; tile += stride) {
         const int n = tile / (tx * ty), r = tile % (tx * ty);
         const int x0 = (r % tx) * FT, y0 = (r / tx) * FT;
         const int64_t img = (int64_t)n * H * W;
@@ -575,9 +625,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const int q = tid + 256 * k;
             if (q < FR0 * FR0) {
                 uint4 o;
-                o.x = f2bf(pr[k]) | ((uint32_t)f2bf(pg[k]) << 16);
-                o.y = f2bf(pb[k]) | ((uint32_t)f2bf(pw[k] * (1.0f / kCorrWScale)) << 16);
-                o.z = f2bf((float)pn[k] * (1.0f / kCorrNScale));
+                o.x = pack_bf16x2(pr[k], pg[k]);
+                o.y = pack_bf16x2(pb[k], pw[k] * (1.0f / kCorrWScale));
+                o.z = pack_bf16x2((float)pn[k] * (1.0f / kCorrNScale), 0.0f);
                 o.w = 0u;
                 *reinterpret_cast<uint4 *>(&s_in[q * 8]) = o;
             }
@@ -596,7 +646,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         __syncthreads();
         // the layer-1 input region (4 pixels of margin) inside the image: no padding zeros anywhere
         const bool interior = x0 >= 4 && y0 >= 4 && x0 + FT + 4 <= W && y0 + FT + 4 <= H;
-        fused_layer<FR1, true, 3, 2, false, false>(s_in, s_a, nullptr, w1, s_bias[0], interior, x0 - 3, y0 - 3, H, W);
+        fused_layer<FR1, true, 3, 2, false, true>(s_in, s_a, nullptr, w1, s_bias[0], interior, x0 - 3, y0 - 3, H, W);
         __syncthreads();
         // s_in is free: keep this tile's render values for the blend, then
         // fetch the next tile's inputs into the registers that held them
@@ -611,7 +661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 d[2] = pb[k];
             }
         }
-        if (tile + (int)gridDim.x < total) fetch(tile + gridDim.x);
+        if (tile + stride < t_hi) fetch(tile + stride);
         fused_layer<FR2, false, 9, 2, false, true>(s_a, s_b, nullptr, w2, s_bias[1], interior, x0 - 2, y0 - 2, H, W);
         __syncthreads();
         fused_layer<FR3, false, 9, 2, false, true>(s_b, s_a, nullptr, w3, s_bias[2], interior, x0 - 1, y0 - 1, H, W);
