@@ -24,12 +24,14 @@ namespace lf {
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// Two FP32 values as packed BF16, a in the low half (hardware conversion,
+// round to nearest even).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, b16x2));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)pack_bf16x2(f, 0.0f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 constexpr int TW = kCorrTileW, TH = kCorrTileH;  // output tile: 16 x 8 pixels
@@ -143,51 +145,75 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, i
 // GEMM with rows (t, ci), columns co and the reduction over pixels. A
 // workgroup strides over 16 x 8 tiles, staging x (with halo, one copy per
 // horizontal tap offset so that 8 consecutive pixels are one aligned 16-byte
-// LDS read) and dz channel-major, and keeps its partial sums in registers;
-// at the end it writes its partial dW / db to its own slot (reduced in a
-// fixed order by k_reduce_partials: deterministic).
+// LDS read) and dz channel-major from 16-byte loads of 8 channels, and keeps
+// its partial sums in registers; db is summed by all threads (channel t mod
+// 32, every 8th pixel). At the end it writes its partial dW / db to its own
+// slot (reduced in a fixed order by k_reduce_partials: deterministic).
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
                                                  int32_t N, int32_t H, int32_t W, int32_t cin_real,
                                                  int32_t cout_real, float *__restrict__ partial) {
+    static_assert(CIN % 8 == 0 && COUT % 8 == 0 && COUT <= 32, "channels come in 16-byte chunks");
     constexpr int MB = (9 * CIN + 15) / 16;  // row blocks of 16 (t, ci) pairs
     constexpr int NBK = (COUT + 15) / 16;
     constexpr int NBLK = MB * NBK;
     constexpr int PER = (NBLK + 3) / 4;      // output blocks per wave
-    constexpr int HY = TH + 2;
+    constexpr int HY = TH + 2, HX = TW + 2;  // x tile with its halo
+    constexpr int CX = CIN / 8, CZ = COUT / 8;
     __shared__ __attribute__((aligned(16))) uint16_t xs[3][CIN][HY][TW];
     __shared__ __attribute__((aligned(16))) uint16_t dzs[16 * NBK][TH][TW];
+    __shared__ float s_db[8][32];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
     const int total = N * tiles_x * tiles_y;
     floatx4 acc[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float db_acc = 0.0f;  // thread tid < COUT: its channel's sum
+    float db_acc = 0.0f;  // channel tid % 32, pixels tid / 32 + 8 k of each tile
+    // padding channels of dz (16 NBK > COUT) stay zero
+    for (int q = tid; q < (16 * NBK - COUT) * TH * TW; q += 256) (&dzs[COUT][0][0])[q] = 0;
 
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int n = tile / (tiles_x * tiles_y), r = tile % (tiles_x * tiles_y);
         const int x0 = (r % tiles_x) * TW, y0 = (r / tiles_x) * TH;
         __syncthreads();
-        // x tile: xs[kx][c][row][col] = x[y0 - 1 + row][x0 + col + kx - 1][c]
-        for (int q = tid; q < 3 * CIN * HY * TW; q += 256) {
-            const int col = q % TW, row = (q / TW) % HY, c = (q / (TW * HY)) % CIN, kx = q / (TW * HY * CIN);
-            const int yy = y0 - 1 + row, xx = x0 + col + kx - 1;
-            uint16_t v = 0;
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[(((int64_t)n * H + yy) * W + xx) * CIN + c];
-            xs[kx][c][row][col] = v;
+        // x tile: xs[kx][c][row][col] = x[y0 - 1 + row][x0 + col + kx - 1][c]; a loaded
+        // pixel at halo column hc lands in column hc - kx of copy kx
+        for (int q = tid; q < HY * CX * HX; q += 256) {
+            const int hc = q % HX, h = (q / HX) % CX, row = q / (HX * CX);
+            const int yy = y0 - 1 + row, xx = x0 - 1 + hc;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = *reinterpret_cast<const uint4 *>(&x[(((int64_t)n * H + yy) * W + xx) * CIN + 8 * h]);
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int col = hc - kx;
+                if (col >= 0 && col < TW) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        xs[kx][8 * h + e][row][col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
+                }
+            }
         }
-        for (int q = tid; q < 16 * NBK * TH * TW; q += 256) {
-            const int col = q % TW, row = (q / TW) % TH, c = q / (TW * TH);
+        for (int q = tid; q < TH * CZ * TW; q += 256) {
+            const int col = q % TW, h = (q / TW) % CZ, row = q / (TW * CZ);
             const int yy = y0 + row, xx = x0 + col;
-            uint16_t v = 0;
-            if (c < COUT && yy < H && xx < W) v = dz[(((int64_t)n * H + yy) * W + xx) * COUT + c];
-            dzs[c][row][col] = v;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy < H && xx < W) v = *reinterpret_cast<const uint4 *>(&dz[(((int64_t)n * H + yy) * W + xx) * COUT + 8 * h]);
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dzs[8 * h + e][row][col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
-        if (tid < COUT) {
+        if ((tid & 31) < COUT) {
+            const int c = tid & 31;
             float sacc = 0.0f;
-            for (int p = 0; p < TH * TW; ++p) sacc += bf2f(dzs[tid][p / TW][p % TW]);
+#pragma unroll
+            for (int k = 0; k < TH * TW / 8; ++k) {
+                const int p = (tid >> 5) + 8 * k;
+                sacc += bf2f(dzs[c][p / TW][p % TW]);
+            }
             db_acc += sacc;
         }
         // reduction over the tile's 128 pixels in 4 steps of 32 (two rows of 16)
@@ -228,7 +254,14 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
             if (ci < cin_real && co < cout_real) pw[(t * cin_real + ci) * cout_real + co] = acc[q][v];
         }
     }
-    if (tid < cout_real) pw[nw + tid] = db_acc;
+    s_db[tid >> 5][tid & 31] = db_acc;
+    __syncthreads();
+    if (tid < cout_real) {
+        float d = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d += s_db[k][tid];
+        pw[nw + tid] = d;
+    }
 }
 
 // out[j] = sum over slots of partial[slot][j], in a fixed order: a workgroup
@@ -378,12 +411,6 @@ struct FusedTile {
     int n, x0, y0;  // image and top-left output pixel of the tile
 };
 
-// Two FP32 values as packed BF16 (hardware round to nearest even).
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, b16x2));
-}
 
 // ReLU of two packed BF16 values: a BF16 value is negative exactly when its
 // bits read as a negative 16-bit integer, so one packed integer maximum with
