@@ -160,8 +160,11 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
     constexpr int PER = (NBLK + 3) / 4;      // output blocks per wave
     constexpr int HY = TH + 2, HX = TW + 2;  // x tile with its halo
     constexpr int CX = CIN / 8, CZ = COUT / 8;
-    __shared__ __attribute__((aligned(16))) uint16_t xs[3][CIN][HY][TW];
-    __shared__ __attribute__((aligned(16))) uint16_t dzs[16 * NBK][TH][TW];
+    // channel planes padded by 16 bytes: the 16 lanes of an MFMA operand read
+    // (consecutive channels) then start on different LDS banks
+    constexpr int PX = HY * TW + 8, PZ = TH * TW + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3][CIN][PX];
+    __shared__ __attribute__((aligned(16))) uint16_t dzs[16 * NBK][PZ];
     __shared__ float s_db[8][32];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
     for (int q = 0; q < PER; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
     float db_acc = 0.0f;  // channel tid % 32, pixels tid / 32 + 8 k of each tile
     // padding channels of dz (16 NBK > COUT) stay zero
-    for (int q = tid; q < (16 * NBK - COUT) * TH * TW; q += 256) (&dzs[COUT][0][0])[q] = 0;
+    for (int q = tid; q < (16 * NBK - COUT) * PZ; q += 256) (&dzs[COUT][0])[q] = 0;
 
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int n = tile / (tiles_x * tiles_y), r = tile % (tiles_x * tiles_y);
@@ -180,7 +183,8 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
         // x tile: xs[kx][c][row][col] = x[y0 - 1 + row][x0 + col + kx - 1][c]; a loaded
         // pixel at halo column hc lands in column hc - kx of copy kx
         for (int q = tid; q < HY * CX * HX; q += 256) {
-            const int hc = q % HX, h = (q / HX) % CX, row = q / (HX * CX);
+            // a wave's lanes cover consecutive columns and rows of one chunk h
+            const int hc = q % HX, row = (q / HX) % HY, h = q / (HX * HY);
             const int yy = y0 - 1 + row, xx = x0 - 1 + hc;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (yy >= 0 && yy < H && xx >= 0 && xx < W)
@@ -192,18 +196,18 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
                 if (col >= 0 && col < TW) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
-                        xs[kx][8 * h + e][row][col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
+                        xs[kx][8 * h + e][row * TW + col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
                 }
             }
         }
         for (int q = tid; q < TH * CZ * TW; q += 256) {
-            const int col = q % TW, h = (q / TW) % CZ, row = q / (TW * CZ);
+            const int col = q % TW, row = (q / TW) % TH, h = q / (TW * TH);
             const int yy = y0 + row, xx = x0 + col;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (yy < H && xx < W) v = *reinterpret_cast<const uint4 *>(&dz[(((int64_t)n * H + yy) * W + xx) * COUT + 8 * h]);
             const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dzs[8 * h + e][row][col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
+            for (int e = 0; e < 8; ++e) dzs[8 * h + e][row * TW + col] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
         if ((tid & 31) < COUT) {
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
 #pragma unroll
             for (int k = 0; k < TH * TW / 8; ++k) {
                 const int p = (tid >> 5) + 8 * k;
-                sacc += bf2f(dzs[c][p / TW][p % TW]);
+                sacc += bf2f(dzs[c][p]);
             }
             db_acc += sacc;
         }
@@ -230,9 +234,9 @@ __global__ __launch_bounds__(256) void k_conv_dw(const uint16_t *__restrict__ x,
                 if (m < 9 * CIN) {
                     const int t = m / CIN, ci = m % CIN;
                     const int ky = t / 3, kx = t % 3;
-                    av = *reinterpret_cast<const bf16x8 *>(&xs[kx][ci][row + ky][col]);
+                    av = *reinterpret_cast<const bf16x8 *>(&xs[kx][ci][(row + ky) * TW + col]);
                 }
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&dzs[16 * nb + i][row][col]);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&dzs[16 * nb + i][row * TW + col]);
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
             }
         }
