@@ -411,11 +411,6 @@ constexpr int FT = 16;                                   // output tile side
 constexpr int FR0 = FT + 8, FR1 = FT + 6, FR2 = FT + 4, FR3 = FT + 2;
 constexpr int FPS = 40;                                  // hidden pixel stride: 32 channels + 8 pad
 
-struct FusedTile {
-    int n, x0, y0;  // image and top-left output pixel of the tile
-};
-
-
 // ReLU of two packed BF16 values: a BF16 value is negative exactly when its
 // bits read as a negative 16-bit integer, so one packed integer maximum with
 // zero does it (and rounding to BF16 keeps the sign, so this equals rounding
@@ -425,16 +420,6 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2){0, 0}));
 }
 
-// One hidden layer (or the last): output region side SOUT from the input
-// region side SOUT + 2; IN8: 8-channel layer-1 input; NBO blocks of 16 output
-// channels. The weights are the MFMA's A operand and the activations its B
-// operand, so D[4 g + v][i] is channel 16 nb + 4 g + v of pixel 16 b + i:
-// each lane stores four consecutive channels of one pixel at once.
-// PAIR: a wave takes two 16-pixel blocks at a time (blocks b and b + 4), four
-// independent accumulation chains. Each K-step's activations are read from
-// LDS one step ahead of the MFMAs that use them, and scheduling barriers keep
-// the compiler from hoisting further reads (registers: the weights of three
-// layers live in them for the whole kernel).
 // Activation tiles are addressed through LDS (address space 3) pointers, so
 // index arithmetic stays 32-bit.
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
@@ -516,6 +501,16 @@ __device__ __forceinline__ void fused_bias(floatx4 (&acc)[NBO], const float *__r
     }
 }
 
+// One hidden layer (or the last): output region side SOUT from the input
+// region side SOUT + 2; IN8: 8-channel layer-1 input; NBO blocks of 16 output
+// channels. The weights are the MFMA's A operand and the activations its B
+// operand, so D[4 g + v][i] is channel 16 nb + 4 g + v of pixel 16 b + i:
+// each lane stores four consecutive channels of one pixel at once.
+// PAIR: a wave takes two 16-pixel blocks at a time (blocks b and b + 4), four
+// independent accumulation chains. Each K-step's activations are read from
+// LDS one step ahead of the MFMAs that use them, and scheduling barriers keep
+// the compiler from hoisting further reads (registers: two layers' weights
+// live in them for the whole kernel).
 template <int SOUT, bool IN8, int KS, int NBO, bool LAST, bool PAIR>
 __device__ __forceinline__ void fused_layer(const uint16_t *__restrict__ src, uint16_t *__restrict__ dst,
                                             float *__restrict__ res, const bf16x8 (&w)[KS][NBO],

@@ -71,12 +71,16 @@ def test_forward_matches_oracle():
     c.close()
 
 
-@pytest.mark.parametrize("shape", [(2, 28, 40), (1, 97, 161)])
+@pytest.mark.parametrize("shape", [(2, 28, 40), (1, 97, 161), (2, 392, 584)])
 def test_fused_inference_matches_training_forward(shape):
     """Inference runs all four layers in one fused kernel over 16 x 16 tiles
     with LDS halos; training runs them layer by layer. The training step's
     loss (from its own forward) must equal the MSE of the fused residual
-    against the same reference, up to the summation order of the loss."""
+    against the same reference, up to the summation order of the loss, so a
+    tile left out or computed twice shows. The last shape (1,850 ragged
+    tiles) has more tiles than resident workgroups, a grid that is a multiple
+    of 8, so each XCD takes its own range of tiles, and ranges of unequal
+    length."""
     import torch
     from paper_1810_08860_amd import lf
     n, h, w = shape
