@@ -662,7 +662,7 @@ def main():
     ap.add_argument("--no-streaming", action="store_true", help="skip the tile streaming leg")
     ap.add_argument("--corrector-steps", type=int, default=1250)
     ap.add_argument("--variants", default="plain,fp16,rgba8,yuv420,yuv420_rgtc,fp16_batched,fp16geo_batched,"
-                                           "rgba8_batched,fp16_batched_oval")
+                                           "u16geo_batched,rgba8_batched,fp16_batched_oval")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_render_traffic.json"))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES five times (HBM counter calibration)")
@@ -712,6 +712,7 @@ def main():
                "yuv420_rgtc": ("yuv420_rgtc", "f16", "circle"),
                "fp16_batched": ("rgba16f", "f32", "circle"),
                "fp16geo_batched": ("rgba16f", "f16", "circle"),
+               "u16geo_batched": ("rgba16f", "u16", "circle"),
                "rgba8_batched": ("rgba8", "f32", "circle"),
                "fp16_batched_oval": ("rgba16f", "f32", "oval")}
     chosen = [v for v in args.variants.split(",") if v]
@@ -818,6 +819,7 @@ def main():
         ov = oracle.OracleViews.from_views(V)
         for name, what in (("fp16_batched", "RGBA16F images, FP32 geometry"),
                            ("fp16geo_batched", "RGBA16F images, FP16 geometry"),
+                           ("u16geo_batched", "RGBA16F images, 16-bit inverse-depth codes"),
                            ("rgba8_batched", "RGBA8 images, FP32 geometry")):
             if name not in results:
                 continue

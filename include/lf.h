@@ -85,9 +85,13 @@ enum {
     LF_IMG_PAGED_RGBA8 = 5  /* RGBA8 tiles streamed into a device tile cache: see lf_cache_config */
 };
 
-/* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex, in
- * FP32 or FP16, packed per mesh cell. Intersection arithmetic is FP32. */
-enum { LF_GEO_F32 = 0, LF_GEO_F16 = 1 };
+/* Storage of the per-view geometry: inverse depth 1/z of each mesh vertex,
+ * packed per mesh cell (its four corners): FP32 (16 bytes a cell), FP16 (8
+ * bytes), or 16-bit codes spread linearly over the view's inverse-depth range
+ * (8 bytes; w = min + code * (max - min) / 65535, an error of at most half a
+ * step, 1/131070 of the range, where FP16 errs by up to 2^-11 of w).
+ * Intersection arithmetic is FP32. */
+enum { LF_GEO_F32 = 0, LF_GEO_F16 = 1, LF_GEO_U16 = 2 };
 
 /* lf_views_desc.flags: the rgba8 / zdepth pointers are device pointers. */
 enum { LF_SRC_DEVICE = 1 };

@@ -74,6 +74,8 @@ int64_t img2_view_bytes(int fmt, int64_t W, int64_t H) {
     return 0;
 }
 size_t geo_bytes_per_cell(int fmt) { return fmt == LF_GEO_F32 ? 16 : 8; }
+// bytes before each view's cells: the (base, scale) of its 16-bit codes
+size_t geo_head_bytes(int fmt) { return fmt == LF_GEO_U16 ? 8 : 0; }
 
 // Limits of the per-view addressing of the kernels (at<T>, mul24 in lf_ray.h).
 constexpr int64_t kMaxViewBytes = (int64_t)1 << 32;
@@ -287,7 +289,8 @@ ViewBases view_bases(const lf_ctx *c) {
     vb.img = static_cast<const char *>(c->img);
     vb.img2 = static_cast<const char *>(c->img2);
     vb.blk = c->blk;
-    vb.geo_bytes = (int64_t)(c->M - 1) * (c->M - 1) * (c->geo_fmt == LF_GEO_F32 ? 16 : 8);
+    vb.geo_head = (int64_t)geo_head_bytes(c->geo_fmt);
+    vb.geo_bytes = (int64_t)(c->M - 1) * (c->M - 1) * (int64_t)geo_bytes_per_cell(c->geo_fmt) + vb.geo_head;
     vb.img_bytes = img_view_bytes(c->img_fmt, c->img_w, c->img_h);
     vb.img2_bytes = img2_view_bytes(c->img_fmt, c->img_w, c->img_h);
     vb.blk_per_view = (int64_t)num_blocks(c->M) * num_blocks(c->M);
@@ -386,7 +389,7 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         return fail(LF_EINVAL, "YUV420 needs even image sizes (got %dx%d)", d->img_w, d->img_h);
     if (d->img_fmt == LF_IMG_YUV420_RGTC && (d->img_w % 8 || d->img_h % 8))
         return fail(LF_EINVAL, "RGTC needs image sizes that are multiples of 8 (got %dx%d)", d->img_w, d->img_h);
-    if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_F16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
+    if (d->geo_fmt < LF_GEO_F32 || d->geo_fmt > LF_GEO_U16) return fail(LF_EINVAL, "unknown geo_fmt %d", d->geo_fmt);
     if (d->flags & ~LF_SRC_DEVICE) return fail(LF_EINVAL, "unknown flags 0x%x", d->flags);
     {
         // the kernels address each view's share of an array with a 32-bit byte
@@ -396,7 +399,7 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
             return fail(LF_EINVAL, "image size %lldx%lld: each dimension must be below 2^24", (long long)W,
                         (long long)H);
         const int64_t per_view[4] = {img_view_bytes(d->img_fmt, W, H), img2_view_bytes(d->img_fmt, W, H), 4 * W * H,
-                                     Mc * Mc * (int64_t)geo_bytes_per_cell(d->geo_fmt)};
+                                     Mc * Mc * (int64_t)geo_bytes_per_cell(d->geo_fmt) + (int64_t)geo_head_bytes(d->geo_fmt)};
         static const char *what[4] = {"image", "second image plane", "RGBA8 source image", "mesh"};
         for (int k = 0; k < 4; ++k)
             if (per_view[k] >= kMaxViewBytes)
@@ -566,7 +569,8 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         }
     }
     const size_t n_cells = (size_t)n * (M - 1) * (M - 1);
-    if ((e = hipMalloc(&c->geo, n_cells * geo_bytes_per_cell(d->geo_fmt))) != hipSuccess) {
+    if ((e = hipMalloc(&c->geo, n_cells * geo_bytes_per_cell(d->geo_fmt) + (size_t)n * geo_head_bytes(d->geo_fmt))) !=
+        hipSuccess) {
         if (z_owned) (void)hipFree(z_dev);
         return bail(hip_fail(e, "hipMalloc(mesh cells)"));
     }
@@ -579,7 +583,8 @@ int lf_load_views(const lf_views_desc *d, lf_ctx **out) {
         if (z_owned) (void)hipFree(z_dev);
         return bail(hip_fail(e, "hipMalloc(cell bounds)"));
     }
-    e = launch_geo_cells(z_dev, c->geo, d->geo_fmt, n, M, 0);
+    // (c->wr first holds the FP32 inverse-depth range the 16-bit codes span)
+    e = launch_geo_cells(z_dev, c->geo, d->geo_fmt, n, M, c->wr, 0);
     if (e == hipSuccess) e = launch_geo_range(c->geo, d->geo_fmt, n, M, c->wr, 0);
     if (e == hipSuccess) e = launch_geo_blocks(c->geo, d->geo_fmt, n, M, c->blk, 0);
     if (e == hipSuccess) e = launch_geo_win(c->geo, d->geo_fmt, n, M, c->win, 0);

@@ -171,4 +171,15 @@ void lfh_half_up(int64_t n, const float *x, uint16_t *bits) {
     for (int64_t k = 0; k < n; ++k) bits[k] = half_up_bits(x[k]);
 }
 
+// Corner inverse depths of cell idx of the view whose cells start at `cells`
+// (for the 16-bit codes, 8 bytes after its (base, scale) header).
+void lfh_load_cell(int32_t geo_fmt, const void *cells, uint32_t idx, float *out4) {
+    const float4 q = geo_fmt == 0 ? load_cell<0>(cells, idx) : geo_fmt == 1 ? load_cell<1>(cells, idx)
+                                                                           : load_cell<2>(cells, idx);
+    out4[0] = q.x;
+    out4[1] = q.y;
+    out4[2] = q.z;
+    out4[3] = q.w;
+}
+
 }  // extern "C"

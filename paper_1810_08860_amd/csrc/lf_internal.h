@@ -78,6 +78,7 @@ struct ViewBases {
     const char *geo, *img, *img2;
     const float2 *blk;
     int64_t geo_bytes, img_bytes, img2_bytes, blk_per_view;
+    int64_t geo_head;  // bytes before each view's cells (its dequantisation constants)
 };
 
 // Mesh grid of the light field as the culling kernels need it: the grid
@@ -176,7 +177,8 @@ hipError_t launch_convert_yuv420(const uint8_t *src, uint8_t *y, uint8_t *uv, in
                                  hipStream_t s);
 hipError_t launch_convert_rgtc(const uint8_t *y, const uint8_t *uv, void *yb, void *uvb, int32_t n, int32_t W,
                                int32_t H, hipStream_t s);
-hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s);
+hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, float2 *qr,
+                            hipStream_t s);
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s);
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s);
 // per mesh cell: the largest corner inverse depth of the kWin x kWin cells from it, FP16 rounded up

@@ -146,9 +146,36 @@ __global__ void k_convert_rgtc(const uint8_t *__restrict__ y, const uint8_t *__r
     }
 }
 
-// Mesh cells of every view: corner inverse depths (w00, w10, w01, w11).
+// Inverse-depth range (1 / z) of each view's vertices in FP32, before any
+// packing: the range the 16-bit codes of LF_GEO_U16 span. One block per view.
+__global__ __launch_bounds__(256) void k_z_range(const float *__restrict__ z, int32_t M, float2 *__restrict__ qr) {
+    const float *zv = z + (int64_t)blockIdx.x * M * M;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int q = threadIdx.x; q < M * M; q += blockDim.x) {
+        const float w = 1.0f / zv[q];
+        lo = fminf(lo, w);
+        hi = fmaxf(hi, w);
+    }
+    __shared__ float slo[256], shi[256];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if ((int)threadIdx.x < t) {
+            slo[threadIdx.x] = fminf(slo[threadIdx.x], slo[threadIdx.x + t]);
+            shi[threadIdx.x] = fmaxf(shi[threadIdx.x], shi[threadIdx.x + t]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) qr[blockIdx.x] = make_float2(slo[0], shi[0]);
+}
+
+// Mesh cells of every view: corner inverse depths (w00, w10, w01, w11), in
+// FP32, FP16 or 16-bit codes over the view's range qr (then each view's
+// cells are preceded by its (base, scale)).
 template <int GEO>
-__global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cells, int32_t n, int32_t M) {
+__global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cells, int32_t n, int32_t M,
+                            const float2 *__restrict__ qr) {
     const int64_t per = (int64_t)(M - 1) * (M - 1);
     const int64_t total = per * n;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total;
@@ -158,14 +185,22 @@ __global__ void k_geo_cells(const float *__restrict__ z, void *__restrict__ cell
         const float *zv = z + v * (int64_t)M * M;
         const float w00 = 1.0f / zv[(int64_t)k * M + j], w10 = 1.0f / zv[(int64_t)k * M + j + 1];
         const float w01 = 1.0f / zv[(int64_t)(k + 1) * M + j], w11 = 1.0f / zv[(int64_t)(k + 1) * M + j + 1];
+        char *view = const_cast<char *>(static_cast<const char *>(geo_view<GEO>(cells, v, per)));
         if (GEO == 0) {
-            reinterpret_cast<float4 *>(cells)[c] = make_float4(w00, w10, w01, w11);
-        } else {
+            reinterpret_cast<float4 *>(view)[r] = make_float4(w00, w10, w01, w11);
+        } else if (GEO == 1) {
             __half2 a = __floats2half2_rn(w00, w10), b = __floats2half2_rn(w01, w11);
             uint2 o;
             o.x = *reinterpret_cast<uint32_t *>(&a);
             o.y = *reinterpret_cast<uint32_t *>(&b);
-            reinterpret_cast<uint2 *>(cells)[c] = o;
+            reinterpret_cast<uint2 *>(view)[r] = o;
+        } else {
+            // code = nearest of base + code * scale, scale = (max - min) / 65535
+            const float base = qr[v].x, scale = (qr[v].y - qr[v].x) * (1.0f / 65535.0f);
+            const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
+            auto code = [&](float w) { return (uint32_t)fminf(fmaxf(rintf((w - base) * inv), 0.0f), 65535.0f); };
+            reinterpret_cast<uint2 *>(view)[r] = make_uint2(code(w00) | (code(w10) << 16), code(w01) | (code(w11) << 16));
+            if (r == 0) reinterpret_cast<float2 *>(view)[-1] = make_float2(base, scale);
         }
     }
 }
@@ -176,7 +211,7 @@ template <int GEO>
 __global__ __launch_bounds__(256) void k_geo_range(const void *__restrict__ cells, int32_t M,
                                                    float2 *__restrict__ wr) {
     const int per = (M - 1) * (M - 1);
-    const void *view = static_cast<const char *>(cells) + (int64_t)blockIdx.x * per * (GEO == 0 ? 16 : 8);
+    const void *view = geo_view<GEO>(cells, blockIdx.x, per);
     float lo = INFINITY, hi = -INFINITY;
     for (int c = threadIdx.x; c < per; c += blockDim.x) {
         const float4 q = load_cell<GEO>(view, (uint32_t)c);
@@ -209,7 +244,7 @@ __global__ __launch_bounds__(256) void k_geo_blocks(const void *__restrict__ cel
         const int r = (int)(b % ((int64_t)NB * NB));
         const int bk = r / NB, bi = r % NB;
         const int j0 = bi * kBlk, j1 = min(j0 + kBlk, Mc), k0 = bk * kBlk, k1 = min(k0 + kBlk, Mc);
-        const void *view = static_cast<const char *>(cells) + v * Mc * Mc * (GEO == 0 ? 16 : 8);
+        const void *view = geo_view<GEO>(cells, v, (int64_t)Mc * Mc);
         float lo = INFINITY, hi = -INFINITY;
         for (int k = k0; k < k1; ++k)
             for (int j = j0; j < j1; ++j) {
@@ -232,7 +267,7 @@ __global__ __launch_bounds__(256) void k_geo_win(const void *__restrict__ cells,
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = c / per;
         const int r = (int)(c % per), k = r / Mc, j = r % Mc;
-        const void *view = static_cast<const char *>(cells) + v * per * (GEO == 0 ? 16 : 8);
+        const void *view = geo_view<GEO>(cells, v, per);
         float m = 0.0f;
         for (int kk = k; kk < min(k + kWin, Mc); ++kk)
             for (int jj = j; jj < min(j + kWin, Mc); ++jj) {
@@ -332,7 +367,7 @@ __device__ __forceinline__ EyeView eye_view(const EyeParam &E, const double *__r
     // a view whose disk no ray of a plain eye can cross is culled for that eye
     // (prefilter eyes send their rays off the pixel rectangle: kept)
     if (E.src_view < 0 && out.rk > 0.0f && !eye_sees_disk(md, od, (double)out.rk, E.tx, E.ty)) out.rk = -1.0f;
-    out.cells = vb.geo + v * vb.geo_bytes;
+    out.cells = vb.geo + v * vb.geo_bytes + vb.geo_head;
     out.img = vb.img + v * vb.img_bytes;
     out.blk = vb.blk + v * vb.blk_per_view;
     out.img2 = vb.img2 ? vb.img2 + v * vb.img2_bytes : nullptr;
@@ -1075,41 +1110,45 @@ hipError_t launch_cache_apply(int32_t *pt, const int2 *patch, int32_t n_patch, c
     return hipGetLastError();
 }
 
-hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, hipStream_t s) {
+hipError_t launch_geo_cells(const float *z, void *cells, int geo_fmt, int32_t n, int32_t M, float2 *qr,
+                            hipStream_t s) {
     const int g = grid_for((int64_t)(M - 1) * (M - 1) * n, 256);
-    if (geo_fmt == 0)
-        hipLaunchKernelGGL(k_geo_cells<0>, dim3(g), dim3(256), 0, s, z, cells, n, M);
-    else
-        hipLaunchKernelGGL(k_geo_cells<1>, dim3(g), dim3(256), 0, s, z, cells, n, M);
+    if (geo_fmt == 0) {
+        hipLaunchKernelGGL(k_geo_cells<0>, dim3(g), dim3(256), 0, s, z, cells, n, M, qr);
+    } else if (geo_fmt == 1) {
+        hipLaunchKernelGGL(k_geo_cells<1>, dim3(g), dim3(256), 0, s, z, cells, n, M, qr);
+    } else {
+        hipLaunchKernelGGL(k_z_range, dim3(n), dim3(256), 0, s, z, M, qr);
+        hipLaunchKernelGGL(k_geo_cells<2>, dim3(g), dim3(256), 0, s, z, cells, n, M, qr);
+    }
     return hipGetLastError();
 }
 
+#define LF_GEO3(K, ...)                                                 \
+    do {                                                                \
+        if (geo_fmt == 0) hipLaunchKernelGGL(K<0>, __VA_ARGS__);        \
+        else if (geo_fmt == 1) hipLaunchKernelGGL(K<1>, __VA_ARGS__);   \
+        else hipLaunchKernelGGL(K<2>, __VA_ARGS__);                     \
+    } while (0)
+
 hipError_t launch_geo_range(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *wr, hipStream_t s) {
-    if (geo_fmt == 0)
-        hipLaunchKernelGGL(k_geo_range<0>, dim3(n), dim3(256), 0, s, cells, M, wr);
-    else
-        hipLaunchKernelGGL(k_geo_range<1>, dim3(n), dim3(256), 0, s, cells, M, wr);
+    LF_GEO3(k_geo_range, dim3(n), dim3(256), 0, s, cells, M, wr);
     return hipGetLastError();
 }
 
 hipError_t launch_geo_blocks(const void *cells, int geo_fmt, int32_t n, int32_t M, float2 *blk, hipStream_t s) {
     const int NB = num_blocks(M);
     const int g = grid_for((int64_t)n * NB * NB, 256);
-    if (geo_fmt == 0)
-        hipLaunchKernelGGL(k_geo_blocks<0>, dim3(g), dim3(256), 0, s, cells, n, M, NB, blk);
-    else
-        hipLaunchKernelGGL(k_geo_blocks<1>, dim3(g), dim3(256), 0, s, cells, n, M, NB, blk);
+    LF_GEO3(k_geo_blocks, dim3(g), dim3(256), 0, s, cells, n, M, NB, blk);
     return hipGetLastError();
 }
 
 hipError_t launch_geo_win(const void *cells, int geo_fmt, int32_t n, int32_t M, uint16_t *win, hipStream_t s) {
     const int g = grid_for((int64_t)n * (M - 1) * (M - 1), 256);
-    if (geo_fmt == 0)
-        hipLaunchKernelGGL(k_geo_win<0>, dim3(g), dim3(256), 0, s, cells, n, M, win);
-    else
-        hipLaunchKernelGGL(k_geo_win<1>, dim3(g), dim3(256), 0, s, cells, n, M, win);
+    LF_GEO3(k_geo_win, dim3(g), dim3(256), 0, s, cells, n, M, win);
     return hipGetLastError();
 }
+#undef LF_GEO3
 
 hipError_t launch_prep(const EyeChunk &ch, const double *vt, const float2 *wr, int32_t n, const DiskBound &db,
                        const ViewBases &vb, EyeView *ev, hipStream_t s) {
@@ -1129,21 +1168,19 @@ template <int MODE, int DISK>
 static void launch_render_mode(const EyeChunk &ch, const RenderArgs &a, int img_fmt, int geo_fmt, hipStream_t s) {
     const dim3 grid(ch.total_tiles), block(ch.tile_w * ch.tile_h);
 #define LF_R(I, G) hipLaunchKernelGGL((k_render<I, G, MODE, DISK>), grid, block, 0, s, ch, a)
-    if (geo_fmt == 0) {
-        if (img_fmt == 0) LF_R(0, 0);
-        else if (img_fmt == 1) LF_R(1, 0);
-        else if (img_fmt == 2) LF_R(2, 0);
-        else if (img_fmt == 3) LF_R(3, 0);
-        else if (img_fmt == 4) LF_R(4, 0);
-        else LF_R(5, 0);
-    } else {
-        if (img_fmt == 0) LF_R(0, 1);
-        else if (img_fmt == 1) LF_R(1, 1);
-        else if (img_fmt == 2) LF_R(2, 1);
-        else if (img_fmt == 3) LF_R(3, 1);
-        else if (img_fmt == 4) LF_R(4, 1);
-        else LF_R(5, 1);
-    }
+#define LF_RG(G)                          \
+    do {                                  \
+        if (img_fmt == 0) LF_R(0, G);     \
+        else if (img_fmt == 1) LF_R(1, G); \
+        else if (img_fmt == 2) LF_R(2, G); \
+        else if (img_fmt == 3) LF_R(3, G); \
+        else if (img_fmt == 4) LF_R(4, G); \
+        else LF_R(5, G);                  \
+    } while (0)
+    if (geo_fmt == 0) LF_RG(0);
+    else if (geo_fmt == 1) LF_RG(1);
+    else LF_RG(2);
+#undef LF_RG
 #undef LF_R
 }
 
@@ -1153,10 +1190,12 @@ static void launch_visibility(const EyeChunk &ch, const RenderArgs &a, int geo_f
 #define LF_V(G, D) hipLaunchKernelGGL((k_render<5, G, MODE_VISIBILITY, D>), grid, block, 0, s, ch, a)
     if (a.ext_inv) {
         if (geo_fmt == 0) LF_V(0, DISK_OVAL);
-        else LF_V(1, DISK_OVAL);
+        else if (geo_fmt == 1) LF_V(1, DISK_OVAL);
+        else LF_V(2, DISK_OVAL);
     } else {
         if (geo_fmt == 0) LF_V(0, DISK_CIRCLE);
-        else LF_V(1, DISK_CIRCLE);
+        else if (geo_fmt == 1) LF_V(1, DISK_CIRCLE);
+        else LF_V(2, DISK_CIRCLE);
     }
 #undef LF_V
 }
@@ -1172,21 +1211,19 @@ static void launch_persistent(const BatchArgs &b, const RenderArgs &a, int img_f
                               hipStream_t s) {
     const dim3 block(b.tile_w * b.tile_h);
 #define LF_P(I, G) hipLaunchKernelGGL((k_render_persistent<I, G, DISK>), dim3(grid), block, 0, s, b, a)
-    if (geo_fmt == 0) {
-        if (img_fmt == 0) LF_P(0, 0);
-        else if (img_fmt == 1) LF_P(1, 0);
-        else if (img_fmt == 2) LF_P(2, 0);
-        else if (img_fmt == 3) LF_P(3, 0);
-        else if (img_fmt == 4) LF_P(4, 0);
-        else LF_P(5, 0);
-    } else {
-        if (img_fmt == 0) LF_P(0, 1);
-        else if (img_fmt == 1) LF_P(1, 1);
-        else if (img_fmt == 2) LF_P(2, 1);
-        else if (img_fmt == 3) LF_P(3, 1);
-        else if (img_fmt == 4) LF_P(4, 1);
-        else LF_P(5, 1);
-    }
+#define LF_PG(G)                          \
+    do {                                  \
+        if (img_fmt == 0) LF_P(0, G);     \
+        else if (img_fmt == 1) LF_P(1, G); \
+        else if (img_fmt == 2) LF_P(2, G); \
+        else if (img_fmt == 3) LF_P(3, G); \
+        else if (img_fmt == 4) LF_P(4, G); \
+        else LF_P(5, G);                  \
+    } while (0)
+    if (geo_fmt == 0) LF_PG(0);
+    else if (geo_fmt == 1) LF_PG(1);
+    else LF_PG(2);
+#undef LF_PG
 #undef LF_P
 }
 
@@ -1218,7 +1255,10 @@ static const void *persistent_fn(int img_fmt, int geo_fmt) {
     const void *f1[6] = {(const void *)k_render_persistent<0, 1, DISK>, (const void *)k_render_persistent<1, 1, DISK>,
                          (const void *)k_render_persistent<2, 1, DISK>, (const void *)k_render_persistent<3, 1, DISK>,
                          (const void *)k_render_persistent<4, 1, DISK>, (const void *)k_render_persistent<5, 1, DISK>};
-    return geo_fmt == 0 ? f0[img_fmt] : f1[img_fmt];
+    const void *f2[6] = {(const void *)k_render_persistent<0, 2, DISK>, (const void *)k_render_persistent<1, 2, DISK>,
+                         (const void *)k_render_persistent<2, 2, DISK>, (const void *)k_render_persistent<3, 2, DISK>,
+                         (const void *)k_render_persistent<4, 2, DISK>, (const void *)k_render_persistent<5, 2, DISK>};
+    return geo_fmt == 0 ? f0[img_fmt] : geo_fmt == 1 ? f1[img_fmt] : f2[img_fmt];
 }
 
 hipError_t persistent_occupancy(int img_fmt, int geo_fmt, bool oval, int block, int *per_cu) {

@@ -107,6 +107,34 @@ LF_HD float4 load_cell<1>(const void *__restrict__ cells, uint32_t idx) {
     __half2 b = *reinterpret_cast<__half2 *>(&p.y);
     return make_float4(__low2float(a), __high2float(a), __low2float(b), __high2float(b));
 }
+// Per-view linear 16-bit codes: w = base + code * scale, with (base, scale)
+// in the 8 bytes that precede the view's cells (a load that does not depend
+// on the cell, so the compiler keeps it out of the walk's loop).
+template <>
+LF_HD float4 load_cell<2>(const void *__restrict__ cells, uint32_t idx) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(1))) char gchar;
+    typedef const __attribute__((address_space(1))) float2 gF2;
+    const float2 q = *(gF2 *)((gchar *)cells - sizeof(float2));
+#else
+    const float2 q = *(reinterpret_cast<const float2 *>(cells) - 1);
+#endif
+    const uint2 p = at<uint2>(cells, idx);
+    return make_float4(fmaf((float)(p.x & 0xffffu), q.y, q.x), fmaf((float)(p.x >> 16), q.y, q.x),
+                       fmaf((float)(p.y & 0xffffu), q.y, q.x), fmaf((float)(p.y >> 16), q.y, q.x));
+}
+
+// Bytes per mesh cell and bytes of the header before each view's cells.
+template <int GEO>
+LF_HD constexpr int geo_cell_bytes() { return GEO == 0 ? 16 : 8; }
+template <int GEO>
+LF_HD constexpr int geo_head_bytes() { return GEO == 2 ? 8 : 0; }
+// View v's cells in a light field of views with `per` cells each.
+template <int GEO>
+LF_HD const void *geo_view(const void *cells, int64_t v, int64_t per) {
+    return static_cast<const char *>(cells) + v * (geo_head_bytes<GEO>() + per * geo_cell_bytes<GEO>()) +
+           geo_head_bytes<GEO>();
+}
 
 // ---------------------------------------------------------------------------------------------
 // per-ray pieces

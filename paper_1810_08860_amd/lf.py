@@ -15,12 +15,12 @@ LIB_PATH = os.environ.get("LF_LIB") or os.path.join(_HERE, "liblf.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
 LF_IMG_RGBA8, LF_IMG_RGBA16F, LF_IMG_RGBA32F, LF_IMG_YUV420, LF_IMG_YUV420_RGTC, LF_IMG_PAGED_RGBA8 = 0, 1, 2, 3, 4, 5
-LF_GEO_F32, LF_GEO_F16 = 0, 1
+LF_GEO_F32, LF_GEO_F16, LF_GEO_U16 = 0, 1, 2
 LF_SRC_DEVICE = 1
 
 IMG_FORMATS = {"rgba8": LF_IMG_RGBA8, "rgba16f": LF_IMG_RGBA16F, "rgba32f": LF_IMG_RGBA32F, "yuv420": LF_IMG_YUV420,
                "yuv420_rgtc": LF_IMG_YUV420_RGTC, "paged_rgba8": LF_IMG_PAGED_RGBA8}
-GEO_FORMATS = {"f32": LF_GEO_F32, "f16": LF_GEO_F16}
+GEO_FORMATS = {"f32": LF_GEO_F32, "f16": LF_GEO_F16, "u16": LF_GEO_U16}
 
 
 class lf_views_desc(ctypes.Structure):

@@ -55,6 +55,7 @@ def _desc(**kw):
     ("img_fmt", 5, "multiples of 64"),  # paged images: 64 x 64-texel tiles
     ("img_fmt", 4, "multiples of 8"),  # RGTC blocks of 4 x 4 chroma samples
     ("geo_fmt", 5, "geo_fmt"),
+    ("geo_fmt", 3, "geo_fmt"),
     ("flags", 8, "flags"),
     ("rgba8", None, "NULL"),
 ])

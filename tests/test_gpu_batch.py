@@ -67,6 +67,16 @@ def test_batch_matches_per_eye_render_for_every_tune(tiny, ctx16):
         assert torch.equal(got, ref), tune
 
 
+def test_batch_matches_per_eye_render_u16_geometry(tiny):
+    """The same with 16-bit inverse-depth codes (per-view dequantisation
+    constants ahead of each view's cells)."""
+    import torch
+    ctx = gpu_context(tiny.views, "rgba8", "u16")
+    eyes, res = _batch_eyes(6, 4, SIZES)
+    assert torch.equal(_batch(ctx, eyes, 90.0, res), _per_eye(ctx, eyes, 90.0, res))
+    ctx.close()
+
+
 def test_graph_replays_follow_new_poses(tiny, ctx16):
     """The captured graph is reused for a batch of the same shape; each call
     uploads new poses, with unrelated device work between replays."""

@@ -41,10 +41,14 @@ def test_full_size_fp32_sampled_parity(full, full_oracle):
     ctx.close()
 
 
-@pytest.mark.parametrize("img,geo", [("rgba16f", "f16"), ("rgba8", "f16"), ("rgba8", "f32")])
-def test_full_size_compact_storage_error(full, full_oracle, img, geo):
+@pytest.mark.parametrize("img,geo,tol", [("rgba16f", "f16", 2.0 / 255), ("rgba8", "f16", 2.0 / 255),
+                                         ("rgba8", "f32", 2.0 / 255), ("rgba16f", "u16", 2.0 / 255),
+                                         ("rgba8", "u16", 1e-3)])
+def test_full_size_compact_storage_error(full, full_oracle, img, geo, tol):
     """Compact storage against the FP64 oracle: max abs error <= 2/255 on
-    stable pixels (reported with the all-pixel maximum and PSNR)."""
+    stable pixels (reported with the all-pixel maximum and PSNR); RGBA8
+    images with 16-bit inverse-depth codes within 1e-3 (the bound of
+    test_storage_formats)."""
     from paper_1810_08860_amd import lf
     ctx = gpu_context(full.views, img, geo)
     errs, sq = [], []
@@ -64,5 +68,5 @@ def test_full_size_compact_storage_error(full, full_oracle, img, geo):
     psnr = 10 * np.log10(1.0 / max(np.mean(sq), 1e-30))
     print(f"{img}/{geo}: max err stable {stable_max:.4g} (2/255 = {2 / 255:.4g}), "
           f"all {max(x[1] for x in errs):.4g}, PSNR {psnr:.1f} dB, unstable {[round(x[2] * 100, 3) for x in errs]} %")
-    assert stable_max <= 2.0 / 255
+    assert stable_max <= tol
     ctx.close()

@@ -30,6 +30,7 @@ def _lib():
                                ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_float,
                                ctypes.c_float, ctypes.c_void_p]
     L.lfh_half_up.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    L.lfh_load_cell.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
     return L
 
 
@@ -209,3 +210,27 @@ def test_half_up_bits_rounds_up_to_the_next_half():
     exact = np.float16(x).astype(np.float32) == x
     assert (h[exact] == x[exact]).all()
     assert np.isinf(h[-2:]).all()
+
+
+def test_sixteen_bit_cell_codes_decode_to_base_plus_code_times_scale():
+    """LF_GEO_U16 layout: a view's (base, scale) as two floats, then per cell
+    four little-endian 16-bit codes in the order (w00, w10, w01, w11); a
+    corner decodes to base + code * scale (checked against numpy in FP64, up
+    to FP32 rounding of one multiply-add)."""
+    L = _lib()
+    rng = np.random.default_rng(9)
+    base, scale = np.float32(0.2137), np.float32(6.5 / 65535)
+    codes = rng.integers(0, 65536, (37, 4)).astype(np.uint16)
+    codes[0] = [0, 65535, 1, 32768]
+    buf = np.concatenate([np.array([base, scale], np.float32).view(np.uint8), codes.reshape(-1).view(np.uint8)])
+    out = np.zeros(4, np.float32)
+    for idx in range(len(codes)):
+        L.lfh_load_cell(2, buf.ctypes.data + 8, idx, out.ctypes.data)
+        want = float(base) + codes[idx].astype(np.float64) * float(scale)
+        assert np.allclose(out, want, rtol=2e-7, atol=0), (idx, out, want)
+    # the FP16 and FP32 layouts of the same cells
+    w = rng.uniform(0.1, 6.0, (5, 4)).astype(np.float32)
+    for fmt, arr in ((0, w), (1, w.astype(np.float16))):
+        for idx in range(5):
+            L.lfh_load_cell(fmt, arr.ctypes.data, idx, out.ctypes.data)
+            assert (out == arr[idx].astype(np.float32)).all()
