@@ -107,33 +107,40 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, i
             }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                acc[rr][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[rr][nb], 0, 0, 0);
+                acc[rr][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bv[nb], av, acc[rr][nb], 0, 0, 0);
         }
     }
 
-    // D[m][j]: m = 4 g + v (pixel along the row), j = i (output channel in the block)
+    // D[m][j] with the weights as the A operand: m = 4 g + v (output channel
+    // in the block), j = i (pixel along the row), so each lane holds four
+    // consecutive channels of one pixel and stores them at once
+    const int xx = x0 + i;
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
         const int yy = y0 + 2 * wave + rr;
-        if (yy >= H) continue;
+        if (yy >= H || xx >= W) continue;
+        const int64_t p = ((int64_t)n * H + yy) * W + xx;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int c = 16 * nb + i;
+            const int c = 16 * nb + 4 * g;  // channels c .. c + 3
             if (c >= COUT_ST) continue;
-            const float bi = (EPI == EPI_MASK_BF16) ? 0.0f : bias[c];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int xx = x0 + 4 * g + v;
-                if (xx >= W) continue;
-                const int64_t o = (((int64_t)n * H + yy) * W + xx) * COUT_ST + c;
-                float val = acc[rr][nb][v] + bi;
-                if (EPI == EPI_RELU_BF16) {
-                    reinterpret_cast<uint16_t *>(out)[o] = f2bf(fmaxf(val, 0.0f));
-                } else if (EPI == EPI_F32) {
-                    reinterpret_cast<float *>(out)[o] = val;
-                } else {
-                    reinterpret_cast<uint16_t *>(out)[o] = f2bf(bf2f(mask[o]) > 0.0f ? val : 0.0f);
-                }
+            const floatx4 a = acc[rr][nb];
+            if (EPI == EPI_RELU_BF16) {
+                const float4 bi = *reinterpret_cast<const float4 *>(&bias[c]);
+                *reinterpret_cast<uint2 *>(&reinterpret_cast<uint16_t *>(out)[p * COUT_ST + c]) =
+                    make_uint2(pack_bf16x2(fmaxf(a[0] + bi.x, 0.0f), fmaxf(a[1] + bi.y, 0.0f)),
+                               pack_bf16x2(fmaxf(a[2] + bi.z, 0.0f), fmaxf(a[3] + bi.w, 0.0f)));
+            } else if (EPI == EPI_F32) {
+                const float4 bi = *reinterpret_cast<const float4 *>(&bias[c]);
+                *reinterpret_cast<float4 *>(&reinterpret_cast<float *>(out)[p * COUT_ST + c]) =
+                    make_float4(a[0] + bi.x, a[1] + bi.y, a[2] + bi.z, a[3] + bi.w);
+            } else {
+                const uint2 mk = *reinterpret_cast<const uint2 *>(&mask[p * COUT_ST + c]);
+                const float m0 = bf2f((uint16_t)mk.x), m1 = bf2f((uint16_t)(mk.x >> 16));
+                const float m2 = bf2f((uint16_t)mk.y), m3 = bf2f((uint16_t)(mk.y >> 16));
+                *reinterpret_cast<uint2 *>(&reinterpret_cast<uint16_t *>(out)[p * COUT_ST + c]) =
+                    make_uint2(pack_bf16x2(m0 > 0.0f ? a[0] : 0.0f, m1 > 0.0f ? a[1] : 0.0f),
+                               pack_bf16x2(m2 > 0.0f ? a[2] : 0.0f, m3 > 0.0f ? a[3] : 0.0f));
             }
         }
     }
