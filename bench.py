@@ -452,6 +452,21 @@ def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     tflops = CORR_FLOP_PER_PX * 2 * EYE_W * EYE_H / (ms * 1e-3) / 1e12
+    # one training step (forward, loss, backward, Adam) on a fixed batch of
+    # crops resident on the device (the training loop above also copies its
+    # random crops from the host side each step)
+    cr = [train_frames[k % len(train_frames)] for k in range(batch)]
+    c_rgb, c_ws, c_cnt, c_ref = (torch.stack([getattr(f, n)[:crop, :crop] for f in cr]).contiguous()
+                                 for n in ("rgb", "wsum", "count", "ref"))
+    for _ in range(3):
+        lf.lf_corrector_train_step(corr, c_rgb, c_ws, c_cnt, c_ref, batch, crop, crop, 0.0, want_loss=False)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(50):
+        lf.lf_corrector_train_step(corr, c_rgb, c_ws, c_cnt, c_ref, batch, crop, crop, 0.0, want_loss=False)
+    b.record()
+    torch.cuda.synchronize()
+    step_ms = a.elapsed_time(b) / 50
     corr.close()
     return {
         "training_crops": steps * batch,
@@ -466,6 +481,8 @@ def corrector_leg(lf, torch, ctx_rt, ctx_ref, steps=1250, batch=16, crop=96):
                            "fallback_frac": ev_scene["fallback_frac"]},
         "pair_generation_s": t_pairs,
         "train_s": t_train,
+        "train_step_ms": step_ms,
+        "train_step": f"{batch} resident crops of {crop} x {crop}, mean of 50 steps (HIP events)",
         "loss_first_last": [log[0][1], log[-1][1]],
         "psnr_plain_db": ev["psnr_plain"],
         "psnr_corrected_db": ev["psnr_corrected"],
