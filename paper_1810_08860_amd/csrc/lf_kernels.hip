@@ -612,51 +612,74 @@ __device__ __forceinline__ void cull_super(const EyeParam &E, int local, int til
     const bool sover = scount > kSuperCap;
     const int ns = sover ? ne : scount;
 
-    // phase 2: each wavefront tests the survivors against its tiles
-    for (int t = wave; t < kSuper * kSuper; t += 4) {
+    // phase 2: each wavefront tests the survivors against its tiles; with at
+    // most 32 survivors a wavefront takes two tiles at once, one per half
+    // (lanes 32 h + s test survivor s against tile t0 + h), and each half's
+    // list fills its own half of the wave's list space
+    const bool pack = !sover && ns <= kListCap / 2;
+    const int per = pack ? 2 : 1;
+    for (int t0 = wave * per; t0 < kSuper * kSuper; t0 += 4 * per) {
+        const int h = pack ? lane >> 5 : 0;
+        const int sl = pack ? lane & 31 : lane;
+        const uint64_t half = pack ? (h ? 0xffffffff00000000ull : 0x00000000ffffffffull) : ~0ull;
+        const int t = t0 + h;
         const int tx = tx0 + t % kSuper, ty = ty0 + t / kSuper;
         const bool active = tx < tx1 && ty < ty1;
+        uint32_t *lst = &sm.tlst[wave][pack ? (kListCap / 2) * h : 0];
+        int4 *box = &sm.tbox[wave][pack ? (kListCap / 2) * h : 0];
+        const int cap = pack ? kListCap / 2 : kListCap;
         int count = 0;
-        if (active) {
+        {
             const int x0 = tx * tile_w, x1 = min(x0 + tile_w, E.W);
             const int y0 = ty * tile_h, y1 = min(y0 + tile_h, E.H);
             float X0 = x0 * sxp - E.tx, X1 = x1 * sxp - E.tx;
             float Y0 = E.ty - y0 * syp, Y1 = E.ty - y1 * syp;
-            const bool any = E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1);
-            for (int b = 0; any && b < ns; b += 64) {
-                const int s = b + lane;
-                const int v = s < ns ? (int)(sover ? elist[s] : sm.slist[s]) : -1;
+            const bool any = active && (E.src_view < 0 || prefilter_rect(E, g, pblk, X0, X1, Y0, Y1));
+            for (int b = 0; b < ns; b += pack ? 32 : 64) {
+                const int s = b + sl;
+                const int v = any && s < ns ? (int)(sover ? elist[s] : sm.slist[s]) : -1;
                 const EyeView &vr = eve[v >= 0 ? v : 0];
                 const TileCorners C = tile_corners(vr, X0, X1, Y0, Y1);
                 const bool keep = v >= 0 && tile_overlaps_disk(vr, C, X0, X1, Y0, Y1);
-                const uint64_t mask = __ballot(keep);
+                const uint64_t mask = __ballot(keep) & half;
                 if (keep) {
                     const int slot = count + __popcll(mask & below);
-                    if (slot < kListCap) {
+                    if (slot < cap) {
                         int4 bx = make_int4(-1, -1, -1, -1);
                         if (!tile_cell_box(vr, C, g.M, g.sM, g.cM, bx.x, bx.y, bx.z, bx.w))
                             bx.x = -1;
-                        sm.tlst[wave][slot] = (uint32_t)v;
-                        sm.tbox[wave][slot] = bx;
+                        lst[slot] = (uint32_t)v;
+                        box[slot] = bx;
                     }
                 }
                 count += __popcll(mask);
             }
         }
-        __syncthreads();
-        if (active) {
-            const int tile = E.tile_off + ty * E.tiles_x + tx;
-            const int m = min(count, kListCap);
+        // the lists are this wave's own: other lanes' LDS writes are visible
+        // once they complete, no other wave takes part
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        for (int hh = 0; hh < per; ++hh) {
+            // tile t0 + hh: its count from a lane of its half
+            const int th = t0 + hh;
+            const int txh = tx0 + th % kSuper, tyh = ty0 + th / kSuper;
+            if (!(txh < tx1 && tyh < ty1)) continue;
+            const int ch = __builtin_amdgcn_readlane(count, 32 * hh);
+            uint32_t *lh = &sm.tlst[wave][pack ? (kListCap / 2) * hh : 0];
+            const int tile = E.tile_off + tyh * E.tiles_x + txh;
+            const int m = min(ch, kListCap);
             // each listed view's start bound: the largest cell bound in its box
             // (lists longer than kListCap are never read: those tiles scan every view)
-            if (count <= kListCap) {
-                list_bounds(g, sm.tlst[wave], sm.tbox[wave], m, lane);
+            if (ch <= kListCap) {
+                list_bounds(g, lh, &sm.tbox[wave][pack ? (kListCap / 2) * hh : 0], m, lane);
                 __threadfence_block();  // the entries written by other lanes are visible below
             }
-            for (int q = lane; q < m; q += 64) tile_list[(int64_t)tile * kListCap + q] = sm.tlst[wave][q];
-            if (lane == 0) tile_count[tile] = count;
+            for (int q = lane; q < m; q += 64) tile_list[(int64_t)tile * kListCap + q] = lh[q];
+            if (lane == 0) tile_count[tile] = ch;
         }
-        __syncthreads();
+        // every lane has read the lists before the wave's next pass rewrites them
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
