@@ -18,10 +18,11 @@ extern "C" {
 // geo_fmt 0 = FP32 cells, 1 = FP16 cells. walk 0: the two-level march over
 // the inverse-depth blocks; walk 1: the single walk from the start bound that
 // the culling gives a listed view (the largest per-cell bound over the cell
-// box of the ray, as a one-ray tile). Returns 0.
+// box of the ray, as a one-ray tile). Returns 0, or 1 for another geo_fmt.
 static int trace(int32_t n, int32_t M, const float *z, const double *centres, const double *rot, double src_fov_deg,
                  double R, int32_t geo_fmt, int32_t walk, int64_t n_rays, const double *o, const double *e,
                  int32_t *cand, int32_t *hit, float *Xs, float *Ys, int32_t *cells_visited) {
+    if (geo_fmt != 0 && geo_fmt != 1) return 1;  // the trace builds FP32 or FP16 cells only
     const int Mc = M - 1, NB = num_blocks(M);
     const size_t per = (size_t)Mc * Mc;
     std::vector<float4> c32(geo_fmt == 0 ? per * n : 0);

@@ -48,9 +48,11 @@ def _trace(V, o, e, geo_fmt=0, R=None, top=False):
     r = np.ascontiguousarray(V.rot.reshape(-1, 9))
     o = np.ascontiguousarray(o, np.float64)
     e = np.ascontiguousarray(e, np.float64)
-    (L.lfh_trace_top if top else L.lfh_trace)(n, M, z.ctypes.data, c.ctypes.data, r.ctypes.data, V.src_fov_deg,
-                V.disk_radius if R is None else R, geo_fmt, nr, o.ctypes.data, e.ctypes.data, cand.ctypes.data,
-                hit.ctypes.data, Xs.ctypes.data, Ys.ctypes.data, cells.ctypes.data)
+    rc = (L.lfh_trace_top if top else L.lfh_trace)(n, M, z.ctypes.data, c.ctypes.data, r.ctypes.data,
+                                                    V.src_fov_deg, V.disk_radius if R is None else R, geo_fmt, nr,
+                                                    o.ctypes.data, e.ctypes.data, cand.ctypes.data, hit.ctypes.data,
+                                                    Xs.ctypes.data, Ys.ctypes.data, cells.ctypes.data)
+    assert rc == 0, rc
     return cand, hit, Xs, Ys, cells
 
 
