@@ -421,7 +421,8 @@ constexpr int FPS = 40;                                  // hidden pixel stride:
 // ReLU of two packed BF16 values: a BF16 value is negative exactly when its
 // bits read as a negative 16-bit integer, so one packed integer maximum with
 // zero does it (and rounding to BF16 keeps the sign, so this equals rounding
-// the ReLU of the FP32 values).
+// the ReLU of the FP32 values; a NaN with its sign bit set becomes 0 and
+// one without stays NaN, where fmaxf gives 0 for both).
 __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t p) {
     typedef short s16x2 __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2){0, 0}));
