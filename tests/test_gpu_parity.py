@@ -46,6 +46,27 @@ def test_storage_formats(tiny, tiny_oracle, img, geo, tol):
     ctx.close()
 
 
+def test_u16_codes_of_a_flat_view_decode_exactly(tiny):
+    """A view whose vertices all share one depth has a zero code step: every
+    code is 0 and decodes to the view's base, its FP32 inverse depth exactly,
+    so with such meshes the 16-bit form renders the FP32 form's image bit for
+    bit (one depth per view, different across views)."""
+    import dataclasses
+    V = tiny.views
+    z = np.repeat(np.linspace(1.8, 4.5, V.n, dtype=np.float32)[:, None, None], V.mesh_m, 1)
+    z = np.ascontiguousarray(np.repeat(z, V.mesh_m, 2))
+    flat = dataclasses.replace(V, zdepth=z)
+    c32, c16 = gpu_context(flat, "rgba8", "f32"), gpu_context(flat, "rgba8", "u16")
+    p, R = tiny.head_pos[0], tiny.head_rot[0]
+    a = gpu_render(c32, [(p, R)], 90.0, [(128, 96)])[0]
+    b = gpu_render(c16, [(p, R)], 90.0, [(128, 96)])[0]
+    assert (a[2] > 0).mean() > 0.5  # most pixels see the flat meshes
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    c32.close()
+    c16.close()
+
+
 def test_ragged_sizes_and_several_eyes(tiny, tiny_oracle, ctx32):
     """Eyes of ragged sizes (partial tiles on both axes) in one call."""
     p, R = tiny.head_pos[0], tiny.head_rot[0]
