@@ -709,15 +709,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 w4[s][0] = *reinterpret_cast<const bf16x8 *>(&wbuf[wz4 + L.layer[3].wf_off + i * L.layer[3].kf + 32 * s + 8 * g]);
             fused_layer<FT, false, 9, 1, true, true>(s_a, nullptr, s_res, w4, s_bias[3], interior, x0, y0, H, W);
         }
-        __syncthreads();
-        // finish: out = render + residual, or the render where max |residual| > thresh
+        // finish: out = render + residual, or the render where max |residual| > thresh.
+        // Layer 4's block b is tile row b, computed by wave b mod 4: each wave
+        // finishes its own rows (w, w + 4, w + 8, w + 12), so only its own LDS
+        // writes need to be complete
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
         {
-            const int xx = x0 + tid % FT, yy = y0 + tid / FT;
+            const int px = (((tid >> 6) + 4 * ((tid & 63) >> 4)) << 4) + (tid & 15);
+            const int xx = x0 + (px & 15), yy = y0 + (px >> 4);
             if (xx < W && yy < H) {
                 const int64_t p = img + (int64_t)yy * W + xx;
-                const float r0 = s_res[tid * 4], r1 = s_res[tid * 4 + 1], r2 = s_res[tid * 4 + 2];
+                const float r0 = s_res[px * 4], r1 = s_res[px * 4 + 1], r2 = s_res[px * 4 + 2];
                 const bool f = fmaxf(fabsf(r0), fmaxf(fabsf(r1), fabsf(r2))) > thresh;
-                const float c0 = s_rgb[tid * 3], c1 = s_rgb[tid * 3 + 1], c2 = s_rgb[tid * 3 + 2];
+                const float c0 = s_rgb[px * 3], c1 = s_rgb[px * 3 + 1], c2 = s_rgb[px * 3 + 2];
                 out[3 * p] = f ? c0 : c0 + r0;
                 out[3 * p + 1] = f ? c1 : c1 + r1;
                 out[3 * p + 2] = f ? c2 : c2 + r2;
