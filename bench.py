@@ -324,12 +324,19 @@ def time_batched(lf, torch, ctx, w, steps, warmup, per_batch, profile=False):
     from the end of the list, so no timed launch repeats a warm-up pose. Each
     launch is bracketed by HIP events on the render stream (p50 / p99 per
     launch); the value is the pixels of all timed launches over the wall
-    time of the timed region."""
+    time of the timed region. Where `steps` frames and the warm-up do not fit
+    in the pose list together, the timed frames are cut to the poses the
+    warm-up leaves (every pose at most once)."""
     P = len(w.head_pos)
-    nb = max(MIN_LAUNCHES, -(-steps // per_batch))
     nw = max(1, -(-warmup // per_batch))
+    nb = max(MIN_LAUNCHES, -(-steps // per_batch))
     if (nb + nw) * per_batch > P:
-        raise SystemExit(f"{nb + nw} launches of {per_batch} poses need more than the {P} poses")
+        fit = P // per_batch - nw
+        if fit < MIN_LAUNCHES:
+            raise SystemExit(f"{MIN_LAUNCHES + nw} launches of {per_batch} poses need more than the {P} poses")
+        print(f"[bench] {steps} frames + warm-up exceed the {P} poses: timing {fit * per_batch} frames",
+              file=sys.stderr, flush=True)
+        nb = fit
     res = np.array([[EYE_W, EYE_H]] * (2 * per_batch), np.int32)
     timed = [batch_poses(w, b * per_batch, per_batch) for b in range(nb)]
     warm = [batch_poses(w, P - (k + 1) * per_batch, per_batch) for k in range(nw)]
