@@ -186,6 +186,15 @@ LF_HD float sat01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 constexpr float kTolW = 4e-6f;
 constexpr float kTolD = 1e-5f;
 
+// x clamped into [lo, hi] (x not NaN, lo <= hi)
+LF_HD float clamp_range(float x, float lo, float hi) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+#else
+    return fminf(fmaxf(x, lo), hi);
+#endif
+}
+
 // Largest root of (mesh inverse depth - w) on one cell's piece of the line,
 // the part with w in [lo, hi]. In the cell's local coordinates the line is
 // (fx, fy) = (px + bx w, py + by w), with (px, py) its point at w = 0 and
@@ -203,7 +212,9 @@ LF_HD bool cell_root(const float4 &c, float px, float py, float bx, float by, fl
     const float wB = fmaf(py, b2, fmaf(px, b1, c.x)) * fast_rcp(fmaf(-by, b2, fmaf(-bx, b1, 1.0f)));
     const bool okA = wA <= hi && wA >= lo && fmaf(dbb, wA, d0) >= -kTolD;
     const bool okB = wB <= hi && wB >= lo && fmaf(dbb, wB, d0) <= kTolD;
-    w = fmaxf(okA ? wA : -INFINITY, okB ? wB : -INFINITY);
+    // the larger accepted root (accepted roots are never NaN)
+    const float tA = okA ? wA : -INFINITY;
+    w = okB && wB > tA ? wB : tA;
     return okA || okB;
 }
 
@@ -222,11 +233,13 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
     const float dwx = -fabsf(ibx), dwy = -fabsf(iby);
     const float dbb = bx - by;
     float w0 = ws;
-    int j = min(max((int)floorf(fmaf(w0, bx, ax)), j0), j1);
-    int k = min(max((int)floorf(fmaf(w0, by, ay)), k0), k1);
+    // the first cell, clamped into the box as a float (exact: whole numbers)
+    const float jf = clamp_range(floorf(fmaf(w0, bx, ax)), (float)j0, (float)j1);
+    const float kf = clamp_range(floorf(fmaf(w0, by, ay)), (float)k0, (float)k1);
+    int j = (int)jf, k = (int)kf;
     // exit edge in local coordinates: 0 when the coordinate falls as w does, else 1
-    float wxe = ((bx > 0.0f ? 0.0f : 1.0f) - (ax - (float)j)) * ibx;
-    float wye = ((by > 0.0f ? 0.0f : 1.0f) - (ay - (float)k)) * iby;
+    float wxe = ((bx > 0.0f ? 0.0f : 1.0f) - (ax - jf)) * ibx;
+    float wye = ((by > 0.0f ? 0.0f : 1.0f) - (ay - kf)) * iby;
     bool found = false, more = true;
     for (int it = 0; it < max_steps && more; ++it) {
         const bool xs = wxe >= wye, ys = wye >= wxe;  // exit edge(s): both at a corner
@@ -236,11 +249,18 @@ LF_HD bool walk_cells(const void *__restrict__ cells, int Mc, float ax, float bx
         const float4 c = load_cell<GEO>(cells, mul24(k, Mc) + j);
         ++n_cells;
         found = cell_root(c, ax - (float)j, ay - (float)k, bx, by, dbb, w1 - tol, w0 + tol, w_hit);
+#if defined(__HIP_DEVICE_COMPILE__)
+        // the root is chosen inside the step: left to itself the compiler
+        // defers the choice past the loop and keeps per-step lane masks
+        // for it in scalar registers instead (more instructions per step)
+        asm volatile("" : "+v"(w_hit));
+#endif
         j += xs ? sx : 0;
         wxe += xs ? dwx : 0.0f;
         k += ys ? sy : 0;
         wye += ys ? dwy : 0.0f;
-        more = !found && !last && j >= j0 && j <= j1 && k >= k0 && k <= k1;
+        // callers pass non-empty boxes (j0 <= j1, k0 <= k1): one unsigned compare per axis
+        more = !found && !last && (unsigned)(j - j0) <= (unsigned)(j1 - j0) && (unsigned)(k - k0) <= (unsigned)(k1 - k0);
         w0 = w1;
     }
     return found;
@@ -400,7 +420,7 @@ LF_HD bool march_top(const void *__restrict__ cells, int M, float sM, float cM, 
                      float Vx, float Vy, float Dx, float Dy, float &w_hit, int &n_cells) {
     GridLine L;
     if (!grid_line(M, sM, cM, Vx, Vy, Dx, Dy, wlo, whi, L)) return false;
-    const float ws = fminf(whi, wtop);
+    const float ws = whi < wtop ? whi : wtop;  // neither is NaN here
     if (!(ws >= wlo)) return false;
     const int Mc = M - 1;
     // a segment crosses at most 2 Mc - 1 cells of the Mc x Mc grid
