@@ -86,6 +86,18 @@ LF_HD Rgb texel<2>(const void *__restrict__ img, uint32_t idx) {  // RGBA32F
     return {p.x, p.y, p.z};
 }
 
+// Address of texel idx of one view's image (RGBA8, RGBA16F or RGBA32F).
+template <int IMG>
+LF_HD const void *texel_row(const void *__restrict__ img, uint32_t idx) {
+    constexpr uint32_t bytes = IMG == 0 ? 4u : IMG == 1 ? 8u : 16u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(1))) char gchar;
+    return (const void *)((gchar *)img + idx * bytes);
+#else
+    return reinterpret_cast<const char *>(img) + idx * bytes;
+#endif
+}
+
 // scale from stored texel units to [0,1]
 template <int IMG>
 LF_HD float texel_scale() { return (IMG == 0 || IMG >= 3) ? (1.0f / 255.0f) : 1.0f; }
@@ -526,8 +538,11 @@ LF_HD Rgb bilinear(const void *__restrict__ img, int W, int H, float limx, float
     taps_next(px, W, limx, x0, fx);
     taps_next(py, H, limy, y0, fy);
     const uint32_t r0 = mul24(y0, W) + x0, r1 = r0 + W;
-    const Rgb a = texel<IMG>(img, r0), b = texel<IMG>(img, r0 + 1);
-    const Rgb c = texel<IMG>(img, r1), d = texel<IMG>(img, r1 + 1);
+    // the right-hand taps through a fixed byte offset from their row's first
+    // tap (an address offset, not an index: one 32-bit offset per row)
+    const void *p0 = texel_row<IMG>(img, r0), *p1 = texel_row<IMG>(img, r1);
+    const Rgb a = texel<IMG>(p0, 0), b = texel<IMG>(p0, 1);
+    const Rgb c = texel<IMG>(p1, 0), d = texel<IMG>(p1, 1);
     // the four tap weights; FP16 taps then feed mixed-precision FMAs directly
     const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.0f - fx) - w01;
     return {fmaf(w11, d.r, fmaf(w01, c.r, fmaf(w10, b.r, fmaf(w00, a.r, 0.0f)))),
