@@ -188,6 +188,33 @@ def achievable_hbm(lf, torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def achievable_fma(lf, torch, waves_per_simd=7, iters=4096, reps=5):
+    """Achievable rate of wave-level FP32 FMA instructions: the library's FMA
+    yardstick (eight independent chains per lane) on seven workgroups of four
+    wavefronts per CU, the render kernel's occupancy, with all 64 lanes of a
+    wavefront live and with 16; median of `reps` timed launches. Rates are
+    per SIMD (four per CU) and per second; x 2 flops x live lanes gives FLOP/s."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = cus * waves_per_simd
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    res = {"waves_per_simd": waves_per_simd, "fma_per_lane": 8 * iters}
+    for active in (64, 16):
+        for _ in range(2):
+            lf.lf_fma_rate(out, blocks, iters, active)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            lf.lf_fma_rate(out, blocks, iters, active)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        per_simd = blocks * 4 * 8 * iters / (ms * 1e-3) / (4 * cus)
+        res[f"lanes{active}"] = {"ms": ms, "wave_fma_per_simd_per_s": per_simd,
+                                 "tflops": per_simd * 4 * cus * 2 * active / 1e12}
+    del out
+    return res
+
+
 def cpu_baseline(lf, torch, views, head_pos, head_rot, ctx_plain, seconds):
     """FP64 oracle on a bounded sample of the same workload (pixels of the
     first stereo frame, strided), on all host cores; also the largest
@@ -833,6 +860,12 @@ def main():
             roofline["traffic_gbs"] = traffic / (render_ms * 1e-3) / 1e9
             roofline["traffic_frac_of_achievable"] = roofline["traffic_gbs"] / hbm
         log(f"[bench] achievable HBM (lf_stream_copy): {hbm:.0f} GB/s")
+        fma = achievable_fma(lf, torch)
+        roofline["valu_fma_achievable"] = fma
+        log(f"[bench] achievable FP32 FMA (lf_fma_rate, 7 waves per SIMD): "
+            f"{fma['lanes64']['tflops']:.1f} TFLOP/s with 64 lanes live "
+            f"({fma['lanes64']['wave_fma_per_simd_per_s'] / 1e9:.3f} G wave-FMAs per SIMD per s), "
+            f"{fma['lanes16']['wave_fma_per_simd_per_s'] / 1e9:.3f} G with 16 lanes live")
 
     cpu = None
     if not args.no_cpu_baseline and ("rgba32f", "f32", "circle") in ctxs:

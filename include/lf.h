@@ -420,6 +420,20 @@ int lf_profile_read(lf_ctx *c, double out[6]);
  */
 int lf_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
 
+/*
+ * Vector FMA yardstick: `blocks` workgroups of 256 threads (four wavefronts);
+ * the first `active` lanes of every wavefront run `iters` steps of eight
+ * independent FP32 FMA chains (x = x * 0.999 + 0.001, chain k starting at
+ * lane + k), the other lanes skip them; every thread writes the sum of its
+ * eight values to out[block * 256 + thread] (DEVICE, blocks * 256 floats).
+ * Asynchronous on hip_stream. Timing it gives the achievable rate of
+ * wave-level FP32 FMA instructions with that many live lanes, which the
+ * render kernel's vector instruction rate is compared with (not part of the
+ * paper's method). Errors: LF_EINVAL for a NULL out, blocks < 1, iters < 1 or
+ * active outside [1, 64].
+ */
+int lf_fma_rate(float *out, int32_t blocks, int32_t iters, int32_t active, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Learned residual corrector (a post-process of the render; not in the paper,
  * whose learning-based methods are related work only, Sec. 2).

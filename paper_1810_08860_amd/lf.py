@@ -77,6 +77,7 @@ def lib():
         L.lf_cache_resident.argtypes = [vp, vp]
         L.lf_cache_page_misses.argtypes = [vp, vp]
         L.lf_stream_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
+        L.lf_fma_rate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
         L.lf_debug_candidates.argtypes = [vp, ctypes.POINTER(lf_eye), f64, i32, i32, i32, vp, vp, vp, vp]
         L.lf_query.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lf_render_stats.argtypes = [vp, ctypes.POINTER(lf_eye), i32, f64, vp, vp, vp]
@@ -485,6 +486,11 @@ def lf_stream_copy(src, dst, nbytes, stream=None):
     _check(lib().lf_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
 
 
+def lf_fma_rate(out, blocks, iters, active, stream=None):
+    """Independent FP32 FMA chains on `active` lanes per wavefront (vector-rate yardstick)."""
+    _check(lib().lf_fma_rate(_ptr(out), int(blocks), int(iters), int(active), _stream(stream)))
+
+
 def lf_last_error() -> str:
     return lib().lf_last_error().decode()
 
@@ -493,7 +499,7 @@ def lf_last_error() -> str:
 EXPORTS = ("lf_load_views", "lf_stereo_eyes", "lf_disk_extents", "lf_set_tune", "lf_render", "lf_render_noalloc",
            "lf_render_reference",
            "lf_prefilter", "lf_set_view_mask", "lf_two_level_mask", "lf_cache_config", "lf_cache_update",
-           "lf_cache_resident", "lf_cache_page_misses", "lf_stream_copy",
+           "lf_cache_resident", "lf_cache_page_misses", "lf_stream_copy", "lf_fma_rate",
            "lf_debug_candidates", "lf_query", "lf_render_stats", "lf_profile", "lf_profile_read",
            "lf_render_batch", "lf_autotune_batch", "lf_batch_frame_times", "lf_corrector_create",
            "lf_corrector_set_params", "lf_corrector_get_params", "lf_corrector_get_state", "lf_corrector_set_state",

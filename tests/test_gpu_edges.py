@@ -88,6 +88,36 @@ def test_stream_copy():
     assert L.lf_stream_copy(None, dst.data_ptr(), 64, None) == lf.LF_EINVAL
 
 
+@pytest.mark.parametrize("active", [64, 17, 16, 1])
+def test_fma_rate_yardstick(active):
+    """The vector-rate yardstick runs its FMA chains on exactly the first
+    `active` lanes of each wavefront (chain k of lane l starts at l + k and
+    steps x -> 0.999 x + 0.001 in FP32 FMAs); the other lanes keep their start
+    values. Bad arguments are rejected."""
+    import torch
+    from paper_1810_08860_amd import lf
+    blocks, iters = 3, 100
+    out = torch.full((blocks * 256,), -1.0, dtype=torch.float32, device="cuda")
+    lf.lf_fma_rate(out, blocks, iters, active)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(blocks, 4, 64)
+    lane = np.arange(64)
+    x = (lane[:, None] + np.arange(8)[None, :]).astype(np.float32)
+    y = x.copy()
+    a, b = np.float32(0.999), np.float32(0.001)
+    for _ in range(iters):  # one rounding per step: the FP64 product of two FP32 values is exact
+        y = (y.astype(np.float64) * np.float64(a) + np.float64(b)).astype(np.float32)
+    x = np.where((lane < active)[:, None], y, x)
+    want = ((x[:, 0] + x[:, 1]) + (x[:, 2] + x[:, 3])) + ((x[:, 4] + x[:, 5]) + (x[:, 6] + x[:, 7]))
+    for blk in got.reshape(-1, 64):
+        np.testing.assert_allclose(blk[:active], want[:active], rtol=1e-6)
+        assert np.array_equal(blk[active:], want[active:])  # untouched start values, exact
+    L = lf.lib()
+    assert L.lf_fma_rate(None, 1, 1, 64, None) == lf.LF_EINVAL
+    for bad in ((0, 1, 64), (1, 0, 64), (1, 1, 0), (1, 1, 65)):
+        assert L.lf_fma_rate(out.data_ptr(), *bad, None) == lf.LF_EINVAL
+
+
 def test_work_counters_match_oracle(tiny, tiny_oracle, ctx):
     """The work counters behind the bench's algorithmic flop count: pixels,
     candidates and samples are the oracle's own totals over a full frame (up
