@@ -5,6 +5,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -405,7 +406,8 @@ LF_HD uint32_t box_window_index(const int4 &b, int tx, int ty, int Mc) {
 struct GridLine {
     float ax, bx, ibx, ay, by, iby;
 };
-LF_HD float min_slope(float b) { return fabsf(b) >= 1e-20f ? b : copysignf(1e-20f, b); }
+// b with its magnitude raised to at least 1e-20 (b finite)
+LF_HD float min_slope(float b) { return copysignf(clamp_range(fabsf(b), 1e-20f, FLT_MAX), b); }
 LF_HD bool grid_line(int M, float sM, float cM, float Vx, float Vy, float Dx, float Dy, float &wlo, float &whi,
                      GridLine &L) {
     const float lim = (float)(M - 1);
