@@ -183,4 +183,26 @@ void lfh_load_cell(int32_t geo_fmt, const void *cells, uint32_t idx, float *out4
     out4[3] = q.w;
 }
 
+// The kernels' bilinear sample (clamp-to-edge, texel i's centre at i, result
+// in stored texel units) of a W x H image of format img_fmt (0 RGBA8, 1
+// RGBA16F, 2 RGBA32F) at (px, py); RGB into rgb3. Returns 0, or 1 for another
+// format or an image smaller than 2 x 2.
+int lfh_bilinear(int32_t img_fmt, const void *img, int32_t W, int32_t H, float px, float py, float *rgb3) {
+    if (W < 2 || H < 2) return 1;
+    const float limx = (float)(W - 1), limy = (float)(H - 1);
+    Rgb c;
+    if (img_fmt == 0)
+        c = bilinear<0>(img, W, H, limx, limy, px, py);
+    else if (img_fmt == 1)
+        c = bilinear<1>(img, W, H, limx, limy, px, py);
+    else if (img_fmt == 2)
+        c = bilinear<2>(img, W, H, limx, limy, px, py);
+    else
+        return 1;
+    rgb3[0] = c.r;
+    rgb3[1] = c.g;
+    rgb3[2] = c.b;
+    return 0;
+}
+
 }  // extern "C"

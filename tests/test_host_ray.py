@@ -31,6 +31,8 @@ def _lib():
                                ctypes.c_float, ctypes.c_void_p]
     L.lfh_half_up.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
     L.lfh_load_cell.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
+    L.lfh_bilinear.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_void_p]
     return L
 
 
@@ -236,3 +238,52 @@ def test_sixteen_bit_cell_codes_decode_to_base_plus_code_times_scale():
         for idx in range(5):
             L.lfh_load_cell(fmt, arr.ctypes.data, idx, out.ctypes.data)
             assert (out == arr[idx].astype(np.float32)).all()
+
+
+def _bilinear_definition(img, x, y):
+    """Clamp-to-edge bilinear of an (H, W, 3) FP64 image with texel (i, j)'s
+    centre at (x, y) = (i, j), written out from the definition."""
+    H, W = img.shape[:2]
+    x = min(max(x, 0.0), W - 1.0)
+    y = min(max(y, 0.0), H - 1.0)
+    x0, y0 = int(np.floor(x)), int(np.floor(y))
+    x1, y1 = min(x0 + 1, W - 1), min(y0 + 1, H - 1)
+    fx, fy = x - x0, y - y0
+    return ((1 - fx) * (1 - fy) * img[y0, x0] + fx * (1 - fy) * img[y0, x1] + (1 - fx) * fy * img[y1, x0]
+            + fx * fy * img[y1, x1])
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("W,H", [(7, 5), (2, 2), (64, 3)])
+def test_bilinear_taps_match_the_clamp_to_edge_definition(fmt, W, H):
+    """The kernels' bilinear sample (the right-hand taps addressed at a fixed
+    byte offset from their row's first tap) built for the host: RGBA8 (0..255),
+    RGBA16F and RGBA32F images, positions inside, on and past every edge,
+    against the definition in FP64; at whole texel positions the sample is the
+    texel itself, exactly (a tap one texel off fails there)."""
+    L = _lib()
+    rng = np.random.default_rng(101 + 7 * fmt + W)
+    if fmt == 0:
+        buf = rng.integers(0, 256, (H, W, 4), dtype=np.uint8)
+    elif fmt == 1:
+        buf = rng.random((H, W, 4)).astype(np.float16)
+    else:
+        buf = rng.random((H, W, 4)).astype(np.float32)
+    buf = np.ascontiguousarray(buf)
+    ref = buf[..., :3].astype(np.float64)
+    edge = lambda n: [-3.2, -1e-3, 0.0, 0.25, 0.5, n - 2.0, n - 1.5, n - 1.0 - 1e-3, n - 1.0, n - 0.9, n + 5.0]
+    xs = np.float32(edge(W) + list(rng.uniform(-2.0, W + 1.0, 12)))
+    ys = np.float32(edge(H) + list(rng.uniform(-2.0, H + 1.0, 12)))
+    out = np.zeros(3, np.float32)
+    tol = 1e-4 if fmt == 0 else 1e-6  # FP32 weights and sums of values up to 255 or 1
+    for x in xs:
+        for y in ys:
+            assert L.lfh_bilinear(fmt, buf.ctypes.data, W, H, float(x), float(y), out.ctypes.data) == 0
+            want = _bilinear_definition(ref, float(x), float(y))
+            assert np.abs(out - want).max() <= tol, (fmt, W, H, x, y, out, want)
+    for j in range(H):
+        for i in range(W):
+            assert L.lfh_bilinear(fmt, buf.ctypes.data, W, H, float(i), float(j), out.ctypes.data) == 0
+            assert np.array_equal(out, ref[j, i].astype(np.float32)), (fmt, i, j)
+    assert L.lfh_bilinear(3, buf.ctypes.data, W, H, 0.0, 0.0, out.ctypes.data) == 1
+    assert L.lfh_bilinear(fmt, buf.ctypes.data, 1, H, 0.0, 0.0, out.ctypes.data) == 1
