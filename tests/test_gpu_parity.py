@@ -67,6 +67,27 @@ def test_u16_codes_of_a_flat_view_decode_exactly(tiny):
     c16.close()
 
 
+def test_eye_next_to_a_source_camera_centre(tiny, tiny_oracle, ctx32):
+    """An eye 1 mm inside the capture sphere behind view k's centre, with view
+    k's frame and field of view: its rays cross disk k within millimetres of
+    the centre, so view k's lines through its mesh are nearly single points
+    (steep lines, huge cell-exit steps). The image matches the oracle, lists
+    included. The centre itself lies on disk k's plane, which the boundary
+    rejects."""
+    import torch
+    from paper_1810_08860_amd import lf
+    V = tiny.views
+    for k in (5, 33):
+        c = V.centres[k]
+        pos = c * (1.0 - 1e-3 / np.linalg.norm(c))
+        s = check_eye(tiny_oracle, ctx32, pos, V.rot[k], V.src_fov_deg, 96, 96)
+        print(f"eye 1 mm behind view {k}'s centre:", s)
+    out = torch.zeros(16 * 16 * 3, dtype=torch.float32, device="cuda")
+    with pytest.raises(lf.LFError) as ei:
+        lf.lf_render(ctx32, [(V.centres[5], V.rot[5])], V.src_fov_deg, (16, 16), out)
+    assert ei.value.code == lf.LF_EINVAL and "disk plane" in str(ei.value)
+
+
 def test_ragged_sizes_and_several_eyes(tiny, tiny_oracle, ctx32):
     """Eyes of ragged sizes (partial tiles on both axes) in one call."""
     p, R = tiny.head_pos[0], tiny.head_rot[0]
